@@ -1,0 +1,416 @@
+"""FP64 CPU oracle of the P3M force evaluation, leapfrog step and its adjoint.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the product path never does. It
+shares no code with the GPU library and imports nothing from it.
+
+Paper: Wyssling & Adelmann, arXiv 2103.02046. Each function cites the
+passage it follows. Where the paper is silent the readings are:
+
+  * placement: the mesh is centred on the bunch's bounding box each
+    evaluation and zoomed by s >= 1 so every assignment stencil fits
+    (h' = s h, r_c' = s r_c, a' = a / s);
+  * the mesh kernel is the erf part of the Ewald split sampled on the mesh,
+    with the Gaussian screening folded into the kernel rather than into the
+    assignment (Sec. 2.2 shows the two are the same convolution); no
+    deconvolution of the assignment function;
+  * the open boundary is realised by zero padding to a doubled mesh (the
+    aperiodic convolution of N nodes needs offsets up to N-1 only);
+  * the force is the variational one of eq. eom_p3m_coord: minus the weight
+    gradient against the mesh potential;
+  * leapfrog is kick-drift-kick with p = m v.
+
+The C part (p3m_oracle.c) holds the particle loops; FFTs are numpy's.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+from scipy.special import erf
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "p3m_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ENOMEM, EDOMAIN, ENONFINITE = 0, -1, -2, -5, -6
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: status {code}")
+        self.code = code
+
+
+def build(force=False):
+    """Compile the C part with gcc (plain -O2, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, dbl, i32 = ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        sig = {
+            "oracle_placement": (i32, [i64, P, P, P, i32, i32, P]),
+            "oracle_pp_brute": (None, [i64, P, P, dbl, dbl, dbl, P]),
+            "oracle_pp_cells": (i32, [i64, P, P, dbl, dbl, dbl, P]),
+            "oracle_pp_sample": (i32, [i64, P, P, dbl, dbl, dbl, i64, P, P]),
+            "oracle_pp_energy": (dbl, [i64, P, P, dbl, dbl, dbl]),
+            "oracle_deposit": (i32, [i64, P, P, P, P, P, i32, P]),
+            "oracle_green": (dbl, [i64, i64, i64, P, dbl]),
+            "oracle_conv_direct": (None, [P, P, dbl, P, P]),
+            "oracle_phi_at": (None, [P, P, dbl, P, i64, P, P]),
+            "oracle_stencil_nodes": (i32, [P, P, P, P, i32, P]),
+            "oracle_gather": (i32, [i64, P, P, P, P, P, i32, P, dbl, P]),
+            "oracle_pp_hvp": (None, [i64, P, P, dbl, dbl, dbl, P, P]),
+            "oracle_deposit_grad": (i32, [i64, P, P, P, P, P, i32, P, P]),
+            "oracle_gather_hvp": (i32, [i64, P, P, P, P, P, i32, P, P, P, dbl, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(code, what):
+    if code != OK:
+        raise OracleError(code, what)
+
+
+class Params:
+    """Run parameters of one P3M configuration (SI units)."""
+
+    def __init__(self, grid, h, r_cut, split, order, ke_q2, m=1.0, dt=0.0, zoom=True, qw=None):
+        self.grid = np.asarray(grid, dtype=np.int32)
+        self.h = np.asarray(h, dtype=np.float64)
+        self.r_cut = float(r_cut)
+        self.split = float(split)
+        self.order = int(order)
+        self.ke_q2 = float(ke_q2)
+        self.m = float(m)
+        self.dt = float(dt)
+        self.zoom = bool(zoom)
+        self.qw = None if qw is None else _f64(qw)
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.grid, wl.h, wl.r_cut, wl.split, wl.order, wl.ke_q2, wl.m, wl.dt, **kw)
+
+
+# ---- placement --------------------------------------------------------------
+
+def placement(x, prm):
+    """Mesh origin, zoom and zoomed spacing for positions x (reading of Sec. 2.4.2)."""
+    x = _f64(x)
+    out = np.zeros(8)
+    _check(lib().oracle_placement(len(x), _p(x), _p(prm.grid), _p(prm.h), prm.order,
+                                  int(prm.zoom), _p(out)), "placement")
+    s = out[3]
+    return {"x0": out[0:3].copy(), "s": s, "hp": out[4:7].copy(),
+            "rc": prm.r_cut * s, "a": prm.split / s}
+
+
+# ---- short range (PP) ---------------------------------------------------------
+
+def pp_brute(x, prm, rc, a):
+    """O(N^2) erfc pair force inside rc (Sec. 1 eq. summation_short; Sec. 2.2)."""
+    x = _f64(x)
+    f = np.zeros_like(x)
+    lib().oracle_pp_brute(len(x), _p(x), _p(prm.qw), rc, a, prm.ke_q2, _p(f))
+    return f
+
+
+def pp_cells(x, prm, rc, a):
+    """Same pair force through linked cells (exact equivalent of pp_brute)."""
+    x = _f64(x)
+    f = np.zeros_like(x)
+    _check(lib().oracle_pp_cells(len(x), _p(x), _p(prm.qw), rc, a, prm.ke_q2, _p(f)), "pp_cells")
+    return f
+
+
+def pp_sample(x, prm, rc, a, idx):
+    x = _f64(x)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    f = np.zeros((len(idx), 3))
+    _check(lib().oracle_pp_sample(len(x), _p(x), _p(prm.qw), rc, a, prm.ke_q2, len(idx),
+                                  _p(idx), _p(f)), "pp_sample")
+    return f
+
+
+def pp_energy(x, prm, rc, a):
+    x = _f64(x)
+    return lib().oracle_pp_energy(len(x), _p(x), _p(prm.qw), rc, a, prm.ke_q2)
+
+
+# ---- mesh (PM) --------------------------------------------------------------
+
+def deposit(x, prm, pl):
+    """Mesh charge Q[z, y, x] (Sec. 2.5 eq. eom_p3m_poiss_L; Sec. 2.4.2 B-splines)."""
+    x = _f64(x)
+    g = prm.grid
+    Q = np.zeros((g[2], g[1], g[0]))
+    _check(lib().oracle_deposit(len(x), _p(x), _p(prm.qw), _p(g), _p(pl["x0"]), _p(pl["hp"]),
+                                prm.order, _p(Q)), "deposit")
+    return Q
+
+
+def green_padded(grid, hp, a):
+    """erf(a r)/r sampled on the doubled mesh, offsets k in [-N, N-1] per axis
+    (stored at k mod 2N), value 2a/sqrt(pi) at r = 0 (Sec. 2.2 charge screening
+    with the free-space Green's function of Sec. 2.1, eq. free_gf)."""
+    axes = []
+    for d in range(3):
+        n = int(grid[d])
+        k = np.arange(2 * n)
+        k = np.where(k < n, k, k - 2 * n)
+        axes.append(k * hp[d])
+    rz, ry, rx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    r = np.sqrt(rx * rx + ry * ry + rz * rz)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        g = erf(a * r) / r
+    g[r == 0] = 2.0 * a / math.sqrt(math.pi)
+    return g
+
+
+def conv_fft(Q, grid, hp, a):
+    """phi = G (x) Q, aperiodic, by zero padding to 2N and numpy's FFT
+    (Sec. 3 eq. phi_L as a finite convolution; Hockney's doubling)."""
+    nz, ny, nx = Q.shape
+    Qp = np.zeros((2 * nz, 2 * ny, 2 * nx))
+    Qp[:nz, :ny, :nx] = Q
+    Gk = np.fft.rfftn(green_padded(grid, hp, a))
+    phi = np.fft.irfftn(np.fft.rfftn(Qp) * Gk, s=Qp.shape, axes=(0, 1, 2))
+    return np.ascontiguousarray(phi[:nz, :ny, :nx])
+
+
+def conv_direct(Q, grid, hp, a):
+    """phi by the plain O(M^2) aperiodic sum (tiny meshes only)."""
+    Q = _f64(Q)
+    phi = np.zeros_like(Q)
+    lib().oracle_conv_direct(_p(np.asarray(grid, np.int32)), _p(_f64(hp)), a, _p(Q), _p(phi))
+    return phi
+
+
+def phi_at(Q, grid, hp, a, nodes):
+    Q = _f64(Q)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros(len(nodes))
+    lib().oracle_phi_at(_p(np.asarray(grid, np.int32)), _p(_f64(hp)), a, _p(Q), len(nodes),
+                        _p(nodes), _p(out))
+    return out
+
+
+def stencil_nodes(xi, prm, pl):
+    nodes = np.zeros(27, dtype=np.int64)
+    k = lib().oracle_stencil_nodes(_p(_f64(xi)), _p(prm.grid), _p(pl["x0"]), _p(pl["hp"]),
+                                   prm.order, _p(nodes))
+    return nodes[:k]
+
+
+def gather(x, prm, pl, phi):
+    """Mesh force -k_e q^2 qw_i sum_m phi_m grad W_m(x_i) (Sec. 2.5 eq. eom_p3m_coord)."""
+    x = _f64(x)
+    phi = _f64(phi)
+    f = np.zeros_like(x)
+    _check(lib().oracle_gather(len(x), _p(x), _p(prm.qw), _p(prm.grid), _p(pl["x0"]),
+                               _p(pl["hp"]), prm.order, _p(phi), prm.ke_q2, _p(f)), "gather")
+    return f
+
+
+# ---- whole force evaluation and step ----------------------------------------
+
+def forces(x, prm, parts=False, brute=False, direct=False, pl=None):
+    """Total P3M force F = F_PP + F_PM at positions x (Sec. 2.5 eq. eom_p3m_coord)."""
+    if pl is None:
+        pl = placement(x, prm)
+    fpp = (pp_brute if brute else pp_cells)(x, prm, pl["rc"], pl["a"])
+    Q = deposit(x, prm, pl)
+    conv = conv_direct if direct else conv_fft
+    phi = conv(Q, prm.grid, pl["hp"], pl["a"])
+    fpm = gather(x, prm, pl, phi)
+    if parts:
+        return fpp + fpm, {"pp": fpp, "pm": fpm, "Q": Q, "phi": phi, "pl": pl}
+    return fpp + fpm
+
+
+def coulomb_brute(x, ke_q2, qw=None):
+    """Unsplit O(N^2) Coulomb force, the physics the split approximates (Sec. 1)."""
+    prm = Params((4, 4, 4), (1, 1, 1), np.inf, 0.0, 1, ke_q2, qw=qw)
+    return pp_brute(x, prm, np.inf, 0.0)
+
+
+def step(x, p, prm, nsteps, f=None):
+    """Kick-drift-kick leapfrog (Sec. 2.4.3 eq. leapfrog; Sec. 2.5 eq. eom_p3m_coord):
+    p += dt/2 F(x); x += dt p/m; p += dt/2 F(x)."""
+    x = _f64(x).copy()
+    p = _f64(p).copy()
+    if f is None:
+        f = forces(x, prm)
+    dt, m = prm.dt, prm.m
+    for _ in range(nsteps):
+        p += 0.5 * dt * f
+        x += dt * p / m
+        f = forces(x, prm)
+        p += 0.5 * dt * f
+    return x, p, f
+
+
+# ---- diagnostics ------------------------------------------------------------
+
+C_LIGHT = 299792458.0
+
+
+def emittance(x, p, m, axis):
+    """Normalised rms emittance sqrt(<dx^2><dp^2> - <dx dp>^2)/(m c), centred."""
+    dx = x[:, axis] - x[:, axis].mean()
+    dp = p[:, axis] - p[:, axis].mean()
+    val = (dx * dx).mean() * (dp * dp).mean() - (dx * dp).mean() ** 2
+    return math.sqrt(max(val, 0.0)) / (m * C_LIGHT)
+
+
+def diagnostics(x, p, prm, brute_pp=False):
+    pl = placement(x, prm)
+    Q = deposit(x, prm, pl)
+    phi = conv_fft(Q, prm.grid, pl["hp"], pl["a"])
+    if brute_pp:
+        upp = pp_energy(x, prm, pl["rc"], pl["a"])
+    else:
+        upp = float("nan")
+    qw = np.ones(len(x)) if prm.qw is None else prm.qw
+    return {
+        "momentum": p.sum(axis=0),
+        "kinetic": float((p * p).sum() / (2 * prm.m)),
+        "u_pp": upp,
+        "u_pm": float(0.5 * prm.ke_q2 * (Q * phi).sum()),
+        "mean": x.mean(axis=0),
+        "rms": x.std(axis=0),
+        "emit_x": emittance(x, p, prm.m, 0),
+        "emit_y": emittance(x, p, prm.m, 1),
+        "charge": float(qw.sum()),
+    }
+
+
+# ---- adjoint ----------------------------------------------------------------
+
+def hvp(x, v, prm, pl, brute=True):
+    """H v with H = dF/dx (symmetric, F = -grad U), placement frozen at pl.
+    PP part: sum_j K_ij (v_i - v_j); PM part: gather of psi = G (x) R plus the
+    second derivative of the weights against phi (derivatives of Sec. 2.5
+    eq. eom_p3m_coord)."""
+    x = _f64(x)
+    v = _f64(v)
+    out_pp = np.zeros_like(x)
+    lib().oracle_pp_hvp(len(x), _p(x), _p(prm.qw), pl["rc"], pl["a"], prm.ke_q2, _p(v), _p(out_pp))
+    g = prm.grid
+    Q = deposit(x, prm, pl)
+    phi = conv_fft(Q, g, pl["hp"], pl["a"])
+    R = np.zeros_like(Q)
+    _check(lib().oracle_deposit_grad(len(x), _p(x), _p(prm.qw), _p(g), _p(pl["x0"]), _p(pl["hp"]),
+                                     prm.order, _p(v), _p(R)), "deposit_grad")
+    psi = conv_fft(R, g, pl["hp"], pl["a"])
+    out_pm = np.zeros_like(x)
+    _check(lib().oracle_gather_hvp(len(x), _p(x), _p(prm.qw), _p(g), _p(pl["x0"]), _p(pl["hp"]),
+                                   prm.order, _p(phi), _p(psi), _p(v), prm.ke_q2, _p(out_pm)),
+           "gather_hvp")
+    return out_pp + out_pm
+
+
+def rollout(x, p, prm, nsteps, record=True):
+    """Forward KDK that also records every step's positions and placement."""
+    xs, pls = [_f64(x).copy()], [placement(x, prm)]
+    f = forces(xs[0], prm, pl=pls[0])
+    x = xs[0].copy()
+    p = _f64(p).copy()
+    for _ in range(nsteps):
+        p += 0.5 * prm.dt * f
+        x += prm.dt * p / prm.m
+        pl = placement(x, prm)
+        f = forces(x, prm, pl=pl)
+        p += 0.5 * prm.dt * f
+        xs.append(x.copy())
+        pls.append(pl)
+    return x, p, xs, pls
+
+
+def step_backward(x_n, x_np1, pl_n, pl_np1, xbar, pbar, prm):
+    """Reverse of one KDK step (placements frozen at the recorded values):
+    with H = dF/dx symmetric,
+      pbar <- pbar_{n+1};  xbar <- xbar_{n+1} + dt/2 H(x_{n+1}) pbar;
+      pbar <- pbar + dt/m xbar;  xbar_n <- xbar + dt/2 H(x_n) pbar."""
+    dt, m = prm.dt, prm.m
+    xb = xbar + 0.5 * dt * hvp(x_np1, pbar, prm, pl_np1)
+    pb = pbar + dt / m * xb
+    xb = xb + 0.5 * dt * hvp(x_n, pb, prm, pl_n)
+    return xb, pb
+
+
+def forward_frozen(x, p, prm, pls):
+    """KDK with the placement of each evaluation taken from pls (for FD checks)."""
+    x = _f64(x).copy()
+    p = _f64(p).copy()
+    f = forces(x, prm, pl=pls[0])
+    for n in range(len(pls) - 1):
+        p += 0.5 * prm.dt * f
+        x += prm.dt * p / prm.m
+        f = forces(x, prm, pl=pls[n + 1])
+        p += 0.5 * prm.dt * f
+    return x, p
+
+
+def objective(x, p, prm):
+    """J = (eps_x + eps_y)/2, the transverse normalised rms emittance."""
+    return 0.5 * (emittance(x, p, prm.m, 0) + emittance(x, p, prm.m, 1))
+
+
+def objective_grad(x, p, prm):
+    """Closed-form dJ/dx, dJ/dp of the transverse emittance."""
+    gx = np.zeros_like(x)
+    gp = np.zeros_like(p)
+    n = len(x)
+    mc = prm.m * C_LIGHT
+    for ax in (0, 1):
+        dx = x[:, ax] - x[:, ax].mean()
+        dp = p[:, ax] - p[:, ax].mean()
+        sxx, spp, sxp = (dx * dx).mean(), (dp * dp).mean(), (dx * dp).mean()
+        e2 = sxx * spp - sxp * sxp
+        if e2 <= 0:
+            continue
+        eps = math.sqrt(e2)
+        # d e2 / d x_i = 2 dx_i spp / n - 2 sxp dp_i / n  (centring terms sum to zero)
+        gx[:, ax] += 0.5 * (2 * dx * spp / n - 2 * sxp * dp / n) / (2 * eps) / mc
+        gp[:, ax] += 0.5 * (2 * dp * sxx / n - 2 * sxp * dx / n) / (2 * eps) / mc
+    return gx, gp
+
+
+def gradient(x0, p0, prm, nsteps):
+    """dJ/d(x0, p0) through the reverse KDK, placements frozen as recorded."""
+    xN, pN, xs, pls = rollout(x0, p0, prm, nsteps)
+    xb, pb = objective_grad(xN, pN, prm)
+    for n in range(nsteps - 1, -1, -1):
+        xb, pb = step_backward(xs[n], xs[n + 1], pls[n], pls[n + 1], xb, pb, prm)
+    return xb, pb, (xN, pN, pls)

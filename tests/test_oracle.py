@@ -1,0 +1,439 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks a closed form, an
+invariant, a special case that reduces to a textbook result, brute force on a
+tiny input, or an exact value from the B-spline definition.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_bunch(n, seed, scale=1.0, aniso=(1, 1, 1)):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, 3)) * scale * np.asarray(aniso, float)
+
+
+def _prm(grid=(16, 16, 16), h=(0.25, 0.25, 0.25), rc=0.5, kappa=3.0, order=2, **kw):
+    return O.Params(grid, h, rc, kappa / rc, order, kw.pop("ke_q2", 1.0), **kw)
+
+
+# ---- split identity and PP kernel (Sec. 2.2, eq. ewald_split) -------------------------
+
+def test_split_kernels_sum_to_coulomb():
+    """erfc(a r)/r (PP energy) + erf(a r)/r (mesh kernel) = 1/r at every offset."""
+    h = np.array([0.3, 0.5, 0.7])
+    a = 2.3
+    for off in [(1, 0, 0), (0, 2, 1), (3, 1, 2), (1, 1, 1), (4, 0, 3)]:
+        r = math.sqrt(sum((o * hh) ** 2 for o, hh in zip(off, h)))
+        x = np.array([[0.0, 0.0, 0.0], [off[0] * h[0], off[1] * h[1], off[2] * h[2]]])
+        prm = O.Params((4, 4, 4), h, 10.0, a, 1, 1.0)
+        u_pp = O.pp_energy(x, prm, 10.0, a)
+        g = O.lib().oracle_green(off[0], off[1], off[2], h.ctypes.data, a)
+        assert abs(u_pp + g - 1.0 / r) < 1e-14 / r
+
+
+def test_mesh_kernel_limit_at_origin():
+    """erf(a r)/r -> 2a/sqrt(pi) as r -> 0 (Taylor series of erf)."""
+    a = 1.7
+    h = np.array([1e-7, 1e-7, 1e-7])
+    g0 = O.lib().oracle_green(0, 0, 0, h.ctypes.data, a)
+    g1 = O.lib().oracle_green(1, 0, 0, h.ctypes.data, a)
+    assert g0 == pytest.approx(2 * a / math.sqrt(math.pi), rel=1e-15)
+    assert g1 == pytest.approx(g0, rel=1e-12)
+
+
+def test_alpha_zero_pp_is_coulomb_two_particles():
+    """a = 0: the PP force is Coulomb's k q1 q2 / r^2 along the separation."""
+    x = np.array([[0.1, -0.2, 0.3], [0.4, 0.2, -0.1]])
+    qw = np.array([1.5, -0.5])
+    prm = O.Params((4, 4, 4), (1, 1, 1), 10.0, 0.0, 1, 2.0, qw=qw)
+    f = O.pp_brute(x, prm, 10.0, 0.0)
+    d = x[0] - x[1]
+    r = np.linalg.norm(d)
+    expect = 2.0 * 1.5 * -0.5 / r ** 2 * d / r
+    np.testing.assert_allclose(f[0], expect, rtol=1e-14)
+    np.testing.assert_allclose(f[1], -expect, rtol=1e-14)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pp_cells_equal_brute(seed):
+    """Linked cells find exactly the pairs of the O(N^2) sum (strict r < r_c)."""
+    rng = np.random.default_rng(seed)
+    x = _rand_bunch(700, seed, aniso=(1, 0.5, 3))
+    x[5] = x[6]                      # coincident pair contributes nothing
+    d = rng.standard_normal(3)
+    x[11] = x[10] + 0.4 * d / np.linalg.norm(d)   # a pair near the cutoff
+    qw = rng.random(len(x)) + 0.5
+    prm = O.Params((8, 8, 8), (1, 1, 1), 0.4, 3.0 / 0.4, 1, 1.0, qw=qw)
+    fb = O.pp_brute(x, prm, 0.4, 7.5)
+    fc = O.pp_cells(x, prm, 0.4, 7.5)
+    scale = np.abs(fb).max()
+    assert np.abs(fb - fc).max() <= 1e-13 * scale
+
+
+def test_pp_newton_third_law():
+    x = _rand_bunch(2000, 3)
+    prm = _prm(rc=0.3)
+    f = O.pp_cells(x, prm, 0.3, 10.0)
+    assert np.abs(f.sum(axis=0)).max() <= 1e-13 * np.abs(f).sum()
+
+
+def test_pp_force_is_minus_energy_gradient():
+    """Central differences of the erfc pair energy give the PP force."""
+    x = _rand_bunch(60, 4, scale=0.3)
+    rc, a = 0.6, 3.0 / 0.6
+    prm = _prm(rc=rc)
+    f = O.pp_brute(x, prm, rc, a)
+    eps = 1e-6
+    for i, d in [(0, 0), (7, 1), (33, 2), (59, 0)]:
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += eps
+        xm[i, d] -= eps
+        fd = -(O.pp_energy(xp, prm, rc, a) - O.pp_energy(xm, prm, rc, a)) / (2 * eps)
+        assert fd == pytest.approx(f[i, d], rel=2e-6, abs=1e-6 * np.abs(f).max())
+
+
+# ---- assignment (Sec. 2.4.2, eq. interpolation_splines_b0) ----------------------------
+
+def _golden_weights():
+    rows = []
+    with open(os.path.join(GOLDEN, "bspline_weights.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                rows.append([float(t) for t in line.split()])
+    return rows
+
+
+def test_bspline_weights_golden():
+    """One particle at fractional node offsets deposits the exact B-spline weights."""
+    for order, frac, w0, w1, w2 in _golden_weights():
+        order = int(order)
+        grid = (8, 8, 8)
+        prm = O.Params(grid, (1, 1, 1), 1.0, 1.0, order, 1.0, zoom=False)
+        pl = {"x0": np.zeros(3), "hp": np.ones(3)}
+        u = 3.0 + frac
+        x = np.array([[u, 3.0, 3.0]])
+        Q = O.deposit(x, prm, pl)
+        line = Q.sum(axis=(0, 1))
+        if order == 1:
+            base = int(math.floor(u))
+            got = [line[base], line[base + 1], 0.0]
+        else:
+            c = int(math.floor(u + 0.5))
+            got = [line[c - 1], line[c], line[c + 1]]
+        np.testing.assert_allclose(got, [w0, w1, w2], atol=1e-15)
+        # the transverse axes sit on a node
+        prof = Q.sum(axis=(0, 2))
+        expect = [1.0] if order == 1 else [0.125, 0.75, 0.125]
+        lo = 3 if order == 1 else 2
+        np.testing.assert_allclose(prof[lo:lo + len(expect)], expect, atol=1e-15)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_deposit_conserves_charge_and_dipole(order):
+    """sum Q = sum q and sum x_m Q_m = sum q_i xi_i (B-splines reproduce linears)."""
+    x = _rand_bunch(3000, 5, aniso=(1, 2, 0.5))
+    rng = np.random.default_rng(9)
+    qw = rng.random(len(x)) + 0.1
+    prm = O.Params((20, 24, 12), (0.4, 0.7, 0.3), 0.8, 3.0, order, 1.0, qw=qw)
+    pl = O.placement(x, prm)
+    Q = O.deposit(x, prm, pl)
+    assert Q.sum() == pytest.approx(qw.sum(), rel=1e-13)
+    nz, ny, nx = Q.shape
+    gz, gy, gx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for d, g in enumerate((gx, gy, gz)):
+        xm = pl["x0"][d] + g * pl["hp"][d]
+        assert (xm * Q).sum() == pytest.approx((qw * x[:, d]).sum(), rel=1e-12, abs=1e-12)
+
+
+# ---- convolution (Sec. 3, eq. phi_L; Hockney doubling) --------------------------------
+
+@pytest.mark.parametrize("grid", [(2, 2, 2), (3, 4, 5), (6, 6, 6), (5, 2, 3)])
+def test_fft_convolution_equals_direct(grid):
+    rng = np.random.default_rng(sum(grid))
+    Q = rng.standard_normal((grid[2], grid[1], grid[0]))
+    hp = np.array([0.5, 0.3, 0.9])
+    a = 1.3
+    np.testing.assert_allclose(O.conv_fft(Q, grid, hp, a), O.conv_direct(Q, grid, hp, a),
+                               rtol=1e-12, atol=1e-12 * np.abs(Q).sum())
+
+
+def test_single_charge_gives_kernel():
+    """A unit charge on node m0 gives phi(m) = G(m - m0), with no wrap-around."""
+    grid = (8, 6, 7)
+    hp = np.array([0.2, 0.35, 0.5])
+    a = 2.0
+    Q = np.zeros((7, 6, 8))
+    Q[6, 0, 7] = 1.0                 # a corner: offsets reach N-1 in every axis
+    phi = O.conv_fft(Q, grid, hp, a)
+    for (z, y, x) in [(0, 5, 0), (6, 0, 7), (3, 2, 1), (0, 0, 0)]:
+        g = O.lib().oracle_green(x - 7, y - 0, z - 6, hp.ctypes.data, a)
+        assert phi[z, y, x] == pytest.approx(g, rel=1e-12)
+
+
+# ---- gather (Sec. 2.5, eq. eom_p3m_coord first term) ----------------------------------
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_gather_linear_potential_exact_gradient(order):
+    """For phi linear in the node position the weight gradient returns it exactly."""
+    grid = (10, 12, 9)
+    x = _rand_bunch(200, 6, scale=0.3)
+    qw = np.random.default_rng(1).random(len(x)) + 0.5
+    prm = O.Params(grid, (0.3, 0.25, 0.4), 0.5, 1.0, order, 2.0, qw=qw)
+    pl = O.placement(x, prm)
+    c = np.array([1.5, -0.7, 0.4])
+    nz, ny, nx = grid[2], grid[1], grid[0]
+    gz, gy, gx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = 3.0 + c[0] * (pl["x0"][0] + gx * pl["hp"][0]) + c[1] * (pl["x0"][1] + gy * pl["hp"][1]) \
+        + c[2] * (pl["x0"][2] + gz * pl["hp"][2])
+    f = O.gather(x, prm, pl, phi)
+    np.testing.assert_allclose(f, -2.0 * qw[:, None] * c[None, :], rtol=1e-11)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_pm_force_is_minus_energy_gradient(order):
+    """F_PM = -dU_PM/dxi with U_PM = k q^2 sum_m Q_m phi_m / 2 (placement frozen)."""
+    x = _rand_bunch(40, 7, scale=0.5)
+    prm = O.Params((12, 12, 12), (0.4, 0.4, 0.4), 0.8, 3.0 / 0.8, order, 1.0)
+    pl = O.placement(x, prm)
+    pl["x0"] = pl["x0"] - 0.013        # keep every particle well away from a knot
+    F, parts = O.forces(x, prm, parts=True, pl=pl)
+
+    def upm(xx):
+        Q = O.deposit(xx, prm, pl)
+        return 0.5 * (Q * O.conv_fft(Q, prm.grid, pl["hp"], pl["a"])).sum()
+
+    eps = 1e-7
+    for i, d in [(0, 0), (3, 1), (17, 2), (39, 1)]:
+        u = (x[i, d] - pl["x0"][d]) / pl["hp"][d]
+        knot = u - math.floor(u) if order == 1 else u + 0.5 - math.floor(u + 0.5)
+        if min(knot, 1 - knot) < 1e-3:
+            continue
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += eps
+        xm[i, d] -= eps
+        fd = -(upm(xp) - upm(xm)) / (2 * eps)
+        assert fd == pytest.approx(parts["pm"][i, d], rel=1e-5, abs=1e-6 * np.abs(parts["pm"]).max())
+
+
+def test_pm_two_particles_far_limit():
+    """TSC, smooth kernel (a h = 0.25): at 8h the mesh force approaches the
+    closed-form force of the erf(a r)/r pair potential."""
+    from scipy.special import erf
+    rng = np.random.default_rng(11)
+    h, a = 1.0, 0.25
+    errs = []
+    for _ in range(10):
+        c = rng.random(3)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        x = np.array([c, c + 8 * h * d])
+        prm = O.Params((32, 32, 32), (h, h, h), 1e-9, a, 2, 1.0)
+        pl = O.placement(x, prm)
+        Q = O.deposit(x, prm, pl)
+        f = O.gather(x, prm, pl, O.conv_fft(Q, prm.grid, pl["hp"], pl["a"]))
+        r = 8.0 * h
+        g = (erf(a * r) / r - 2 * a / math.sqrt(math.pi) * math.exp(-(a * r) ** 2)) / r ** 2
+        exact = g * (x[0] - x[1])
+        errs.append(np.linalg.norm(f[0] - exact) / np.linalg.norm(exact))
+    assert max(errs) < 0.03
+
+
+# ---- whole force ----------------------------------------------------------------
+
+def test_alpha_zero_large_cutoff_equals_coulomb():
+    """a = 0 and r_c wider than the bunch: P3M is the O(N^2) Coulomb sum."""
+    x = _rand_bunch(500, 8)
+    prm = O.Params((8, 8, 8), (1.0, 1.0, 1.0), 100.0, 0.0, 2, 3.0)
+    f = O.forces(x, prm)
+    fc = O.coulomb_brute(x, 3.0)
+    assert np.abs(f - fc).max() <= 1e-13 * np.abs(fc).max()
+
+
+def test_zoom_keeps_stencils_on_mesh_and_scales():
+    x = _rand_bunch(400, 9, scale=5.0)
+    prm = O.Params((16, 16, 16), (0.2, 0.2, 0.2), 0.4, 7.5, 2, 1.0)
+    pl = O.placement(x, prm)
+    assert pl["s"] > 1
+    u = (x - pl["x0"]) / pl["hp"]
+    assert u.min() > 0.5 and u.max() < 16 - 1.5
+    assert pl["rc"] == pytest.approx(0.4 * pl["s"]) and pl["a"] == pytest.approx(7.5 / pl["s"])
+
+
+def test_error_paths():
+    x = _rand_bunch(50, 10)
+    prm = O.Params((16, 16, 16), (0.01, 0.01, 0.01), 0.02, 150.0, 2, 1.0, zoom=False)
+    with pytest.raises(O.OracleError) as e:
+        O.placement(x, prm)
+    assert e.value.code == O.EDOMAIN
+    x[3, 1] = np.nan
+    prm.zoom = True
+    with pytest.raises(O.OracleError) as e:
+        O.placement(x, prm)
+    assert e.value.code == O.ENONFINITE
+    prm.order = 3
+    with pytest.raises(O.OracleError) as e:
+        O.placement(x[:2] * 0, prm)
+    assert e.value.code == O.EINVAL
+
+
+# ---- integrator (Sec. 2.4.3, eq. leapfrog; Sec. 2.5, eq. eom_p3m_coord) --------------
+
+def _small_run_prm(n=300, seed=12):
+    x = _rand_bunch(n, seed, scale=1e-3)
+    ke_q2 = 8.9875517923e9 * (1e-9 / n) ** 2
+    m = (1e-9 / n) * 9.1093837015e-31 / 1.602176634e-19
+    prm = O.Params((16, 16, 16), (8e-3 / 14,) * 3, 2 * 8e-3 / 14, 3.0 / (2 * 8e-3 / 14), 2,
+                   ke_q2, m=m, dt=2e-12)
+    return x, prm
+
+
+def test_leapfrog_discrete_euler_lagrange():
+    """KDK positions obey m (xi^{n+1} - 2 xi^n + xi^{n-1}) = dt^2 F(xi^n)."""
+    x, prm = _small_run_prm()
+    p = np.zeros_like(x)
+    xs = [x]
+    f = None
+    for _ in range(3):
+        x, p, f = O.step(x, p, prm, 1, f)
+        xs.append(x)
+    for n in (1, 2):
+        lhs = prm.m * (xs[n + 1] - 2 * xs[n] + xs[n - 1])
+        rhs = prm.dt ** 2 * O.forces(xs[n], prm)
+        assert np.abs(lhs - rhs).max() <= 1e-9 * np.abs(rhs).max()
+
+
+def test_leapfrog_time_reversible():
+    x0, prm = _small_run_prm()
+    p0 = np.zeros_like(x0)
+    x1, p1, _ = O.step(x0, p0, prm, 5)
+    x2, p2, _ = O.step(x1, -p1, prm, 5)
+    assert np.abs(x2 - x0).max() <= 1e-9 * np.abs(x1 - x0).max()
+    assert np.abs(p2).max() <= 1e-8 * np.abs(p1).max()
+
+
+def test_two_particles_from_rest_closed_form():
+    """Pure Coulomb pair (a = 0) released at r0: s = r/r0 obeys s'' = A/s^2,
+    A = 2 k q^2/(m r0^3); t sqrt(2A) = sqrt(s(s-1)) + ln(sqrt(s) + sqrt(s-1)).
+    Leapfrog converges to it at second order."""
+    ke_q2, m, r0 = 1.0, 1.0, 1.0
+    A = 2 * ke_q2 / (m * r0 ** 3)
+    T = 1.5
+    s_exact = brentq(lambda s: math.sqrt(s * (s - 1)) + math.log(math.sqrt(s) + math.sqrt(s - 1))
+                     - T * math.sqrt(2 * A), 1.0 + 1e-12, 100.0)
+    errs = []
+    for nsteps in (100, 200):
+        prm = O.Params((4, 4, 4), (1.0, 1.0, 1.0), 1e6, 0.0, 1, ke_q2, m=m, dt=T / nsteps)
+        x = np.array([[0.0, 0.0, -0.5], [0.0, 0.0, 0.5]])
+        xn, _, _ = O.step(x, np.zeros_like(x), prm, nsteps)
+        errs.append(abs((xn[1, 2] - xn[0, 2]) / r0 - s_exact))
+    assert errs[0] < 1e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_energy_bounded():
+    x, prm = _small_run_prm(n=200)
+    prm.dt = 5e-12
+    p = np.zeros_like(x)
+
+    def energy(x, p):
+        pl = O.placement(x, prm)
+        d = O.diagnostics(x, p, prm, brute_pp=True)
+        return d["kinetic"] + d["u_pp"] + d["u_pm"]
+
+    e0 = energy(x, p)
+    es = []
+    f = None
+    for _ in range(6):
+        x, p, f = O.step(x, p, prm, 5, f)
+        es.append(energy(x, p))
+    ke = O.diagnostics(x, p, prm)["kinetic"]
+    assert max(abs(e - e0) for e in es) < 0.05 * ke
+
+
+@pytest.mark.slow
+def test_uniform_sphere_expansion_closed_form():
+    """Cold uniform ball: r_rms(t) = sqrt(3/5) R s(t) with
+    t w_p sqrt(2/3) = sqrt(s(s-1)) + ln(sqrt(s) + sqrt(s-1))."""
+    from paper_2103_02046_amd import workloads as W
+    wl = W.sphere_tsc(n=20000, grid=32, steps=50)
+    x, p = wl.draw()
+    prm = O.Params.from_workload(wl)
+    xn, pn, _ = O.step(x, p, prm, 50)        # 0.25 plasma periods
+    t = 50 * wl.dt
+    wp = 2 * math.pi / (200 * wl.dt)
+    s = brentq(lambda s: math.sqrt(s * (s - 1)) + math.log(math.sqrt(s) + math.sqrt(s - 1))
+               - t * wp * math.sqrt(2 / 3), 1 + 1e-12, 50)
+    rrms = math.sqrt(((xn - xn.mean(0)) ** 2).sum(1).mean())
+    rrms0 = math.sqrt(((x - x.mean(0)) ** 2).sum(1).mean())
+    assert rrms / rrms0 == pytest.approx(s, rel=2e-2)
+
+
+# ---- adjoint pieces -------------------------------------------------------------
+
+def _adj_setup(order=2, n=80, seed=13):
+    x = _rand_bunch(n, seed, scale=0.5)
+    prm = O.Params((12, 12, 12), (0.35, 0.35, 0.35), 0.7, 3.0 / 0.7, order, 1.0, m=1.0, dt=0.01)
+    pl = O.placement(x, prm)
+    pl["x0"] = pl["x0"] - 0.011
+    return x, prm, pl
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_hvp_symmetric(order):
+    x, prm, pl = _adj_setup(order)
+    rng = np.random.default_rng(3)
+    v, w = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+    a = (O.hvp(x, v, prm, pl) * w).sum()
+    b = (v * O.hvp(x, w, prm, pl)).sum()
+    assert a == pytest.approx(b, rel=1e-11)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_hvp_matches_force_differences(order):
+    x, prm, pl = _adj_setup(order)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal(x.shape)
+    eps = 1e-7
+    fd = (O.forces(x + eps * v, prm, brute=True, pl=pl) - O.forces(x - eps * v, prm, brute=True, pl=pl)) / (2 * eps)
+    hv = O.hvp(x, v, prm, pl)
+    assert np.abs(fd - hv).max() <= 1e-5 * np.abs(hv).max()
+
+
+def test_gradient_drift_only_closed_form():
+    """k_e = 0: x_N = x_0 + N dt p_0/m, so dJ/dx0 = g_x, dJ/dp0 = g_p + N dt/m g_x."""
+    x, prm, _ = _adj_setup()
+    prm.ke_q2 = 0.0
+    rng = np.random.default_rng(5)
+    p = rng.standard_normal(x.shape)
+    N = 4
+    gx, gp, (xN, pN, _) = O.gradient(x, p, prm, N)
+    ex, ep = O.objective_grad(xN, pN, prm)
+    np.testing.assert_allclose(gx, ex, rtol=1e-12, atol=1e-14 * np.abs(ex).max())
+    np.testing.assert_allclose(gp, ep + N * prm.dt / prm.m * ex, rtol=1e-12,
+                               atol=1e-14 * np.abs(ep + ex).max())
+
+
+def test_gradient_matches_central_differences():
+    x, prm, _ = _adj_setup(n=60)
+    prm.dt = 0.02
+    rng = np.random.default_rng(6)
+    p = 0.1 * rng.standard_normal(x.shape)
+    N = 3
+    gx, gp, (_, _, pls) = O.gradient(x, p, prm, N)
+    for _ in range(4):
+        dx, dp = rng.standard_normal(x.shape), rng.standard_normal(p.shape)
+        eps = 1e-6
+        jp = O.objective(*O.forward_frozen(x + eps * dx, p + eps * dp, prm, pls), prm)
+        jm = O.objective(*O.forward_frozen(x - eps * dx, p - eps * dp, prm, pls), prm)
+        fd = (jp - jm) / (2 * eps)
+        an = (gx * dx).sum() + (gp * dp).sum()
+        assert an == pytest.approx(fd, rel=1e-5)
