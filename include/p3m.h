@@ -1,0 +1,206 @@
+/*
+ * p3m.h -- C ABI of the MI355X P3M space-charge library (libp3m.so).
+ *
+ * The library evaluates the P3M force of Wyssling & Adelmann (arXiv
+ * 2103.02046) on a bunch of equal-mass macro-particles and advances it with
+ * the leapfrog integrator, all in hand-written HIP kernels for gfx950:
+ *
+ *   F_i = F_i^PP + F_i^PM                              (Sec. 2.5, eq. eom_p3m_coord)
+ *   F_i^PP = sum_{j != i, r_ij < r_c'} k_e q^2 w_i w_j
+ *            [erfc(a' r)/r + (2a'/sqrt(pi)) e^{-a'^2 r^2}] (x_i - x_j)/r^2
+ *                                       (Sec. 1, eq. summation_short with the
+ *                                        erfc part of eq. ewald_split, Sec. 2.2)
+ *   Q_m    = sum_i w_i prod_d b_p(u_{i,d} - m_d)     (Sec. 2.4.2, B-spline assignment,
+ *                                                      eq. interpolation_splines_b0)
+ *   phi_m  = sum_m' G(m - m') Q_m',  G = erf(a' r)/r sampled on the mesh,
+ *            aperiodic (open boundaries by zero padding to a doubled mesh)
+ *                                       (Sec. 3, eq. phi_L with eq. free_gf)
+ *   F_i^PM = -k_e q^2 w_i sum_m phi_m grad b(u_i - m) (Sec. 2.5, eq. eom_p3m_coord)
+ *   leapfrog (kick-drift-kick)          (Sec. 2.4.3, eq. leapfrog)
+ *
+ * Placement: every evaluation centres the mesh (nodes x0 + k h') on the
+ * bounding box of the positions. When the box is wider than the nodes an
+ * assignment stencil may use (grid-1 for CIC, grid-2 for TSC), a common zoom
+ * s >= 1 scales h' = s h and r_c' = s r_c and divides the split parameter,
+ * a' = a / s (with zoom disabled this is the P3M_EDOMAIN error instead).
+ *
+ * Conventions for every call:
+ *   - particle arrays are DEVICE pointers, row-major [n][3] float64, in the
+ *     caller's particle order, owned by the caller; the library never keeps
+ *     them after the call returns;
+ *   - `stream` is a hipStream_t (NULL = the default stream); all work is
+ *     enqueued on it and calls return without synchronising unless stated;
+ *     one context must be used by one stream at a time;
+ *   - errors in the arguments are returned at once; errors that depend on
+ *     the data (non-finite or out-of-mesh positions) are raised in a device
+ *     status word and returned by the next p3m_status_sync;
+ *   - p3m_last_error gives a message for the last failing call.
+ */
+#ifndef P3M_H
+#define P3M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct p3m_ctx p3m_ctx;
+typedef int32_t p3m_status;
+
+#define P3M_OK          0
+#define P3M_EINVAL     (-1)   /* bad argument                                   */
+#define P3M_ENOMEM     (-2)   /* device allocation failed                       */
+#define P3M_EHIP       (-3)   /* a HIP runtime call failed                      */
+#define P3M_ESTATE     (-4)   /* call not valid in the context's state          */
+#define P3M_EDOMAIN    (-5)   /* a particle left the mesh with zoom disabled    */
+#define P3M_ENONFINITE (-6)   /* a position was NaN or infinite                 */
+
+#define P3M_FP64   0          /* every stage in float64                         */
+#define P3M_FP32C  1          /* pair forces and FFT in float32 with Kahan-     */
+                              /* compensated pair sums; float64 Green's table,  */
+                              /* positions, momenta and reductions              */
+
+#define P3M_CIC 1             /* linear B-spline b1 (2 nodes per axis)          */
+#define P3M_TSC 2             /* quadratic B-spline b2 (3 nodes per axis)       */
+
+/* Placement record of one evaluation: x0[3] (position of mesh node 0, m) and
+ * the zoom s. Used to record placements in a forward run and replay them. */
+#define P3M_PLACEMENT_DOUBLES 4
+
+typedef struct {
+    int32_t order;      /* P3M_CIC or P3M_TSC                               [TSC]  */
+    int32_t precision;  /* P3M_FP64 or P3M_FP32C                            [FP64] */
+    int32_t zoom;       /* 1: zoom the mesh to fit the bunch; 0: EDOMAIN    [1]    */
+    int32_t keep_mesh;  /* 1: keep the charge mesh of the last evaluation for
+                           p3m_mesh (one extra clear per evaluation)        [0]    */
+    double ke;          /* Coulomb constant 1/(4 pi eps0)     [8.9875517923e9]    */
+    double q;           /* macro-particle charge, C                        [1.0]  */
+    double m;           /* macro-particle mass, kg                         [1.0]  */
+} p3m_opts;
+
+/* Fill *opts with the defaults shown in brackets above. */
+p3m_status p3m_default_opts(p3m_opts *opts);
+
+/*
+ * Create a context for a grid[0] x grid[1] x grid[2] vertex mesh with spacing
+ * h[3] (m), PP cutoff r_cut (m) and Ewald split parameter `split` (1/m; 0
+ * means the whole Coulomb force is summed pairwise inside r_cut and the mesh
+ * part vanishes). Grid sizes must be powers of two in [4, 1024].
+ * Builds the Fourier transform of the sampled erf(a r)/r kernel on the
+ * doubled mesh in float64 (once; zoom rescales it exactly by 1/s).
+ * *out receives the context; the caller frees it with p3m_destroy.
+ * Errors: P3M_EINVAL (sizes, non-positive h or r_cut, negative split, bad
+ * opts), P3M_ENOMEM, P3M_EHIP.
+ */
+p3m_status p3m_create(p3m_ctx **out, const int32_t grid[3], const double h[3],
+                      double r_cut, double split, const p3m_opts *opts);
+
+/*
+ * Total P3M force on n particles at positions x[n][3] (device, m).
+ * qw[n] (device, may be NULL = all 1) are dimensionless charge weights: the
+ * charge of particle i is q * qw[i]. Writes f[n][3] (device, N) in caller
+ * order. n may be 0 (no work). Device buffers grow on demand (this call may
+ * allocate when n exceeds every earlier n).
+ * Errors: P3M_EINVAL (n < 0, NULL x or f), P3M_ENOMEM, P3M_EHIP; data
+ * errors via p3m_status_sync.
+ */
+p3m_status p3m_forces(p3m_ctx *ctx, int64_t n, const double *x, const double *qw,
+                      double *f, void *stream);
+
+/*
+ * As p3m_forces, with the two parts written separately (either may be NULL)
+ * and an optional fixed placement: if place_in (device, P3M_PLACEMENT_DOUBLES
+ * float64) is not NULL the mesh is placed there instead of on the bounding
+ * box; if place_out (device) is not NULL the placement used is written there.
+ */
+p3m_status p3m_forces_ex(p3m_ctx *ctx, int64_t n, const double *x, const double *qw,
+                         double *f_pp, double *f_pm, const double *place_in,
+                         double *place_out, void *stream);
+
+/*
+ * Advance (x, p) (device [n][3] float64, m and kg m/s, updated in place) by
+ * nsteps kick-drift-kick leapfrog steps of dt seconds:
+ *   p += dt/2 F(x);  x += dt p / m;  p += dt/2 F(x).
+ * The force at the starting x is evaluated first unless `reuse_force` is 1
+ * and the previous p3m_step on this context ended at this same x (the
+ * context caches that force; any other call clears the cache).
+ * If place_replay (device) is not NULL it holds (nsteps+1) placement
+ * records used instead of the bounding-box placement: record 0 for the start
+ * position, record k for the end of step k (a recorded run replayed exactly).
+ * If place_record (device) is not NULL it receives the (nsteps+1) placements
+ * used, in the same order.
+ * Errors: as p3m_forces; P3M_ESTATE if reuse_force is asked with no cache.
+ */
+p3m_status p3m_step(p3m_ctx *ctx, int64_t n, double *x, double *p, const double *qw,
+                    double dt, int32_t nsteps, int32_t reuse_force, const double *place_replay,
+                    double *place_record, void *stream);
+
+/*
+ * Hessian-vector product of the P3M potential: out = H v, H = dF/dx at x with
+ * the placement fixed at place (device, P3M_PLACEMENT_DOUBLES; NULL = the
+ * bounding-box placement of x). H is symmetric because F = -grad U, so this
+ * is also the vector-Jacobian product. v and out are device [n][3] float64.
+ */
+p3m_status p3m_hvp(p3m_ctx *ctx, int64_t n, const double *x, const double *qw,
+                   const double *v, const double *place, double *out, void *stream);
+
+/*
+ * Adjoint of one leapfrog step (x_n, p_n) -> (x_np1, p_np1) of length dt,
+ * with the placements recorded in the forward run (place_n, place_np1,
+ * device). Given the gradients xbar_np1, pbar_np1 of a scalar objective with
+ * respect to (x_np1, p_np1), writes those with respect to (x_n, p_n):
+ *   xb = xbar_np1 + dt/2 H(x_np1) pbar_np1;  pb = pbar_np1 + dt/m xb;
+ *   xbar_n = xb + dt/2 H(x_n) pb;  pbar_n = pb.
+ * All arrays device [n][3] float64; outputs may alias the inputs.
+ */
+p3m_status p3m_backward(p3m_ctx *ctx, int64_t n, const double *x_n, const double *x_np1,
+                        const double *qw, const double *xbar_np1, const double *pbar_np1,
+                        double *xbar_n, double *pbar_n, double dt, const double *place_n,
+                        const double *place_np1, void *stream);
+
+typedef struct {
+    double momentum[3];   /* sum_i p_i                                   kg m/s */
+    double kinetic;       /* sum_i |p_i|^2 / (2m)                        J      */
+    double u_pp;          /* sum_{i<j, r<r_c'} k_e q^2 w_i w_j erfc(a'r)/r  J   */
+    double u_pm;          /* k_e q^2 sum_m Q_m phi_m / 2                  J      */
+    double mean[3];       /* centroid                                    m      */
+    double rms[3];        /* rms size per axis                           m      */
+    double emit_n[3];     /* normalised rms emittance per axis, m rad:
+                             sqrt(<dx^2><dp^2> - <dx dp>^2) / (m c)            */
+    double zoom;          /* s of this evaluation                               */
+    double charge;        /* sum_i w_i                                          */
+} p3m_diag;
+
+/*
+ * Observables of (x, p) in float64 reductions (the energies use a fresh force
+ * evaluation at x). Synchronises `stream`; *out is host memory.
+ */
+p3m_status p3m_diagnostics(p3m_ctx *ctx, int64_t n, const double *x, const double *p,
+                           const double *qw, p3m_diag *out, void *stream);
+
+/*
+ * Copy the mesh of the last evaluation into out (device, float64,
+ * [grid[2]][grid[1]][grid[0]], x fastest): which = 0 the charge Q (units of
+ * q), which = 1 the potential phi (1/m; the physical potential is k_e q phi).
+ */
+p3m_status p3m_mesh(p3m_ctx *ctx, int32_t which, double *out, void *stream);
+
+/* Synchronise `stream`, return and clear the device status word
+ * (P3M_OK, P3M_EDOMAIN or P3M_ENONFINITE). */
+p3m_status p3m_status_sync(p3m_ctx *ctx, void *stream);
+
+/* Number of radix-sort passes, PP cells and padded FFT extents (host info). */
+p3m_status p3m_info(const p3m_ctx *ctx, int64_t out[8]);
+
+/* Message of the last failing call on ctx (never NULL). */
+const char *p3m_last_error(const p3m_ctx *ctx);
+
+/* Free the context and every device buffer it owns. NULL is a no-op. */
+void p3m_destroy(p3m_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P3M_H */

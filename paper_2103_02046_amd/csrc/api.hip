@@ -1,0 +1,575 @@
+// C ABI of libp3m: context, device buffers and the order of the kernels of
+// one P3M force evaluation, leapfrog step and adjoint step.
+//
+//   placement (bbox) -> cell keys -> radix sort -> cell starts -> reorder
+//   -> PP pair forces  -> deposit -> FFT convolution -> gather (+ push)
+//
+// Everything is enqueued on the caller's stream; the host never waits for
+// the device inside p3m_forces / p3m_step / p3m_hvp / p3m_backward.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "p3m.h"
+#include "launch.h"
+
+using namespace p3m;
+
+namespace {
+
+constexpr double kCLight = 299792458.0;
+
+template <typename R>
+struct Engine {
+  // per-particle
+  PPRec<R>* pp = nullptr;
+  MeshRec<R>* mesh = nullptr;
+  PPRec<R>* fpp = nullptr;
+  // mesh
+  R* Q = nullptr;
+  R* phi = nullptr;
+  C2<R>* spec = nullptr;
+  C2<R>* tw[3] = {nullptr, nullptr, nullptr};
+  int64_t cap = 0;
+  bool mesh_ready = false;
+};
+
+}  // namespace
+
+struct p3m_ctx {
+  Geo geo{};
+  p3m_opts opts{};
+  std::string err;
+  int64_t cap = 0;
+  // sort
+  SortBufs sb{};
+  int sort_nb_cap = 0;
+  // placement, status, small scratch
+  Place* place = nullptr;
+  int* status = nullptr;
+  double* bbox_part = nullptr;
+  double* acc = nullptr;        // 64 doubles of reduction scratch
+  double* ghat = nullptr;
+  // step
+  double* fcache = nullptr;     // [cap][3]
+  bool force_cached = false;
+  const double* cached_x = nullptr;
+  int64_t cached_n = -1;
+  // adjoint scratch (float64)
+  double *v_sorted = nullptr, *hpp = nullptr, *hv = nullptr, *xb = nullptr, *pb = nullptr;
+  double *Rm = nullptr, *psi = nullptr;
+  Engine<float> e32;
+  Engine<double> e64;
+  uint32_t* keys = nullptr;     // sorted keys of the last evaluation
+  uint32_t* perm = nullptr;     // sorted -> caller index of the last evaluation
+  int last_precision = -1;      // engine of the last evaluation
+  bool keep_mesh = false;
+};
+
+namespace {
+
+size_t mesh_nodes(const Geo& g) { return (size_t)g.grid[0] * g.grid[1] * g.grid[2]; }
+
+p3m_status fail(p3m_ctx* c, p3m_status code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? P3M_ENOMEM : P3M_EHIP,             \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+template <typename R>
+p3m_status engine_mesh_alloc(p3m_ctx* ctx, Engine<R>& E) {
+  if (E.mesh_ready) return P3M_OK;
+  const Geo& g = ctx->geo;
+  HIPCHK(dalloc(&E.Q, mesh_nodes(g)));
+  HIPCHK(dalloc(&E.phi, mesh_nodes(g)));
+  HIPCHK(dalloc(&E.spec, spectrum_elems(g)));
+  HIPCHK(hipMemset(E.Q, 0, mesh_nodes(g) * sizeof(R)));
+  for (int d = 0; d < 3; ++d) {
+    const int L = 2 * g.grid[d];
+    std::vector<C2<R>> h(L);
+    make_twiddles<R>(L, h.data());
+    HIPCHK(dalloc(&E.tw[d], (size_t)L));
+    HIPCHK(hipMemcpy(E.tw[d], h.data(), L * sizeof(C2<R>), hipMemcpyHostToDevice));
+  }
+  E.mesh_ready = true;
+  return P3M_OK;
+}
+
+template <typename R>
+p3m_status engine_particles(p3m_ctx* ctx, Engine<R>& E, int64_t n) {
+  if (n <= E.cap) return P3M_OK;
+  dfree(E.pp);
+  dfree(E.mesh);
+  dfree(E.fpp);
+  E.cap = 0;
+  HIPCHK(dalloc(&E.pp, (size_t)n));
+  HIPCHK(dalloc(&E.mesh, (size_t)n));
+  HIPCHK(dalloc(&E.fpp, (size_t)n));
+  E.cap = n;
+  return P3M_OK;
+}
+
+template <typename R>
+void engine_free(Engine<R>& E) {
+  dfree(E.pp);
+  dfree(E.mesh);
+  dfree(E.fpp);
+  dfree(E.Q);
+  dfree(E.phi);
+  dfree(E.spec);
+  for (int d = 0; d < 3; ++d) dfree(E.tw[d]);
+  E.cap = 0;
+  E.mesh_ready = false;
+}
+
+p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
+  if (n > 0xffffffffll / 2) return fail(ctx, P3M_EINVAL, "n exceeds the 32-bit particle index range");
+  if (n <= ctx->cap) return P3M_OK;
+  dfree(ctx->sb.keys_a);
+  dfree(ctx->sb.vals_a);
+  dfree(ctx->sb.keys_b);
+  dfree(ctx->sb.vals_b);
+  dfree(ctx->sb.counts);
+  dfree(ctx->fcache);
+  dfree(ctx->v_sorted);
+  dfree(ctx->hpp);
+  dfree(ctx->hv);
+  dfree(ctx->xb);
+  dfree(ctx->pb);
+  ctx->cap = 0;
+  ctx->force_cached = false;
+  HIPCHK(dalloc(&ctx->sb.keys_a, (size_t)n));
+  HIPCHK(dalloc(&ctx->sb.vals_a, (size_t)n));
+  HIPCHK(dalloc(&ctx->sb.keys_b, (size_t)n));
+  HIPCHK(dalloc(&ctx->sb.vals_b, (size_t)n));
+  HIPCHK(dalloc(&ctx->sb.counts, (size_t)256 * sort_blocks(n)));
+  HIPCHK(dalloc(&ctx->fcache, (size_t)3 * n));
+  ctx->cap = n;
+  return P3M_OK;
+}
+
+p3m_status ensure_adjoint(p3m_ctx* ctx, int64_t n) {
+  if (!ctx->v_sorted) {
+    HIPCHK(dalloc(&ctx->v_sorted, (size_t)3 * ctx->cap));
+    HIPCHK(dalloc(&ctx->hpp, (size_t)3 * ctx->cap));
+    HIPCHK(dalloc(&ctx->hv, (size_t)3 * ctx->cap));
+    HIPCHK(dalloc(&ctx->xb, (size_t)3 * ctx->cap));
+    HIPCHK(dalloc(&ctx->pb, (size_t)3 * ctx->cap));
+  }
+  if (!ctx->Rm) {
+    HIPCHK(dalloc(&ctx->Rm, mesh_nodes(ctx->geo)));
+    HIPCHK(dalloc(&ctx->psi, mesh_nodes(ctx->geo)));
+  }
+  (void)n;
+  return P3M_OK;
+}
+
+// Placement from the bounding box of x (or from place_in), into ctx->place.
+void place(p3m_ctx* ctx, int64_t n, const double* x, const double* place_in, double* place_out,
+           hipStream_t st) {
+  const int nb = bbox_blocks(n);
+  launch_bbox(n, x, ctx->bbox_part, nb, ctx->status, st);
+  launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_in, ctx->place, place_out, ctx->status, st);
+}
+
+// Everything after the placement: linked cells, PP, mesh, gather.
+template <typename R>
+p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, int64_t n, const double* x, const double* qw,
+                    GatherOut out, double* e_pp, double* e_pm, hipStream_t st) {
+  p3m_status s;
+  if ((s = engine_mesh_alloc(ctx, E)) != P3M_OK) return s;
+  if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
+  const Geo& g = ctx->geo;
+  launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
+  launch_reorder<R>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, st);
+  launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, E.fpp, e_pp, st);
+  if (ctx->keep_mesh) launch_fill(E.Q, mesh_nodes(g) * sizeof(R), st);
+  launch_deposit<R>(n, E.pp, E.mesh, g, E.Q, st);
+  const C2<R>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
+  launch_convolve<R>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, ctx->keep_mesh ? 0 : 1, st);
+  launch_gather<R>(n, E.pp, E.mesh, E.fpp, ctx->perm, g, ctx->place, E.phi, out, e_pm, st);
+  ctx->last_precision = sizeof(R) == 4 ? P3M_FP32C : P3M_FP64;
+  return P3M_OK;
+}
+
+p3m_status evaluate_any(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, GatherOut out,
+                        double* e_pp, double* e_pm, hipStream_t st) {
+  if (ctx->opts.precision == P3M_FP32C) return evaluate<float>(ctx, ctx->e32, n, x, qw, out, e_pp, e_pm, st);
+  return evaluate<double>(ctx, ctx->e64, n, x, qw, out, e_pp, e_pm, st);
+}
+
+p3m_status check_last(p3m_ctx* ctx) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, P3M_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return P3M_OK;
+}
+
+// H v at x (placement fixed at ctx->place), float64, into out (caller order).
+p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, const double* v,
+                    double* out, hipStream_t st) {
+  p3m_status s;
+  Engine<double>& E = ctx->e64;
+  if ((s = engine_mesh_alloc(ctx, E)) != P3M_OK) return s;
+  if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
+  if ((s = ensure_adjoint(ctx, n)) != P3M_OK) return s;
+  const Geo& g = ctx->geo;
+  launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
+  launch_reorder<double>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, st);
+  launch_sort_vector<double>(n, v, ctx->perm, ctx->v_sorted, st);
+  launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
+  const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
+  launch_fill(E.Q, mesh_nodes(g) * sizeof(double), st);
+  launch_deposit<double>(n, E.pp, E.mesh, g, E.Q, st);
+  launch_convolve<double>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, 1, st);
+  launch_fill(ctx->Rm, mesh_nodes(g) * sizeof(double), st);
+  launch_deposit_grad(n, E.pp, E.mesh, ctx->v_sorted, g, ctx->Rm, st);
+  launch_convolve<double>(g, ctx->Rm, E.spec, ctx->ghat, tw, ctx->psi, 1, st);
+  launch_gather_hvp(n, E.pp, E.mesh, ctx->hpp, ctx->v_sorted, ctx->perm, g, ctx->place, E.phi, ctx->psi,
+                    out, st);
+  ctx->last_precision = -1;
+  return P3M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+p3m_status p3m_default_opts(p3m_opts* o) {
+  if (!o) return P3M_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->order = P3M_TSC;
+  o->precision = P3M_FP64;
+  o->zoom = 1;
+  o->ke = 8.9875517923e9;
+  o->q = 1.0;
+  o->m = 1.0;
+  return P3M_OK;
+}
+
+p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], double r_cut,
+                      double split, const p3m_opts* opts) {
+  if (!out || !grid || !h) return P3M_EINVAL;
+  *out = nullptr;
+  p3m_opts o;
+  if (opts) o = *opts;
+  else p3m_default_opts(&o);
+  if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
+  if (o.precision != P3M_FP64 && o.precision != P3M_FP32C) return P3M_EINVAL;
+  if (!(o.m > 0) || !std::isfinite(o.ke) || !std::isfinite(o.q)) return P3M_EINVAL;
+  if (!(r_cut > 0) || !std::isfinite(r_cut) || !(split >= 0) || !std::isfinite(split)) return P3M_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    if (!fft_supported(grid[d])) return P3M_EINVAL;
+    if (!(h[d] > 0) || !std::isfinite(h[d])) return P3M_EINVAL;
+  }
+  p3m_ctx* ctx = new (std::nothrow) p3m_ctx();
+  if (!ctx) return P3M_ENOMEM;
+  ctx->opts = o;
+  ctx->keep_mesh = o.keep_mesh != 0;
+  Geo& g = ctx->geo;
+  g.rc = r_cut;
+  g.kappa = split * r_cut;
+  g.ke_q2 = o.ke * o.q * o.q;
+  g.order = o.order;
+  g.zoom = o.zoom ? 1 : 0;
+  g.ncells = 1;
+  for (int d = 0; d < 3; ++d) {
+    g.grid[d] = grid[d];
+    g.h[d] = h[d];
+    g.hu[d] = h[d] / r_cut;
+    const double span = (grid[d] - 1) * h[d];
+    long long nc = (long long)std::floor(span / r_cut);
+    if (nc < 1) nc = 1;
+    if (nc > 4096) nc = 4096;
+    g.ncell[d] = (int)nc;
+    g.cu[d] = span / (double)nc / r_cut;
+    g.ncells *= nc;
+  }
+  if (g.ncells > (1ll << 31) - 2) {
+    delete ctx;
+    return P3M_EINVAL;
+  }
+  auto bail = [&](p3m_status s) {
+    p3m_destroy(ctx);
+    return s;
+  };
+  hipStream_t st = 0;
+  if (dalloc(&ctx->place, 1) != hipSuccess || dalloc(&ctx->status, 1) != hipSuccess ||
+      dalloc(&ctx->bbox_part, 6 * 1024) != hipSuccess || dalloc(&ctx->acc, 64) != hipSuccess ||
+      dalloc(&ctx->sb.ghist, 4 * 256) != hipSuccess ||
+      dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess)
+    return bail(P3M_ENOMEM);
+  if (hipMemset(ctx->status, 0, sizeof(int)) != hipSuccess) return bail(P3M_EHIP);
+  // Fourier table of the mesh kernel (float64), built once.
+  const size_t oct = (size_t)(grid[0] + 1) * (grid[1] + 1) * (grid[2] + 1);
+  double* scratch = nullptr;
+  double* cosv[3] = {nullptr, nullptr, nullptr};
+  if (dalloc(&ctx->ghat, oct) != hipSuccess || dalloc(&scratch, oct) != hipSuccess) {
+    dfree(scratch);
+    return bail(P3M_ENOMEM);
+  }
+  for (int d = 0; d < 3; ++d) {
+    const int n2 = 2 * grid[d];
+    std::vector<double> c(n2);
+    for (int m = 0; m < n2; ++m) c[m] = std::cos(M_PI * (double)m / (double)grid[d]);
+    if (dalloc(&cosv[d], (size_t)n2) != hipSuccess ||
+        hipMemcpy(cosv[d], c.data(), n2 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      for (int k = 0; k <= d; ++k) dfree(cosv[k]);
+      dfree(scratch);
+      return bail(P3M_ENOMEM);
+    }
+  }
+  build_green_table(g, ctx->ghat, scratch, cosv, st);
+  hipError_t e = hipStreamSynchronize(st);
+  for (int d = 0; d < 3; ++d) dfree(cosv[d]);
+  dfree(scratch);
+  if (e != hipSuccess) return bail(P3M_EHIP);
+  *out = ctx;
+  return P3M_OK;
+}
+
+p3m_status p3m_forces_ex(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, double* f_pp,
+                         double* f_pm, const double* place_in, double* place_out, void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  if (n < 0 || (n > 0 && !x)) return fail(ctx, P3M_EINVAL, "bad particle arguments");
+  ctx->force_cached = false;
+  if (n == 0) return P3M_OK;
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if ((s = ensure_capacity(ctx, n)) != P3M_OK) return s;
+  place(ctx, n, x, place_in, place_out, st);
+  GatherOut out{nullptr, f_pp, f_pm, nullptr, 0.0};
+  if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
+  return check_last(ctx);
+}
+
+p3m_status p3m_forces(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, double* f, void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !f))) return fail(ctx, P3M_EINVAL, "bad particle arguments");
+  ctx->force_cached = false;
+  if (n == 0) return P3M_OK;
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if ((s = ensure_capacity(ctx, n)) != P3M_OK) return s;
+  place(ctx, n, x, nullptr, nullptr, st);
+  GatherOut out{f, nullptr, nullptr, nullptr, 0.0};
+  if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
+  return check_last(ctx);
+}
+
+p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double* qw, double dt,
+                    int32_t nsteps, int32_t reuse_force, const double* place_replay,
+                    double* place_record, void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  if (n < 0 || nsteps < 0 || !std::isfinite(dt) || (n > 0 && (!x || !p)))
+    return fail(ctx, P3M_EINVAL, "bad step arguments");
+  if (n == 0) return P3M_OK;
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if ((s = ensure_capacity(ctx, n)) != P3M_OK) return s;
+  if (reuse_force) {
+    if (!ctx->force_cached || ctx->cached_x != x || ctx->cached_n != n)
+      return fail(ctx, P3M_ESTATE, "no cached force for these positions");
+    if (place_record || place_replay)
+      return fail(ctx, P3M_EINVAL, "placement record/replay needs a fresh start force");
+  } else {
+    place(ctx, n, x, place_replay, place_record, st);
+    GatherOut out{ctx->fcache, nullptr, nullptr, nullptr, 0.0};
+    if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
+  }
+  const double inv_m = 1.0 / ctx->opts.m;
+  const int nb = bbox_blocks(n);
+  for (int k = 0; k < nsteps; ++k) {
+    const size_t off = (size_t)P3M_PLACEMENT_DOUBLES * (k + 1);
+    launch_kick_drift_bbox(n, x, p, ctx->fcache, dt, inv_m, ctx->bbox_part, nb, ctx->status, st);
+    launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_replay ? place_replay + off : nullptr,
+                          ctx->place, place_record ? place_record + off : nullptr, ctx->status, st);
+    GatherOut out{ctx->fcache, nullptr, nullptr, p, 0.5 * dt};
+    if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
+  }
+  ctx->force_cached = true;
+  ctx->cached_x = x;
+  ctx->cached_n = n;
+  return check_last(ctx);
+}
+
+p3m_status p3m_hvp(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, const double* v,
+                   const double* place_in, double* out, void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !v || !out))) return fail(ctx, P3M_EINVAL, "bad hvp arguments");
+  ctx->force_cached = false;
+  if (n == 0) return P3M_OK;
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if ((s = ensure_capacity(ctx, n)) != P3M_OK) return s;
+  place(ctx, n, x, place_in, nullptr, st);
+  if ((s = hvp_core(ctx, n, x, qw, v, out, st)) != P3M_OK) return s;
+  return check_last(ctx);
+}
+
+p3m_status p3m_backward(p3m_ctx* ctx, int64_t n, const double* x_n, const double* x_np1, const double* qw,
+                        const double* xbar_np1, const double* pbar_np1, double* xbar_n, double* pbar_n,
+                        double dt, const double* place_n, const double* place_np1, void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  if (n < 0 || !std::isfinite(dt) ||
+      (n > 0 && (!x_n || !x_np1 || !xbar_np1 || !pbar_np1 || !xbar_n || !pbar_n)))
+    return fail(ctx, P3M_EINVAL, "bad backward arguments");
+  ctx->force_cached = false;
+  if (n == 0) return P3M_OK;
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if ((s = ensure_capacity(ctx, n)) != P3M_OK) return s;
+  if ((s = ensure_adjoint(ctx, n)) != P3M_OK) return s;
+  const size_t bytes = (size_t)3 * n * sizeof(double);
+  // xb = xbar_np1 + dt/2 H(x_np1) pbar_np1
+  place(ctx, n, x_np1, place_np1, nullptr, st);
+  if ((s = hvp_core(ctx, n, x_np1, qw, pbar_np1, ctx->hv, st)) != P3M_OK) return s;
+  HIPCHK(hipMemcpyAsync(ctx->xb, xbar_np1, bytes, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(ctx->pb, pbar_np1, bytes, hipMemcpyDeviceToDevice, st));
+  launch_kick(n, ctx->xb, ctx->hv, dt, st);                  // xb += dt/2 hv
+  // pb += dt/m xb  (a kick with 'force' xb and step 2 dt/m)
+  launch_kick(n, ctx->pb, ctx->xb, 2.0 * dt / ctx->opts.m, st);
+  // xbar_n = xb + dt/2 H(x_n) pb
+  place(ctx, n, x_n, place_n, nullptr, st);
+  if ((s = hvp_core(ctx, n, x_n, qw, ctx->pb, ctx->hv, st)) != P3M_OK) return s;
+  launch_kick(n, ctx->xb, ctx->hv, dt, st);
+  HIPCHK(hipMemcpyAsync(xbar_n, ctx->xb, bytes, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(pbar_n, ctx->pb, bytes, hipMemcpyDeviceToDevice, st));
+  return check_last(ctx);
+}
+
+p3m_status p3m_diagnostics(p3m_ctx* ctx, int64_t n, const double* x, const double* p, const double* qw,
+                           p3m_diag* out, void* stream) {
+  if (!ctx || !out) return P3M_EINVAL;
+  if (n < 1 || !x || !p) return fail(ctx, P3M_EINVAL, "bad diagnostics arguments");
+  ctx->force_cached = false;
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if ((s = ensure_capacity(ctx, n)) != P3M_OK) return s;
+  launch_fill(ctx->acc, 64 * sizeof(double), st);
+  place(ctx, n, x, nullptr, nullptr, st);
+  GatherOut go{nullptr, nullptr, nullptr, nullptr, 0.0};
+  if ((s = evaluate_any(ctx, n, x, qw, go, ctx->acc + 40, ctx->acc + 41, st)) != P3M_OK) return s;
+  launch_moments(n, x, p, qw, ctx->acc, 0, st);
+  launch_moments(n, x, p, qw, ctx->acc, 1, st);
+  double h[64];
+  Place P;
+  HIPCHK(hipMemcpyAsync(h, ctx->acc, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&P, ctx->place, sizeof(P), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double inv_n = 1.0 / (double)n;
+  const double m = ctx->opts.m;
+  for (int d = 0; d < 3; ++d) {
+    out->momentum[d] = h[d];
+    out->mean[d] = h[4 + d] * inv_n;
+    const double sxx = h[16 + d] * inv_n, spp = h[19 + d] * inv_n, sxp = h[22 + d] * inv_n;
+    out->rms[d] = std::sqrt(sxx);
+    const double e2 = sxx * spp - sxp * sxp;
+    out->emit_n[d] = std::sqrt(e2 > 0 ? e2 : 0.0) / (m * kCLight);
+  }
+  out->kinetic = h[3] / (2.0 * m);
+  // energies: internal units times k_e q^2 / Lu
+  const double escale = ctx->geo.ke_q2 * P.inv_lu;
+  out->u_pp = h[40] * escale;
+  out->u_pm = h[41] * escale;
+  out->zoom = P.s;
+  out->charge = h[7];
+  return P3M_OK;
+}
+
+p3m_status p3m_mesh(p3m_ctx* ctx, int32_t which, double* out, void* stream) {
+  if (!ctx || !out || (which != 0 && which != 1)) return P3M_EINVAL;
+  if (ctx->last_precision < 0) return fail(ctx, P3M_ESTATE, "no force evaluation yet");
+  if (which == 0 && !ctx->keep_mesh)
+    return fail(ctx, P3M_ESTATE, "the charge mesh is cleared by the transform unless keep_mesh is set");
+  hipStream_t st = (hipStream_t)stream;
+  if (ctx->last_precision == P3M_FP32C)
+    launch_mesh_export<float>(ctx->geo, which ? ctx->e32.phi : ctx->e32.Q, ctx->place, which, out, st);
+  else
+    launch_mesh_export<double>(ctx->geo, which ? ctx->e64.phi : ctx->e64.Q, ctx->place, which, out, st);
+  return check_last(ctx);
+}
+
+p3m_status p3m_status_sync(p3m_ctx* ctx, void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, ctx->status, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h) {
+    launch_fill(ctx->status, sizeof(int), st);
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  if (h & kBitNonFinite) return fail(ctx, P3M_ENONFINITE, "non-finite particle position");
+  if (h & kBitDomain) return fail(ctx, P3M_EDOMAIN, "particle outside the mesh (zoom disabled or replayed placement)");
+  return P3M_OK;
+}
+
+p3m_status p3m_info(const p3m_ctx* ctx, int64_t out[8]) {
+  if (!ctx || !out) return P3M_EINVAL;
+  out[0] = sort_passes(ctx->geo.ncells);
+  out[1] = ctx->geo.ncells;
+  out[2] = ctx->geo.ncell[0];
+  out[3] = ctx->geo.ncell[1];
+  out[4] = ctx->geo.ncell[2];
+  out[5] = 2 * ctx->geo.grid[0];
+  out[6] = 2 * ctx->geo.grid[1];
+  out[7] = 2 * ctx->geo.grid[2];
+  return P3M_OK;
+}
+
+const char* p3m_last_error(const p3m_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+void p3m_destroy(p3m_ctx* ctx) {
+  if (!ctx) return;
+  engine_free(ctx->e32);
+  engine_free(ctx->e64);
+  dfree(ctx->sb.keys_a);
+  dfree(ctx->sb.vals_a);
+  dfree(ctx->sb.keys_b);
+  dfree(ctx->sb.vals_b);
+  dfree(ctx->sb.counts);
+  dfree(ctx->sb.ghist);
+  dfree(ctx->sb.cell_start);
+  dfree(ctx->place);
+  dfree(ctx->status);
+  dfree(ctx->bbox_part);
+  dfree(ctx->acc);
+  dfree(ctx->ghat);
+  dfree(ctx->fcache);
+  dfree(ctx->v_sorted);
+  dfree(ctx->hpp);
+  dfree(ctx->hv);
+  dfree(ctx->xb);
+  dfree(ctx->pb);
+  dfree(ctx->Rm);
+  dfree(ctx->psi);
+  delete ctx;
+}
+
+}  // extern "C"

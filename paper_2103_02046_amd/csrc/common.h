@@ -1,0 +1,86 @@
+// Internal definitions shared by the HIP sources of libp3m (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace p3m {
+
+// Error bits of the device status word.
+constexpr int kBitDomain = 1;     // a particle outside the mesh with zoom off
+constexpr int kBitNonFinite = 2;  // a non-finite position
+
+constexpr int kThreads = 256;     // block size of the particle kernels
+
+// Placement of one evaluation, written on the device by the finalize kernel.
+// Lengths inside the kernels are measured in the unit Lu = s * r_c, in which
+// the cutoff is 1, the Ewald parameter is kappa = a * r_c and the PP cell and
+// mesh spacings are zoom-invariant constants; physical forces are the
+// internal ones times fscale = k_e q^2 / Lu^2.
+struct Place {
+  double x0[3];        // position of mesh node 0 (m)
+  double s;            // zoom
+  double inv_hp[3];    // 1 / (s h_d)
+  double inv_lu;       // 1 / (s r_c)
+  double inv_cell[3];  // 1 / (s c_d), c_d = PP cell edge at zoom 1
+  double fscale;       // k_e q^2 / (s r_c)^2
+  double phiscale;     // 1 / (s r_c): internal potential -> 1/m
+  double pad[3];
+};
+static_assert(sizeof(Place) == 16 * sizeof(double), "Place layout");
+
+// Zoom-invariant geometry, passed by value.
+struct Geo {
+  int grid[3];         // mesh nodes per axis
+  int ncell[3];        // PP cells per axis
+  long long ncells;    // product of ncell
+  double h[3];         // mesh spacing at zoom 1 (m)
+  double rc;           // cutoff at zoom 1 (m)
+  double hu[3];        // h_d / r_c
+  double cu[3];        // c_d / r_c (PP cell edge in units of the cutoff)
+  double kappa;        // a * r_c
+  double ke_q2;        // k_e q^2
+  int order;           // 1 CIC, 2 TSC
+  int zoom;            // 1 zoom on
+};
+
+template <typename T>
+struct C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> cconj(C2<T> a) { return {a.x, -a.y}; }
+// multiply by -i
+template <typename T>
+__device__ __forceinline__ C2<T> cmul_mi(C2<T> a) { return {a.y, -a.x}; }
+
+// Sorted particle records.
+template <typename R> struct PPRec;              // position in the own PP cell + weight
+template <> struct alignas(16) PPRec<float> { float x, y, z, w; };
+template <> struct alignas(32) PPRec<double> { double x, y, z, w; };
+
+template <typename R> struct MeshRec;            // stencil origin node + fractional offsets
+template <> struct alignas(16) MeshRec<float> { float fx, fy, fz; int base; };
+template <> struct alignas(32) MeshRec<double> { double fx, fy, fz; long long base; };
+
+__host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Floor of a double clamped to [lo, hi] in floating point first, so NaN and
+// huge values map into range before the integer conversion.
+__device__ __forceinline__ int floor_clamp(double v, int lo, int hi) {
+  double f = floor(v);
+  f = fmax(f, (double)lo);
+  f = fmin(f, (double)hi);
+  return (int)f;
+}
+
+}  // namespace p3m

@@ -1,0 +1,418 @@
+// Open-boundary convolution phi = G (x) Q on the mesh by FFT on the doubled
+// mesh (zero padding), and the Fourier table of G.
+//
+// The long-range potential is the finite convolution of the mesh charge with
+// the long-range kernel (Sec. 3, eq. phi_L); with free-space boundaries
+// (Sec. 2.1, eq. free_gf) and the Gaussian screening of Sec. 2.2 folded into
+// the kernel, G(delta) = erf(kappa rho)/rho sampled at the node offsets,
+// G(0) = 2 kappa / sqrt(pi). The charge occupies N nodes per axis, so every
+// offset that matters lies in [-(N-1), N-1] and a cyclic convolution on 2N
+// nodes per axis reproduces the aperiodic one exactly.
+//
+// Passes (L_d = 2 N_d; forward transforms e^{-2 pi i k n / L}):
+//   x: real lines of N_x charges, two lines packed as one complex line,
+//      zero-padded to L_x, split into two half spectra (k_x = 0..N_x);
+//   y: for every (z < N_z, k_x): N_y inputs, L_y outputs;
+//   z: for every (k_y, k_x): N_z inputs -> L_z -> times the real, even Ghat
+//      -> inverse -> keep z < N_z  (the full spectrum never reaches memory);
+//   y inverse: keep y < N_y;  x inverse: two half spectra -> two real lines.
+// Each line is transformed in LDS by a Stockham radix-8 (then 4 or 2) FFT;
+// a block holds B lines side by side (point-major), so the strided y and z
+// passes read and write rows of B consecutive k_x values.
+// The inverse is conj(FFT(conj(.))); 1/(L_x L_y L_z) is folded into Ghat.
+#include <cmath>
+#include <vector>
+
+#include "launch.h"
+
+namespace p3m {
+
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kLdsBytes = 32768;
+
+template <typename T, int L>
+struct Cfg {
+  static constexpr int raw = kLdsBytes / (L * (int)sizeof(C2<T>));
+  static constexpr int B = raw < 1 ? 1 : raw;   // lines per block (power of two)
+};
+
+template <typename T>
+__device__ __forceinline__ void dft2(C2<T>* v) {
+  C2<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(C2<T>* v) {
+  C2<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+  C2<T> a2 = cadd(v[1], v[3]), a3 = cmul_mi(csub(v[1], v[3]));
+  v[0] = cadd(a0, a2);
+  v[2] = csub(a0, a2);
+  v[1] = cadd(a1, a3);
+  v[3] = csub(a1, a3);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft8(C2<T>* v) {
+  C2<T> e[4] = {v[0], v[2], v[4], v[6]};
+  C2<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e);
+  dft4(o);
+  const T c = (T)0.70710678118654752440;
+  // multiply o[k] by e^{-2 pi i k / 8}
+  C2<T> o1 = {c * (o[1].x + o[1].y), c * (o[1].y - o[1].x)};
+  C2<T> o2 = cmul_mi(o[2]);
+  C2<T> o3 = {c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y)};
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dftR(C2<T>* v) {
+  if constexpr (R == 8) dft8(v);
+  else if constexpr (R == 4) dft4(v);
+  else if constexpr (R == 2) dft2(v);
+}
+
+// One Stockham stage: radix R, Ns = product of the radices already applied.
+// Element j + r L/R of every line is read, twiddled by w_{Ns R}^{r (j mod Ns)},
+// transformed, and written to (j / Ns) Ns R + (j mod Ns) + r Ns.
+template <typename T, int L, int B, int Ns, int R>
+__device__ __forceinline__ void fft_stage(C2<T>* s, const C2<T>* __restrict__ tw) {
+  constexpr int NBF = B * (L / R);
+  constexpr int PER = (NBF + kFftThreads - 1) / kFftThreads;
+  C2<T> v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int t = tid + it * kFftThreads;
+    if (NBF % kFftThreads == 0 || t < NBF) {
+      const int b = t % B, jj = t / B;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = s[(jj + r * (L / R)) * B + b];
+      if constexpr (Ns > 1) {
+        const int k = jj % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], tw[r * k * (L / (Ns * R))]);
+      }
+      dftR<T, R>(v[it]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int t = tid + it * kFftThreads;
+    if (NBF % kFftThreads == 0 || t < NBF) {
+      const int b = t % B, jj = t / B;
+      const int k = jj % Ns;
+      const int base = (jj / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[(base + r * Ns) * B + b] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, int B, int Ns = 1>
+__device__ __forceinline__ void fft_lines(C2<T>* s, const C2<T>* __restrict__ tw) {
+  if constexpr (Ns < L) {
+    constexpr int rem = L / Ns;
+    constexpr int R = rem >= 8 ? 8 : rem;
+    fft_stage<T, L, B, Ns, R>(s, tw);
+    fft_lines<T, L, B, Ns * R>(s, tw);
+  }
+}
+
+// ---- x pass, forward: two real rows -> one complex line -> two half spectra
+template <typename T, int L>
+__global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, T* __restrict__ Q,
+                                                           C2<T>* __restrict__ S,
+                                                           const C2<T>* __restrict__ tw, int clearQ) {
+  constexpr int B = Cfg<T, L>::B;
+  constexpr int N = L / 2, K = N + 1;
+  __shared__ C2<T> s[L * B];
+  const int ny = geo.grid[1];
+  const long long rows = (long long)ny * geo.grid[2];
+  const long long row0 = (long long)blockIdx.x * (2 * B);
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) s[e] = C2<T>{(T)0, (T)0};
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * B * N; e += kFftThreads) {
+    const int r = e / N, p = e % N;
+    const long long gr = row0 + r;
+    if (gr < rows) {
+      T v = Q[gr * N + p];
+      if (clearQ) Q[gr * N + p] = (T)0;
+      if (r & 1) s[p * B + (r >> 1)].y = v;
+      else s[p * B + (r >> 1)].x = v;
+    }
+  }
+  __syncthreads();
+  fft_lines<T, L, B>(s, tw);
+  for (int e = threadIdx.x; e < 2 * B * K; e += kFftThreads) {
+    const int r = e / K, k = e % K;
+    const long long gr = row0 + r;
+    if (gr >= rows) continue;
+    const int l = r >> 1;
+    const C2<T> z = s[k * B + l], zm = s[((L - k) & (L - 1)) * B + l];
+    C2<T> o;
+    if (r & 1) o = C2<T>{(T)0.5 * (z.y + zm.y), (T)-0.5 * (z.x - zm.x)};   // (Z - conj Zm) / 2i
+    else o = C2<T>{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};          // (Z + conj Zm) / 2
+    const long long z_ = gr / ny, y = gr % ny;
+    S[(z_ * 2 * ny + y) * K + k] = o;
+  }
+}
+
+// ---- y pass: lines over y for fixed (z, kx); INV: inverse, keep y < N_y
+template <typename T, int L, bool INV>
+__global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restrict__ S,
+                                                       const C2<T>* __restrict__ tw) {
+  constexpr int B = Cfg<T, L>::B;
+  constexpr int N = L / 2;
+  __shared__ C2<T> s[L * B];
+  const int K = geo.grid[0] + 1;
+  const int nch = (K + B - 1) / B;
+  const int z = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
+  C2<T>* base = S + (long long)z * L * K;
+  const int nin = INV ? L : N;
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+    const int p = e / B, b = e % B;
+    C2<T> v{(T)0, (T)0};
+    if (p < nin && kx0 + b < K) v = base[(long long)p * K + kx0 + b];
+    if (INV) v.y = -v.y;
+    s[e] = v;
+  }
+  __syncthreads();
+  fft_lines<T, L, B>(s, tw);
+  const int nout = INV ? N : L;
+  for (int e = threadIdx.x; e < nout * B; e += kFftThreads) {
+    const int p = e / B, b = e % B;
+    if (kx0 + b < K) {
+      C2<T> v = s[e];
+      if (INV) v.y = -v.y;
+      base[(long long)p * K + kx0 + b] = v;
+    }
+  }
+}
+
+// ---- z pass: forward, times Ghat, inverse, keep z < N_z
+template <typename T, int L>
+__global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restrict__ S,
+                                                       const double* __restrict__ ghat,
+                                                       const C2<T>* __restrict__ tw) {
+  constexpr int B = Cfg<T, L>::B;
+  constexpr int N = L / 2;
+  __shared__ C2<T> s[L * B];
+  const int K = geo.grid[0] + 1;
+  const int ly = 2 * geo.grid[1];
+  const int nch = (K + B - 1) / B;
+  const int ky = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
+  const long long zstride = (long long)ly * K;
+  C2<T>* base = S + (long long)ky * K;
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+    const int p = e / B, b = e % B;
+    C2<T> v{(T)0, (T)0};
+    if (p < N && kx0 + b < K) v = base[p * zstride + kx0 + b];
+    s[e] = v;
+  }
+  __syncthreads();
+  fft_lines<T, L, B>(s, tw);
+  const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
+  const long long gplane = (long long)(geo.grid[1] + 1) * K;
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+    const int kz = e / B, b = e % B;
+    const int kzp = kz <= N ? kz : L - kz;
+    const int kx = kx0 + b < K ? kx0 + b : K - 1;
+    const T g = (T)ghat[kzp * gplane + (long long)kyp * K + kx];
+    C2<T> v = s[e];
+    s[e] = C2<T>{g * v.x, -(g * v.y)};   // conj(g Z): input of the inverse
+  }
+  __syncthreads();
+  fft_lines<T, L, B>(s, tw);
+  for (int e = threadIdx.x; e < N * B; e += kFftThreads) {
+    const int p = e / B, b = e % B;
+    if (kx0 + b < K) {
+      C2<T> v = s[e];
+      base[p * zstride + kx0 + b] = C2<T>{v.x, -v.y};
+    }
+  }
+}
+
+// ---- x pass, inverse: two half spectra -> one complex line -> two real rows
+template <typename T, int L>
+__global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(Geo geo, const C2<T>* __restrict__ S,
+                                                           T* __restrict__ phi,
+                                                           const C2<T>* __restrict__ tw) {
+  constexpr int B = Cfg<T, L>::B;
+  constexpr int N = L / 2, K = N + 1;
+  __shared__ C2<T> s[L * B];
+  const int ny = geo.grid[1];
+  const long long rows = (long long)ny * geo.grid[2];
+  const long long row0 = (long long)blockIdx.x * (2 * B);
+  for (int e = threadIdx.x; e < B * K; e += kFftThreads) {
+    const int l = e / K, k = e % K;
+    const long long ga = row0 + 2 * l, gc = ga + 1;
+    C2<T> A{(T)0, (T)0}, C{(T)0, (T)0};
+    if (ga < rows) A = S[((ga / ny) * 2 * ny + ga % ny) * K + k];
+    if (gc < rows) C = S[((gc / ny) * 2 * ny + gc % ny) * K + k];
+    // Z_k = A_k + i C_k ; stored conjugated (input of the inverse)
+    s[k * B + l] = C2<T>{A.x - C.y, -(A.y + C.x)};
+    if (k > 0 && k < N) s[(L - k) * B + l] = C2<T>{A.x + C.y, -(C.x - A.y)};
+  }
+  __syncthreads();
+  fft_lines<T, L, B>(s, tw);
+  for (int e = threadIdx.x; e < 2 * B * N; e += kFftThreads) {
+    const int r = e / N, p = e % N;
+    const long long gr = row0 + r;
+    if (gr >= rows) continue;
+    const C2<T> v = s[p * B + (r >> 1)];
+    phi[gr * N + p] = (r & 1) ? -v.y : v.x;
+  }
+}
+
+// ---- Fourier table of the sampled kernel (float64) -------------------------
+
+__global__ void k_green_sample(Geo geo, double* __restrict__ g) {
+  const int kx = geo.grid[0] + 1, ky = geo.grid[1] + 1, kz = geo.grid[2] + 1;
+  const long long total = (long long)kx * ky * kz;
+  const long long e = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (e >= total) return;
+  const int ix = (int)(e % kx), iy = (int)((e / kx) % ky), iz = (int)(e / ((long long)kx * ky));
+  const double rx = ix * geo.hu[0], ry = iy * geo.hu[1], rz = iz * geo.hu[2];
+  const double rho = sqrt(rx * rx + ry * ry + rz * rz);
+  g[e] = rho == 0.0 ? 1.12837916709551257390 * geo.kappa : erf(geo.kappa * rho) / rho;
+}
+
+// Even extension to 2N points, transformed along one axis: a cosine sum
+//   out[k] = sum_{d=0}^{N} c_d in[d] cos(pi k d / N),  c_0 = c_N = 1, else 2.
+__global__ void k_green_dct(int axis, Geo geo, const double* __restrict__ in, double* __restrict__ out,
+                            const double* __restrict__ cosv, double scale) {
+  const int kx = geo.grid[0] + 1, ky = geo.grid[1] + 1, kz = geo.grid[2] + 1;
+  const long long total = (long long)kx * ky * kz;
+  const long long e = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (e >= total) return;
+  const int ext[3] = {kx, ky, kz};
+  const long long stride[3] = {1, kx, (long long)kx * ky};
+  const int n = geo.grid[axis];
+  const int idx[3] = {(int)(e % kx), (int)((e / kx) % ky), (int)(e / ((long long)kx * ky))};
+  const int k = idx[axis];
+  const long long line = e - (long long)k * stride[axis];
+  double acc = 0.0;
+  for (int d = 0; d <= n; ++d) {
+    const double c = (d == 0 || d == n) ? 1.0 : 2.0;
+    acc += c * in[line + d * stride[axis]] * cosv[((long long)k * d) % (2 * n)];
+  }
+  out[e] = acc * scale;
+  (void)ext;
+}
+
+inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+template <typename T, int L>
+void run_x_fwd(const Geo& g, T* Q, C2<T>* S, const C2<T>* tw, int clear, hipStream_t st) {
+  constexpr int B = Cfg<T, L>::B;
+  long long rows = (long long)g.grid[1] * g.grid[2];
+  unsigned blocks = (unsigned)((rows + 2 * B - 1) / (2 * B));
+  k_fft_x_fwd<T, L><<<blocks, kFftThreads, 0, st>>>(g, Q, S, tw, clear);
+}
+template <typename T, int L>
+void run_x_inv(const Geo& g, const C2<T>* S, T* phi, const C2<T>* tw, hipStream_t st) {
+  constexpr int B = Cfg<T, L>::B;
+  long long rows = (long long)g.grid[1] * g.grid[2];
+  unsigned blocks = (unsigned)((rows + 2 * B - 1) / (2 * B));
+  k_fft_x_inv<T, L><<<blocks, kFftThreads, 0, st>>>(g, S, phi, tw);
+}
+template <typename T, int L, bool INV>
+void run_y(const Geo& g, C2<T>* S, const C2<T>* tw, hipStream_t st) {
+  constexpr int B = Cfg<T, L>::B;
+  int K = g.grid[0] + 1;
+  unsigned blocks = (unsigned)(g.grid[2] * ((K + B - 1) / B));
+  k_fft_y<T, L, INV><<<blocks, kFftThreads, 0, st>>>(g, S, tw);
+}
+template <typename T, int L>
+void run_z(const Geo& g, C2<T>* S, const double* ghat, const C2<T>* tw, hipStream_t st) {
+  constexpr int B = Cfg<T, L>::B;
+  int K = g.grid[0] + 1;
+  unsigned blocks = (unsigned)(2 * g.grid[1] * ((K + B - 1) / B));
+  k_fft_z<T, L><<<blocks, kFftThreads, 0, st>>>(g, S, ghat, tw);
+}
+
+#define P3M_FFT_SWITCH(L_, CALL) \
+  switch (L_) {                  \
+    case 8: CALL(8); break;      \
+    case 16: CALL(16); break;    \
+    case 32: CALL(32); break;    \
+    case 64: CALL(64); break;    \
+    case 128: CALL(128); break;  \
+    case 256: CALL(256); break;  \
+    case 512: CALL(512); break;  \
+    case 1024: CALL(1024); break;\
+    case 2048: CALL(2048); break;\
+    default: break;              \
+  }
+
+}  // namespace
+
+bool fft_supported(int nodes) {
+  return nodes >= 4 && nodes <= 1024 && (nodes & (nodes - 1)) == 0;
+}
+
+size_t spectrum_elems(const Geo& g) {
+  return (size_t)g.grid[2] * 2 * g.grid[1] * (g.grid[0] + 1);
+}
+
+template <typename R>
+void launch_convolve(const Geo& g, R* Q, C2<R>* S, const double* ghat, const C2<R>* tw[3], R* phi,
+                     int clearQ, hipStream_t st) {
+  const int Lx = 2 * g.grid[0], Ly = 2 * g.grid[1], Lz = 2 * g.grid[2];
+#define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], clearQ, st)
+#define YF(L) run_y<R, L, false>(g, S, tw[1], st)
+#define ZZ(L) run_z<R, L>(g, S, ghat, tw[2], st)
+#define YI(L) run_y<R, L, true>(g, S, tw[1], st)
+#define XI(L) run_x_inv<R, L>(g, S, phi, tw[0], st)
+  P3M_FFT_SWITCH(Lx, XF)
+  P3M_FFT_SWITCH(Ly, YF)
+  P3M_FFT_SWITCH(Lz, ZZ)
+  P3M_FFT_SWITCH(Ly, YI)
+  P3M_FFT_SWITCH(Lx, XI)
+#undef XF
+#undef YF
+#undef ZZ
+#undef YI
+#undef XI
+}
+
+template <typename R>
+void make_twiddles(int L, C2<R>* out) {
+  for (int k = 0; k < L; ++k) {
+    const double a = -2.0 * M_PI * (double)k / (double)L;
+    out[k] = C2<R>{(R)std::cos(a), (R)std::sin(a)};
+  }
+}
+
+void build_green_table(const Geo& g, double* table, double* scratch, double* const cosv[3],
+                       hipStream_t st) {
+  const long long total = (long long)(g.grid[0] + 1) * (g.grid[1] + 1) * (g.grid[2] + 1);
+  const double scale = 1.0 / (8.0 * g.grid[0] * g.grid[1] * g.grid[2]);
+  k_green_sample<<<blocks_for(total), kThreads, 0, st>>>(g, scratch);
+  k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(0, g, scratch, table, cosv[0], 1.0);
+  k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(1, g, table, scratch, cosv[1], 1.0);
+  k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(2, g, scratch, table, cosv[2], scale);
+}
+
+template void launch_convolve<float>(const Geo&, float*, C2<float>*, const double*, const C2<float>*[3],
+                                     float*, int, hipStream_t);
+template void launch_convolve<double>(const Geo&, double*, C2<double>*, const double*,
+                                      const C2<double>*[3], double*, int, hipStream_t);
+template void make_twiddles<float>(int, C2<float>*);
+template void make_twiddles<double>(int, C2<double>*);
+
+}  // namespace p3m

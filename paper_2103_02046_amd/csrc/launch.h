@@ -1,0 +1,93 @@
+// Host-side launchers of the libp3m kernels (internal).
+#pragma once
+
+#include "common.h"
+
+namespace p3m {
+
+// ---- placement and push (placement.hip) -----------------------------------
+int bbox_blocks(int64_t n);
+void launch_bbox(int64_t n, const double* x, double* part, int nblk, int* status, hipStream_t st);
+void launch_kick_drift_bbox(int64_t n, double* x, double* p, const double* f, double dt,
+                            double inv_m, double* part, int nblk, int* status, hipStream_t st);
+void launch_kick(int64_t n, double* p, const double* f, double dt, hipStream_t st);
+void launch_place_finalize(int nblk, const double* part, const Geo& geo, const double* place_in,
+                           Place* out, double* place_out, int* status, hipStream_t st);
+
+// ---- linked cells (sort.hip) ----------------------------------------------
+struct SortBufs {
+  uint32_t *keys_a, *vals_a, *keys_b, *vals_b;
+  int* counts;      // [256][nblocks]
+  int* ghist;       // [passes][256]
+  int* cell_start;  // [ncells + 1]
+};
+int sort_passes(long long ncells);
+int sort_blocks(int64_t n);
+// Sorts particles by PP cell; on return *keys/*perm point at the sorted arrays.
+void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b,
+                      uint32_t** keys, uint32_t** perm, hipStream_t st);
+template <typename R>
+void launch_reorder(int64_t n, const double* x, const double* qw, const uint32_t* perm,
+                    const uint32_t* keys, const Place* pl, const Geo& geo, PPRec<R>* pp,
+                    MeshRec<R>* mesh, int* status, hipStream_t st);
+template <typename R>
+void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out, hipStream_t st);
+
+// ---- pair forces (pp.hip) ------------------------------------------------
+template <typename R>
+void launch_pp(int64_t n, const PPRec<R>* rec, const uint32_t* keys, const int* cell_start,
+               const Geo& geo, PPRec<R>* out, double* energy, hipStream_t st);
+void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
+                   const int* cell_start, const Geo& geo, const double* v_sorted,
+                   double* out_sorted, hipStream_t st);
+
+// ---- mesh assignment (mesh.hip) --------------------------------------------
+template <typename R>
+void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, R* Q,
+                    hipStream_t st);
+// Gather modes: write the total force, the two parts, or (step) total + half kick.
+struct GatherOut {
+  double* f;        // total, caller order (may be NULL)
+  double* f_pp;     // PP part, caller order (may be NULL)
+  double* f_pm;     // PM part, caller order (may be NULL)
+  double* p;        // momenta to kick by half_dt * f (may be NULL)
+  double half_dt;
+};
+template <typename R>
+void launch_gather(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
+                   const uint32_t* perm, const Geo& geo, const Place* pl, const R* phi,
+                   GatherOut out, double* energy, hipStream_t st);
+void launch_deposit_grad(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,
+                         const double* v_sorted, const Geo& geo, double* R, hipStream_t st);
+void launch_gather_hvp(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,
+                       const double* hpp_sorted, const double* v_sorted, const uint32_t* perm,
+                       const Geo& geo, const Place* pl, const double* phi, const double* psi,
+                       double* out, hipStream_t st);
+template <typename R>
+void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale_phi, double* out,
+                        hipStream_t st);
+
+// ---- open-boundary convolution (fft.hip) ------------------------------------
+bool fft_supported(int nodes);
+// Spectrum buffer: complex, grid[2] x 2 grid[1] x (grid[0] + 1).
+size_t spectrum_elems(const Geo& geo);
+// phi = G (x) Q on the mesh (internal units). Q is cleared on the way if clearQ.
+template <typename R>
+void launch_convolve(const Geo& geo, R* Q, C2<R>* spec, const double* ghat, const C2<R>* tw[3],
+                     R* phi, int clearQ, hipStream_t st);
+template <typename R>
+void make_twiddles(int L, C2<R>* host_out);
+// Fourier transform of the sampled kernel erf(kappa rho)/rho on the doubled
+// mesh, divided by the number of doubled-mesh nodes: (grid+1)^3 float64
+// octant [kz][ky][kx]. scratch holds 2 (grid+1)^3 doubles.
+void build_green_table(const Geo& geo, double* table, double* scratch, double* const cosv[3],
+                       hipStream_t st);
+
+// ---- reductions (diag.hip) ------------------------------------------------
+// acc[0..15] += first moments (mode 0) or centred second moments about the
+// means held in acc[16..] (mode 1); see diag.hip for the layout.
+void launch_moments(int64_t n, const double* x, const double* p, const double* qw, double* acc,
+                    int mode, hipStream_t st);
+void launch_fill(void* ptr, size_t bytes, hipStream_t st);
+
+}  // namespace p3m

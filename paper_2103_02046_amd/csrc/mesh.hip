@@ -1,0 +1,285 @@
+// Charge assignment to the mesh and force interpolation back to particles.
+//
+// Assignment weight of node m for a particle at mesh coordinate u is the
+// cardinal B-spline b_p(u - m) per axis (Sec. 2.4.2, eq.
+// interpolation_splines_b0: b1, cloud-in-cell; b2, triangular-shaped cloud,
+// is the next step of the same recursion):
+//   CIC, f = u - floor(u):        w = (1 - f, f)              w' = (-1, 1)
+//   TSC, d = u - round(u):        w = ((1/2-d)^2/2, 3/4-d^2, (1/2+d)^2/2)
+//                                 w' = (-(1/2-d), -2d, 1/2+d)  w'' = (1, -2, 1)
+// Deposit: Q_m = sum_i w_i W_m(x_i)             (Sec. 2.5, eq. eom_p3m_poiss_L)
+// Gather:  F_i = -w_i sum_m phi_m grad W_m(x_i) (Sec. 2.5, eq. eom_p3m_coord),
+//          the weight gradient read as a finite difference of phi at the
+//          nearest nodes (the remark after eq. eom_p3m_coord).
+// Lengths are in the unit Lu = s r_c, so grad = (1/hu_d) d/du with hu = h/r_c.
+#include "launch.h"
+
+namespace p3m {
+
+namespace {
+
+template <typename R, int ORDER>
+struct Stencil {
+  static constexpr int N = ORDER + 1;
+  R w[3][N], dw[3][N];
+  __device__ __forceinline__ Stencil(R fx, R fy, R fz) {
+    const R f[3] = {fx, fy, fz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (ORDER == 1) {
+        w[d][0] = (R)1 - f[d];
+        w[d][1] = f[d];
+        dw[d][0] = (R)-1;
+        dw[d][1] = (R)1;
+      } else {
+        const R a = (R)0.5 - f[d], b = (R)0.5 + f[d];
+        w[d][0] = (R)0.5 * a * a;
+        w[d][1] = (R)0.75 - f[d] * f[d];
+        w[d][N - 1] = (R)0.5 * b * b;
+        dw[d][0] = -a;
+        dw[d][1] = (R)-2 * f[d];
+        dw[d][N - 1] = b;
+      }
+    }
+  }
+};
+
+template <typename R, int ORDER>
+__global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>* __restrict__ pp,
+                                                      const MeshRec<R>* __restrict__ mesh, Geo geo,
+                                                      R* __restrict__ Q) {
+  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= n) return;
+  const MeshRec<R> m = mesh[j];
+  const R q = pp[j].w;
+  Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
+  const int nx = geo.grid[0];
+  const long long nxy = (long long)nx * geo.grid[1];
+#pragma unroll
+  for (int c = 0; c < S.N; ++c)
+#pragma unroll
+    for (int b = 0; b < S.N; ++b) {
+      const R wyz = q * S.w[1][b] * S.w[2][c];
+      R* row = Q + m.base + c * nxy + (long long)b * nx;
+#pragma unroll
+      for (int a = 0; a < S.N; ++a) atomicAdd(row + a, wyz * S.w[0][a]);
+    }
+}
+
+template <typename R, int ORDER>
+__global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPRec<R>* __restrict__ pp,
+                                                     const MeshRec<R>* __restrict__ mesh,
+                                                     const PPRec<R>* __restrict__ fpp,
+                                                     const uint32_t* __restrict__ perm, Geo geo,
+                                                     const Place* __restrict__ pl,
+                                                     const R* __restrict__ phi, GatherOut out,
+                                                     double* __restrict__ energy) {
+  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double e_acc = 0.0;
+  if (j < n) {
+    const MeshRec<R> m = mesh[j];
+    const R q = pp[j].w;
+    Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
+    const int nx = geo.grid[0];
+    const long long nxy = (long long)nx * geo.grid[1];
+    R g[3] = {0, 0, 0};
+    R pot = 0;
+#pragma unroll
+    for (int c = 0; c < S.N; ++c)
+#pragma unroll
+      for (int b = 0; b < S.N; ++b) {
+        const R* row = phi + m.base + c * nxy + (long long)b * nx;
+        R sx = 0, sdx = 0;
+#pragma unroll
+        for (int a = 0; a < S.N; ++a) {
+          const R v = row[a];
+          sx += v * S.w[0][a];
+          sdx += v * S.dw[0][a];
+        }
+        g[0] += sdx * S.w[1][b] * S.w[2][c];
+        g[1] += sx * S.dw[1][b] * S.w[2][c];
+        g[2] += sx * S.w[1][b] * S.dw[2][c];
+        pot += sx * S.w[1][b] * S.w[2][c];
+      }
+    const double fs = pl->fscale;
+    const uint32_t i = perm[j];
+    double fpm[3], fp[3] = {0, 0, 0}, ft[3];
+    const PPRec<R> a = fpp[j];
+    fp[0] = (double)a.x;
+    fp[1] = (double)a.y;
+    fp[2] = (double)a.z;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      fpm[d] = -(double)q * (double)g[d] / geo.hu[d];
+      ft[d] = fs * (fp[d] + fpm[d]);
+    }
+    if (out.f)
+      for (int d = 0; d < 3; ++d) out.f[3 * i + d] = ft[d];
+    if (out.f_pp)
+      for (int d = 0; d < 3; ++d) out.f_pp[3 * i + d] = fs * fp[d];
+    if (out.f_pm)
+      for (int d = 0; d < 3; ++d) out.f_pm[3 * i + d] = fs * fpm[d];
+    if (out.p)
+      for (int d = 0; d < 3; ++d) out.p[3 * i + d] += out.half_dt * ft[d];
+    e_acc = 0.5 * (double)q * (double)pot;
+  }
+  if (energy) {
+    __shared__ double s[kThreads];
+    s[threadIdx.x] = e_acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(energy, s[0]);
+  }
+}
+
+// R_m = sum_j w_j grad W_m(x_j) . v_j (derivative of the deposit along v).
+template <int ORDER>
+__global__ void __launch_bounds__(kThreads) k_deposit_grad(int64_t n, const PPRec<double>* __restrict__ pp,
+                                                           const MeshRec<double>* __restrict__ mesh,
+                                                           const double* __restrict__ v, Geo geo,
+                                                           double* __restrict__ Rm) {
+  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= n) return;
+  const MeshRec<double> m = mesh[j];
+  const double q = pp[j].w;
+  Stencil<double, ORDER> S(m.fx, m.fy, m.fz);
+  const double vx = v[3 * j] / geo.hu[0], vy = v[3 * j + 1] / geo.hu[1], vz = v[3 * j + 2] / geo.hu[2];
+  const int nx = geo.grid[0];
+  const long long nxy = (long long)nx * geo.grid[1];
+  for (int c = 0; c < S.N; ++c)
+    for (int b = 0; b < S.N; ++b)
+      for (int a = 0; a < S.N; ++a) {
+        double val = S.dw[0][a] * S.w[1][b] * S.w[2][c] * vx + S.w[0][a] * S.dw[1][b] * S.w[2][c] * vy +
+                     S.w[0][a] * S.w[1][b] * S.dw[2][c] * vz;
+        atomicAdd(Rm + m.base + c * nxy + (long long)b * nx + a, q * val);
+      }
+}
+
+// out_i = (fscale/Lu) [hpp_i - w_i (sum_m psi_m grad W_m(x_i) + sum_m phi_m (grad grad W_m(x_i)) v_i)]
+// in caller order: the PM part of the Hessian-vector product plus the PP part.
+template <int ORDER>
+__global__ void __launch_bounds__(kThreads) k_gather_hvp(
+    int64_t n, const PPRec<double>* __restrict__ pp, const MeshRec<double>* __restrict__ mesh,
+    const double* __restrict__ hpp, const double* __restrict__ v, const uint32_t* __restrict__ perm,
+    Geo geo, const Place* __restrict__ pl, const double* __restrict__ phi,
+    const double* __restrict__ psi, double* __restrict__ out) {
+  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= n) return;
+  const MeshRec<double> m = mesh[j];
+  const double q = pp[j].w;
+  Stencil<double, ORDER> S(m.fx, m.fy, m.fz);
+  double d2[3][S.N];
+  for (int d = 0; d < 3; ++d)
+    for (int a = 0; a < S.N; ++a) d2[d][a] = ORDER == 1 ? 0.0 : (a == 1 ? -2.0 : 1.0);
+  const int nx = geo.grid[0];
+  const long long nxy = (long long)nx * geo.grid[1];
+  double gpsi[3] = {0, 0, 0};
+  double hess[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int c = 0; c < S.N; ++c)
+    for (int b = 0; b < S.N; ++b)
+      for (int a = 0; a < S.N; ++a) {
+        const long long node = m.base + c * nxy + (long long)b * nx + a;
+        const double ps = psi[node], ph = phi[node];
+        const double W[3] = {S.w[0][a], S.w[1][b], S.w[2][c]};
+        const double D[3] = {S.dw[0][a], S.dw[1][b], S.dw[2][c]};
+        const double E[3] = {d2[0][a], d2[1][b], d2[2][c]};
+        gpsi[0] += ps * D[0] * W[1] * W[2];
+        gpsi[1] += ps * W[0] * D[1] * W[2];
+        gpsi[2] += ps * W[0] * W[1] * D[2];
+        for (int p = 0; p < 3; ++p)
+          for (int r = 0; r < 3; ++r) {
+            double prod = 1.0;
+            for (int e = 0; e < 3; ++e) {
+              if (p == r && e == p) prod *= E[e];
+              else if (e == p || e == r) prod *= D[e];
+              else prod *= W[e];
+            }
+            hess[p][r] += ph * prod;
+          }
+      }
+  const double vj[3] = {v[3 * j], v[3 * j + 1], v[3 * j + 2]};
+  const double scale = pl->fscale * pl->inv_lu;
+  const uint32_t i = perm[j];
+  for (int p = 0; p < 3; ++p) {
+    double acc = gpsi[p] / geo.hu[p];
+    for (int r = 0; r < 3; ++r) acc += hess[p][r] * vj[r] / (geo.hu[p] * geo.hu[r]);
+    out[3 * i + p] = scale * (hpp[3 * j + p] - q * acc);
+  }
+}
+
+template <typename R>
+__global__ void k_mesh_export(long long count, const R* __restrict__ src, const Place* __restrict__ pl,
+                              int scale_phi, double* __restrict__ out) {
+  long long k = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (k >= count) return;
+  double v = (double)src[k];
+  out[k] = scale_phi ? v * pl->phiscale : v;
+}
+
+inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+template <typename R>
+void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, R* Q,
+                    hipStream_t st) {
+  if (geo.order == 1)
+    k_deposit<R, 1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+  else
+    k_deposit<R, 2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+}
+
+template <typename R>
+void launch_gather(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
+                   const uint32_t* perm, const Geo& geo, const Place* pl, const R* phi,
+                   GatherOut out, double* energy, hipStream_t st) {
+  if (geo.order == 1)
+    k_gather<R, 1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
+  else
+    k_gather<R, 2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
+}
+
+void launch_deposit_grad(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,
+                         const double* v_sorted, const Geo& geo, double* Rm, hipStream_t st) {
+  if (geo.order == 1)
+    k_deposit_grad<1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, v_sorted, geo, Rm);
+  else
+    k_deposit_grad<2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, v_sorted, geo, Rm);
+}
+
+void launch_gather_hvp(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,
+                       const double* hpp_sorted, const double* v_sorted, const uint32_t* perm,
+                       const Geo& geo, const Place* pl, const double* phi, const double* psi,
+                       double* out, hipStream_t st) {
+  if (geo.order == 1)
+    k_gather_hvp<1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, hpp_sorted, v_sorted, perm, geo, pl,
+                                                        phi, psi, out);
+  else
+    k_gather_hvp<2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, hpp_sorted, v_sorted, perm, geo, pl,
+                                                        phi, psi, out);
+}
+
+template <typename R>
+void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale_phi, double* out,
+                        hipStream_t st) {
+  long long count = (long long)geo.grid[0] * geo.grid[1] * geo.grid[2];
+  k_mesh_export<R><<<blocks_for(count), kThreads, 0, st>>>(count, src, pl, scale_phi, out);
+}
+
+template void launch_deposit<float>(int64_t, const PPRec<float>*, const MeshRec<float>*, const Geo&,
+                                    float*, hipStream_t);
+template void launch_deposit<double>(int64_t, const PPRec<double>*, const MeshRec<double>*, const Geo&,
+                                     double*, hipStream_t);
+template void launch_gather<float>(int64_t, const PPRec<float>*, const MeshRec<float>*, const PPRec<float>*,
+                                   const uint32_t*, const Geo&, const Place*, const float*, GatherOut,
+                                   double*, hipStream_t);
+template void launch_gather<double>(int64_t, const PPRec<double>*, const MeshRec<double>*,
+                                    const PPRec<double>*, const uint32_t*, const Geo&, const Place*,
+                                    const double*, GatherOut, double*, hipStream_t);
+template void launch_mesh_export<float>(const Geo&, const float*, const Place*, int, double*, hipStream_t);
+template void launch_mesh_export<double>(const Geo&, const double*, const Place*, int, double*, hipStream_t);
+
+}  // namespace p3m

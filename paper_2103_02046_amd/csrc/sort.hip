@@ -1,0 +1,266 @@
+// Linked cells on the device: PP-cell key per particle, a stable LSD radix
+// sort of (key, index) with 8-bit digits, the start of every cell in the
+// sorted order, and the reorder of the particles into sorted records.
+//
+// The paper sums the short-range force over particles "close to" each
+// particle (Sec. 1, eq. summation_short) inside the cutoff; cells of edge
+// >= r_c make the 27 neighbouring cells a superset of that neighbourhood.
+// The cell edge is c_d = (N_d - 1) h_d / n_d with n_d = floor((N_d-1) h_d / r_c),
+// so the cell grid covers exactly the mesh span and zoom leaves n_d unchanged.
+#include "launch.h"
+
+namespace p3m {
+
+namespace {
+
+constexpr int kItems = 16;                 // keys per thread in a radix tile
+constexpr int kTile = kThreads * kItems;   // 4096 keys per block
+constexpr int kWaves = kThreads / 64;
+
+__global__ void __launch_bounds__(kThreads) k_keys(int64_t n, const double* __restrict__ x,
+                                                   const Place* __restrict__ pl, Geo geo,
+                                                   uint32_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals,
+                                                   int* __restrict__ ghist, int nhist) {
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < nhist; k += kThreads) ghist[k] = 0;
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= n) return;
+  const Place P = *pl;
+  int c[3];
+  for (int d = 0; d < 3; ++d)
+    c[d] = floor_clamp((x[3 * i + d] - P.x0[d]) * P.inv_cell[d], 0, geo.ncell[d] - 1);
+  keys[i] = (uint32_t)(((long long)c[2] * geo.ncell[1] + c[1]) * geo.ncell[0] + c[0]);
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kThreads) k_radix_count(int64_t n, const uint32_t* __restrict__ keys,
+                                                          int shift, int* __restrict__ counts,
+                                                          int* __restrict__ ghist, int nb) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kTile;
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  int c = h[threadIdx.x];
+  counts[threadIdx.x * nb + blockIdx.x] = c;
+  if (c) atomicAdd(&ghist[threadIdx.x], c);
+}
+
+// Exclusive scan of 256 values held one per thread; returns the thread's
+// exclusive prefix and writes the block total to *total.
+__device__ inline int block_exclusive_scan(int v, int* total) {
+  __shared__ int s[kThreads];
+  const int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    int add = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int incl = s[t];
+  *total = s[kThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// One block per digit: offsets[d][b] = (keys with a smaller digit) + (keys of
+// digit d in blocks before b). counts is overwritten with the offsets.
+__global__ void __launch_bounds__(kThreads) k_radix_scan(int* __restrict__ counts,
+                                                         const int* __restrict__ ghist, int nb) {
+  const int d = blockIdx.x, t = threadIdx.x;
+  int total;
+  int pre = block_exclusive_scan(ghist[t], &total);
+  __shared__ int base_s;
+  if (t == d) base_s = pre;
+  __syncthreads();
+  int carry = base_s;
+  int* row = counts + (int64_t)d * nb;
+  for (int b0 = 0; b0 < nb; b0 += kThreads) {
+    int v = (b0 + t < nb) ? row[b0 + t] : 0;
+    int ex = block_exclusive_scan(v, &total);
+    if (b0 + t < nb) row[b0 + t] = carry + ex;
+    carry += total;
+  }
+}
+
+// Stable scatter of one tile: keys keep their order within a digit.
+__global__ void __launch_bounds__(kThreads) k_radix_scatter(
+    int64_t n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift,
+    const int* __restrict__ offsets, int nb) {
+  __shared__ int run[256];
+  __shared__ int base[256];
+  __shared__ int wcnt[kWaves][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  run[t] = 0;
+  base[t] = offsets[t * nb + blockIdx.x];
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int64_t tile = (int64_t)blockIdx.x * kTile;
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = tile + k * kThreads + t;
+    const bool valid = i < n;
+    uint32_t key = valid ? kin[i] : 0u;
+    uint32_t val = valid ? vin[i] : 0u;
+    const int d = (int)((key >> shift) & 255u);
+    for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
+    __syncthreads();
+    unsigned long long peers = __ballot(valid);
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool b = (d >> bit) & 1;
+      unsigned long long m = __ballot(b);
+      peers &= b ? m : ~m;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = base[d] + run[d] + rank;
+      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int q = 0; q < kWaves; ++q) add += wcnt[q][t];
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// cell_start[c] = first sorted index with key >= c, for c in [0, ncells].
+__global__ void k_cell_start(int64_t n, const uint32_t* __restrict__ keys, int* __restrict__ cs,
+                             long long ncells) {
+  int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= n) return;
+  long long k = keys[j];
+  long long prev = j ? (long long)keys[j - 1] : -1;
+  for (long long c = prev + 1; c <= k; ++c) cs[c] = (int)j;
+  if (j == n - 1)
+    for (long long c = k + 1; c <= ncells; ++c) cs[c] = (int)n;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_reorder(
+    int64_t n, const double* __restrict__ x, const double* __restrict__ qw,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ keys,
+    const Place* __restrict__ pl, Geo geo, PPRec<R>* __restrict__ pp, MeshRec<R>* __restrict__ mesh,
+    int* __restrict__ status) {
+  int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= n) return;
+  const Place P = *pl;
+  const uint32_t i = perm[j];
+  const uint32_t key = keys[j];
+  const int c[3] = {(int)(key % (uint32_t)geo.ncell[0]),
+                    (int)((key / (uint32_t)geo.ncell[0]) % (uint32_t)geo.ncell[1]),
+                    (int)(key / ((uint32_t)geo.ncell[0] * (uint32_t)geo.ncell[1]))};
+  double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+  const double w = qw ? qw[i] : 1.0;
+  // PP record: offset from the own cell corner in units of the cutoff Lu,
+  // formed in float64 before rounding.
+  PPRec<R> r;
+  r.x = (R)((xi[0] - P.x0[0]) * P.inv_lu - c[0] * geo.cu[0]);
+  r.y = (R)((xi[1] - P.x0[1]) * P.inv_lu - c[1] * geo.cu[1]);
+  r.z = (R)((xi[2] - P.x0[2]) * P.inv_lu - c[2] * geo.cu[2]);
+  r.w = (R)w;
+  pp[j] = r;
+  // Mesh record: stencil origin and fractional offset (Sec. 2.4.2 B-splines).
+  // CIC: base floor(u), offset u - base in [0, 1).
+  // TSC: centre floor(u + 1/2), offset u - centre in [-1/2, 1/2), base centre - 1.
+  int b[3];
+  double f[3];
+  bool out = false;
+  for (int d = 0; d < 3; ++d) {
+    double u = (xi[d] - P.x0[d]) * P.inv_hp[d];
+    if (geo.order == 1) {
+      double fl = floor(u);
+      b[d] = floor_clamp(u, 0, geo.grid[d] - 2);
+      out |= (double)b[d] != fl;
+      f[d] = u - (double)b[d];
+    } else {
+      double fl = floor(u + 0.5);
+      int cc = floor_clamp(u + 0.5, 1, geo.grid[d] - 2);
+      out |= (double)cc != fl;
+      f[d] = u - (double)cc;
+      b[d] = cc - 1;
+    }
+  }
+  if (out) atomicOr(status, kBitDomain);
+  MeshRec<R> m;
+  m.fx = (R)f[0];
+  m.fy = (R)f[1];
+  m.fz = (R)f[2];
+  m.base = ((b[2] * geo.grid[1]) + b[1]) * geo.grid[0] + b[0];
+  mesh[j] = m;
+}
+
+template <typename R>
+__global__ void k_sort_vector(int64_t n, const double* __restrict__ v, const uint32_t* __restrict__ perm,
+                              R* __restrict__ out) {
+  int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= n) return;
+  uint32_t i = perm[j];
+  out[3 * j] = (R)v[3 * i];
+  out[3 * j + 1] = (R)v[3 * i + 1];
+  out[3 * j + 2] = (R)v[3 * i + 2];
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+int sort_passes(long long ncells) {
+  int bits = 1;
+  while ((1ll << bits) < ncells) ++bits;
+  return (bits + 7) / 8;
+}
+
+int sort_blocks(int64_t n) { return (int)((n + kTile - 1) / kTile); }
+
+void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b,
+                      uint32_t** keys, uint32_t** perm, hipStream_t st) {
+  const int passes = sort_passes(geo.ncells);
+  const int nb = sort_blocks(n);
+  k_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_a, b.vals_a, b.ghist, passes * 256);
+  uint32_t *ka = b.keys_a, *va = b.vals_a, *kb = b.keys_b, *vb = b.vals_b;
+  for (int p = 0; p < passes; ++p) {
+    int* gh = b.ghist + p * 256;
+    k_radix_count<<<nb, kThreads, 0, st>>>(n, ka, 8 * p, b.counts, gh, nb);
+    k_radix_scan<<<256, kThreads, 0, st>>>(b.counts, gh, nb);
+    k_radix_scatter<<<nb, kThreads, 0, st>>>(n, ka, va, kb, vb, 8 * p, b.counts, nb);
+    uint32_t* tk = ka; ka = kb; kb = tk;
+    uint32_t* tv = va; va = vb; vb = tv;
+  }
+  k_cell_start<<<blocks_for(n), kThreads, 0, st>>>(n, ka, b.cell_start, geo.ncells);
+  *keys = ka;
+  *perm = va;
+}
+
+template <typename R>
+void launch_reorder(int64_t n, const double* x, const double* qw, const uint32_t* perm,
+                    const uint32_t* keys, const Place* pl, const Geo& geo, PPRec<R>* pp,
+                    MeshRec<R>* mesh, int* status, hipStream_t st) {
+  k_reorder<R><<<blocks_for(n), kThreads, 0, st>>>(n, x, qw, perm, keys, pl, geo, pp, mesh, status);
+}
+
+template <typename R>
+void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out, hipStream_t st) {
+  k_sort_vector<R><<<blocks_for(n), kThreads, 0, st>>>(n, v, perm, out);
+}
+
+template void launch_reorder<float>(int64_t, const double*, const double*, const uint32_t*,
+                                    const uint32_t*, const Place*, const Geo&, PPRec<float>*,
+                                    MeshRec<float>*, int*, hipStream_t);
+template void launch_reorder<double>(int64_t, const double*, const double*, const uint32_t*,
+                                     const uint32_t*, const Place*, const Geo&, PPRec<double>*,
+                                     MeshRec<double>*, int*, hipStream_t);
+template void launch_sort_vector<float>(int64_t, const double*, const uint32_t*, float*, hipStream_t);
+template void launch_sort_vector<double>(int64_t, const double*, const uint32_t*, double*, hipStream_t);
+
+}  // namespace p3m

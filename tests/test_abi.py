@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every symbol include/p3m.h declares
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "p3m.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(p3m_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("p3m_create", "p3m_forces", "p3m_step", "p3m_backward"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2103_02046_amd import p3m
+    lib = ctypes.CDLL(p3m.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(p3m.SYMBOLS) == _declared()
+
+
+def test_default_opts_and_argument_errors_without_gpu():
+    """Calls that touch no device memory: defaults, and arguments rejected
+    before any allocation."""
+    from paper_2103_02046_amd import p3m
+    L = p3m.lib()
+    o = p3m.Opts()
+    assert L.p3m_default_opts(ctypes.byref(o)) == p3m.OK
+    assert (o.order, o.precision, o.zoom, o.keep_mesh) == (p3m.TSC, p3m.FP64, 1, 0)
+    assert o.ke == pytest.approx(8.9875517923e9)
+    assert L.p3m_default_opts(None) == p3m.EINVAL
+    ctx = ctypes.c_void_p()
+    for grid, h, rc, a in [((12, 16, 16), (1, 1, 1), 1.0, 1.0),    # not a power of two
+                           ((16, 16, 2048), (1, 1, 1), 1.0, 1.0),  # too large
+                           ((16, 16, 16), (1, 0, 1), 1.0, 1.0),    # h <= 0
+                           ((16, 16, 16), (1, 1, 1), 0.0, 1.0),    # r_cut <= 0
+                           ((16, 16, 16), (1, 1, 1), 1.0, -1.0)]:  # split < 0
+        g = (ctypes.c_int32 * 3)(*grid)
+        hh = (ctypes.c_double * 3)(*h)
+        assert L.p3m_create(ctypes.byref(ctx), g, hh, rc, a, ctypes.byref(o)) == p3m.EINVAL
+    bad = p3m.Opts()
+    L.p3m_default_opts(ctypes.byref(bad))
+    bad.order = 3
+    g = (ctypes.c_int32 * 3)(16, 16, 16)
+    hh = (ctypes.c_double * 3)(1, 1, 1)
+    assert L.p3m_create(ctypes.byref(ctx), g, hh, 1.0, 1.0, ctypes.byref(bad)) == p3m.EINVAL
+    assert L.p3m_last_error(None) == b"null context"
+    L.p3m_destroy(None)
+
+
+def test_product_path_has_no_oracle_or_cpu_fallback():
+    """The library and its binding never reach the oracle."""
+    pkg = os.path.join(ROOT, "paper_2103_02046_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text, f
