@@ -1,0 +1,214 @@
+"""Throughput of the P3M leapfrog step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload aniso1m]
+                    [--precision fp32c|fp64] [--cpu-steps 2] [--no-cpu-baseline]
+
+One step = one kick-drift-kick leapfrog step of the whole bunch: push,
+placement, linked-cell sort, PP pair forces, deposit, FFT convolution,
+gather (every stage of the P3M force evaluation). Inputs are resident in HBM
+before the timed region. Warm-up steps run on a copy of the bunch; the K
+timed steps then start from the initial state, whose force is evaluated
+before the timer starts, so the timed region holds exactly the run's K
+steps and K force evaluations.
+
+Prints one JSON line with the metric, a roofline entry for the dominant
+kernel (timed live with HIP events on the library's stream during the timed
+region) and the FP64 CPU oracle timed on a bounded sample on this host.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
+PEAK_FP32_VALU = 157.3         # TFLOP/s, vector FP32 (256 CU x 2.4 GHz)
+PEAK_FP64_VALU = 78.6          # TFLOP/s, vector FP64
+PP_FLOP_PER_PAIR = 40          # canonical count per in-cutoff ordered pair
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="aniso1m")
+    ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def stage_sources():
+    return {
+        "pp": ["pp.hip", "erfcx_fit.h", "common.h"],
+        "fft": ["fft.hip", "common.h"],
+        "sort": ["sort.hip", "common.h"],
+        "deposit": ["mesh.hip", "common.h"],
+        "gather": ["mesh.hip", "common.h"],
+        "reorder": ["sort.hip", "common.h"],
+        "push+placement": ["placement.hip", "common.h"],
+    }
+
+
+def source_hash(stage):
+    h = hashlib.sha256()
+    for f in stage_sources()[stage]:
+        with open(os.path.join(ROOT, "paper_2103_02046_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(stage, workload, precision, launches_per_step):
+    """HBM bytes per launch from the committed counter summary, or None if the
+    summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash(stage):
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, steps):
+    """The FP64 CPU oracle as it stands, on `steps` leapfrog steps of the same
+    workload (the initial force evaluation is not timed)."""
+    from oracle import oracle as O
+    x, p = wl.draw()
+    prm = O.Params.from_workload(wl)
+    f = O.forces(x, prm)
+    t0 = time.perf_counter()
+    O.step(x, p, prm, steps, f)
+    t = time.perf_counter() - t0
+    return {"value": wl.n * steps / t, "unit": "particle-steps/s", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} full leapfrog steps of the {wl.n}-particle workload "
+                      f"(FP64 C/OpenMP + numpy FFT), {t:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(the sharded design is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    from paper_2103_02046_amd import p3m
+    from paper_2103_02046_amd import workloads as W
+
+    wl = W.get(args.workload)
+    prec = p3m.FP32C if args.precision == "fp32c" else p3m.FP64
+    x0, p0 = wl.draw()
+    dev = torch.device("cuda:0")
+    x = torch.tensor(x0, dtype=torch.float64, device=dev)
+    p = torch.tensor(p0, dtype=torch.float64, device=dev)
+    ctx = p3m.Context.from_workload(wl, precision=prec)
+
+    # accuracy of this precision against the float64 path on the same GPU
+    f_this = ctx.forces(x)
+    f64 = p3m.Context.from_workload(wl, precision=p3m.FP64).forces(x)
+    err = float(torch.sqrt(((f_this - f64) ** 2).sum() / (f64 ** 2).sum()))
+    d0 = ctx.diagnostics(x, p)
+
+    if args.copy_calibration:
+        a = torch.empty(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # warm-up on a copy; the timed steps start from the initial state with its
+    # force already evaluated (untimed), so they are exactly the run's K steps
+    xw, pw = x.clone(), p.clone()
+    ctx.step(xw, pw, wl.dt, max(args.warmup, 1))
+    del xw, pw
+    ctx.step(x, p, wl.dt, 0)
+    torch.cuda.synchronize()
+    n_stage_launch = 8 * (args.steps + 2)
+    ctx.profile_begin(n_stage_launch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(x, p, wl.dt, args.steps, reuse_force=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    status = ctx.status_sync()
+    d1 = ctx.diagnostics(x, p)
+    wall = t1 - t0
+    value = wl.n * args.steps / wall
+
+    # dominant stage and its roofline
+    stage, (ms_tot, launches) = max(prof.items(), key=lambda kv: kv[1][0])
+    avg_s = ms_tot / max(launches, 1) * 1e-3
+    pairs = 0.5 * (d0["pairs"] + d1["pairs"])
+    mesh_nodes = wl.grid[0] * wl.grid[1] * wl.grid[2]
+    fbytes = 4 if prec == p3m.FP32C else 8
+    if stage == "pp":
+        flops = pairs * PP_FLOP_PER_PAIR
+        peak = PEAK_FP32_VALU if prec == p3m.FP32C else PEAK_FP64_VALU
+        achieved = flops / avg_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak}
+    else:
+        # compulsory bytes per launch of the stage (the design doc lists each)
+        per_stage = {
+            "fft": 2 * fbytes * mesh_nodes + 8 * (wl.grid[0] + 1) * (wl.grid[1] + 1) * (wl.grid[2] + 1),
+            "sort": 3 * 16 * wl.n,
+            "reorder": (4 + 4 + 24 + 2 * 4 * fbytes) * wl.n,
+            "deposit": 8 * fbytes * wl.n + fbytes * mesh_nodes,
+            "gather": (3 * 4 * fbytes + 4 + 2 * 24 + 24) * wl.n,
+            "push+placement": 96 * wl.n,
+        }
+        bytes_ = per_stage[stage]
+        achieved = bytes_ / avg_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    roof["kernel"] = stage
+    roof["avg_launch_ms"] = avg_s * 1e3
+    roof["traffic"] = traffic_from_profiles(stage, args.workload, args.precision, 1)
+
+    out = {
+        "metric": "P3M particle-steps/s at <=1e-5 rms force error vs FP64",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == p3m.FP32C else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {wl.n} particles, Gaussian sigma (1,1,3) mm, "
+                        f"{wl.grid[0]}^3 mesh ({2 * wl.grid[0]}^3 zero-padded FFT), "
+                        f"{'TSC' if wl.order == 2 else 'CIC'}, r_c = 2 h_x, kappa = 3, dt = T_p/200"
+            if args.workload == "aniso1m" else args.workload,
+            "precision": "fp32 pair forces and FFT with Kahan sums; fp64 table, push, reductions"
+            if prec == p3m.FP32C else "fp64",
+            "force_rms_err_vs_fp64": err,
+            "pp_pairs_per_s": pairs * args.steps / wall,
+            "pairs_per_eval": pairs,
+            "status": status,
+            "stage_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in prof.items()},
+        },
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

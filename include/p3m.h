@@ -170,6 +170,7 @@ typedef struct {
                              sqrt(<dx^2><dp^2> - <dx dp>^2) / (m c)            */
     double zoom;          /* s of this evaluation                               */
     double charge;        /* sum_i w_i                                          */
+    double pairs;         /* ordered pairs (i, j), j != i, with 0 < r < r_c'    */
 } p3m_diag;
 
 /*
@@ -185,6 +186,15 @@ p3m_status p3m_diagnostics(p3m_ctx *ctx, int64_t n, const double *x, const doubl
  * q), which = 1 the potential phi (1/m; the physical potential is k_e q phi).
  */
 p3m_status p3m_mesh(p3m_ctx *ctx, int32_t which, double *out, void *stream);
+
+/* Stage timing with HIP events recorded on the calling stream around every
+ * stage of every evaluation, for at most max_records stage launches:
+ *   0 push + placement, 1 linked-cell sort, 2 reorder, 3 PP pair forces,
+ *   4 deposit, 5 FFT convolution (five passes), 6 gather.
+ * p3m_profile_end synchronises `stream`, writes the summed milliseconds and
+ * the number of timed launches per stage (arrays of 8, host) and stops. */
+p3m_status p3m_profile_begin(p3m_ctx *ctx, int32_t max_records);
+p3m_status p3m_profile_end(p3m_ctx *ctx, double ms[8], int64_t launches[8], void *stream);
 
 /* Synchronise `stream`, return and clear the device status word
  * (P3M_OK, P3M_EDOMAIN or P3M_ENONFINITE). */

@@ -80,6 +80,7 @@ def lib():
             "oracle_pp_hvp": (None, [i64, P, P, dbl, dbl, dbl, P, P]),
             "oracle_deposit_grad": (i32, [i64, P, P, P, P, P, i32, P, P]),
             "oracle_gather_hvp": (i32, [i64, P, P, P, P, P, i32, P, P, P, dbl, P]),
+            "oracle_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -120,6 +121,11 @@ class Params:
     @classmethod
     def from_workload(cls, wl, **kw):
         return cls(wl.grid, wl.h, wl.r_cut, wl.split, wl.order, wl.ke_q2, wl.m, wl.dt, **kw)
+
+
+def threads():
+    """OpenMP threads used by the C loops."""
+    return int(lib().oracle_threads())
 
 
 # ---- placement --------------------------------------------------------------

@@ -535,3 +535,11 @@ int oracle_gather_hvp(int64_t n, const double *x, const double *qw, const int32_
     }
     return bad ? OR_EDOMAIN : OR_OK;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+#ifdef _OPENMP
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }
+#else
+int oracle_threads(void) { return 1; }
+#endif

@@ -67,6 +67,11 @@ struct p3m_ctx {
   uint32_t* perm = nullptr;     // sorted -> caller index of the last evaluation
   int last_precision = -1;      // engine of the last evaluation
   bool keep_mesh = false;
+  // stage timing
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_stage;
+  int prof_next = 0;
 };
 
 namespace {
@@ -187,9 +192,27 @@ p3m_status ensure_adjoint(p3m_ctx* ctx, int64_t n) {
   return P3M_OK;
 }
 
+// Stage timing: record an event pair around a group of launches.
+struct StageTimer {
+  p3m_ctx* c;
+  hipStream_t st;
+  int slot = -1;
+  StageTimer(p3m_ctx* ctx, int stage, hipStream_t s) : c(ctx), st(s) {
+    if (c->prof_on && c->prof_next < (int)c->prof_stage.size()) {
+      slot = c->prof_next++;
+      c->prof_stage[slot] = stage;
+      (void)hipEventRecord(c->prof_ev[2 * slot], st);
+    }
+  }
+  ~StageTimer() {
+    if (slot >= 0) (void)hipEventRecord(c->prof_ev[2 * slot + 1], st);
+  }
+};
+
 // Placement from the bounding box of x (or from place_in), into ctx->place.
 void place(p3m_ctx* ctx, int64_t n, const double* x, const double* place_in, double* place_out,
            hipStream_t st) {
+  StageTimer t(ctx, 0, st);
   const int nb = bbox_blocks(n);
   launch_bbox(n, x, ctx->bbox_part, nb, ctx->status, st);
   launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_in, ctx->place, place_out, ctx->status, st);
@@ -203,14 +226,32 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, int64_t n, const double* x, cons
   if ((s = engine_mesh_alloc(ctx, E)) != P3M_OK) return s;
   if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
   const Geo& g = ctx->geo;
-  launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
-  launch_reorder<R>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, st);
-  launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, E.fpp, e_pp, st);
-  if (ctx->keep_mesh) launch_fill(E.Q, mesh_nodes(g) * sizeof(R), st);
-  launch_deposit<R>(n, E.pp, E.mesh, g, E.Q, st);
-  const C2<R>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
-  launch_convolve<R>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, ctx->keep_mesh ? 0 : 1, st);
-  launch_gather<R>(n, E.pp, E.mesh, E.fpp, ctx->perm, g, ctx->place, E.phi, out, e_pm, st);
+  {
+    StageTimer t(ctx, 1, st);
+    launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
+  }
+  {
+    StageTimer t(ctx, 2, st);
+    launch_reorder<R>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, st);
+  }
+  {
+    StageTimer t(ctx, 3, st);
+    launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, E.fpp, e_pp, st);
+  }
+  {
+    StageTimer t(ctx, 4, st);
+    if (ctx->keep_mesh) launch_fill(E.Q, mesh_nodes(g) * sizeof(R), st);
+    launch_deposit<R>(n, E.pp, E.mesh, g, E.Q, st);
+  }
+  {
+    StageTimer t(ctx, 5, st);
+    const C2<R>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
+    launch_convolve<R>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, ctx->keep_mesh ? 0 : 1, st);
+  }
+  {
+    StageTimer t(ctx, 6, st);
+    launch_gather<R>(n, E.pp, E.mesh, E.fpp, ctx->perm, g, ctx->place, E.phi, out, e_pm, st);
+  }
   ctx->last_precision = sizeof(R) == 4 ? P3M_FP32C : P3M_FP64;
   return P3M_OK;
 }
@@ -403,9 +444,12 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
   const int nb = bbox_blocks(n);
   for (int k = 0; k < nsteps; ++k) {
     const size_t off = (size_t)P3M_PLACEMENT_DOUBLES * (k + 1);
-    launch_kick_drift_bbox(n, x, p, ctx->fcache, dt, inv_m, ctx->bbox_part, nb, ctx->status, st);
-    launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_replay ? place_replay + off : nullptr,
-                          ctx->place, place_record ? place_record + off : nullptr, ctx->status, st);
+    {
+      StageTimer t(ctx, 0, st);
+      launch_kick_drift_bbox(n, x, p, ctx->fcache, dt, inv_m, ctx->bbox_part, nb, ctx->status, st);
+      launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_replay ? place_replay + off : nullptr,
+                            ctx->place, place_record ? place_record + off : nullptr, ctx->status, st);
+    }
     GatherOut out{ctx->fcache, nullptr, nullptr, p, 0.5 * dt};
     if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
   }
@@ -471,6 +515,7 @@ p3m_status p3m_diagnostics(p3m_ctx* ctx, int64_t n, const double* x, const doubl
   launch_fill(ctx->acc, 64 * sizeof(double), st);
   place(ctx, n, x, nullptr, nullptr, st);
   GatherOut go{nullptr, nullptr, nullptr, nullptr, 0.0};
+  // acc[40] pair energy, acc[41] mesh energy, acc[42] pair count
   if ((s = evaluate_any(ctx, n, x, qw, go, ctx->acc + 40, ctx->acc + 41, st)) != P3M_OK) return s;
   launch_moments(n, x, p, qw, ctx->acc, 0, st);
   launch_moments(n, x, p, qw, ctx->acc, 1, st);
@@ -496,6 +541,7 @@ p3m_status p3m_diagnostics(p3m_ctx* ctx, int64_t n, const double* x, const doubl
   out->u_pm = h[41] * escale;
   out->zoom = P.s;
   out->charge = h[7];
+  out->pairs = h[42];
   return P3M_OK;
 }
 
@@ -510,6 +556,32 @@ p3m_status p3m_mesh(p3m_ctx* ctx, int32_t which, double* out, void* stream) {
   else
     launch_mesh_export<double>(ctx->geo, which ? ctx->e64.phi : ctx->e64.Q, ctx->place, which, out, st);
   return check_last(ctx);
+}
+
+p3m_status p3m_profile_begin(p3m_ctx* ctx, int32_t max_records) {
+  if (!ctx || max_records < 1) return P3M_EINVAL;
+  for (auto& e : ctx->prof_ev) (void)hipEventDestroy(e);
+  ctx->prof_ev.assign(2 * (size_t)max_records, nullptr);
+  for (auto& e : ctx->prof_ev) HIPCHK(hipEventCreate(&e));
+  ctx->prof_stage.assign(max_records, -1);
+  ctx->prof_next = 0;
+  ctx->prof_on = true;
+  return P3M_OK;
+}
+
+p3m_status p3m_profile_end(p3m_ctx* ctx, double ms[8], int64_t launches[8], void* stream) {
+  if (!ctx || !ms || !launches) return P3M_EINVAL;
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  for (int k = 0; k < 8; ++k) { ms[k] = 0.0; launches[k] = 0; }
+  for (int s = 0; s < ctx->prof_next; ++s) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, ctx->prof_ev[2 * s], ctx->prof_ev[2 * s + 1]));
+    ms[ctx->prof_stage[s]] += t;
+    launches[ctx->prof_stage[s]] += 1;
+  }
+  ctx->prof_on = false;
+  ctx->prof_next = 0;
+  return P3M_OK;
 }
 
 p3m_status p3m_status_sync(p3m_ctx* ctx, void* stream) {
@@ -547,6 +619,7 @@ const char* p3m_last_error(const p3m_ctx* ctx) {
 
 void p3m_destroy(p3m_ctx* ctx) {
   if (!ctx) return;
+  for (auto& e : ctx->prof_ev) (void)hipEventDestroy(e);
   engine_free(ctx->e32);
   engine_free(ctx->e64);
   dfree(ctx->sb.keys_a);

@@ -12,6 +12,8 @@
 //          the weight gradient read as a finite difference of phi at the
 //          nearest nodes (the remark after eq. eom_p3m_coord).
 // Lengths are in the unit Lu = s r_c, so grad = (1/hu_d) d/du with hu = h/r_c.
+#include <climits>
+
 #include "launch.h"
 
 namespace p3m {
@@ -44,26 +46,113 @@ struct Stencil {
   }
 };
 
+// Deposit, privatised in LDS: a block takes 1024 consecutive sorted
+// particles. Sorted by PP cell, they usually cover a small box of nodes
+// (dense core: a few cells along one x row); the block then accumulates
+// their weights in an LDS tile of that box and adds the tile to the mesh
+// with one global atomic per touched node. When the box does not fit the
+// tile (sparse halo, where particles rarely share nodes) each particle adds
+// its weights to the mesh directly.
+constexpr int kDepItems = 4;
+constexpr int kDepChunk = kThreads * kDepItems;
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+
 template <typename R, int ORDER>
 __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>* __restrict__ pp,
                                                       const MeshRec<R>* __restrict__ mesh, Geo geo,
                                                       R* __restrict__ Q) {
-  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (j >= n) return;
-  const MeshRec<R> m = mesh[j];
-  const R q = pp[j].w;
-  Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
-  const int nx = geo.grid[0];
-  const long long nxy = (long long)nx * geo.grid[1];
+  constexpr int kTileNodes = 32768 / (int)sizeof(R);
+  constexpr int NS = ORDER + 1;
+  __shared__ R tile[kTileNodes];
+  __shared__ int red[6];
+  const int t = threadIdx.x;
+  const int nx = geo.grid[0], ny = geo.grid[1];
+  const long long nxy = (long long)nx * ny;
+  const int64_t j0 = (int64_t)blockIdx.x * kDepChunk;
+  MeshRec<R> m[kDepItems];
+  R q[kDepItems];
+  int b[kDepItems][3];
+  bool ok[kDepItems];
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
 #pragma unroll
-  for (int c = 0; c < S.N; ++c)
-#pragma unroll
-    for (int b = 0; b < S.N; ++b) {
-      const R wyz = q * S.w[1][b] * S.w[2][c];
-      R* row = Q + m.base + c * nxy + (long long)b * nx;
-#pragma unroll
-      for (int a = 0; a < S.N; ++a) atomicAdd(row + a, wyz * S.w[0][a]);
+  for (int it = 0; it < kDepItems; ++it) {
+    const int64_t j = j0 + it * kThreads + t;
+    ok[it] = j < n;
+    if (ok[it]) {
+      m[it] = mesh[j];
+      q[it] = pp[j].w;
+      const long long base = m[it].base;
+      b[it][0] = (int)(base % nx);
+      b[it][1] = (int)((base / nx) % ny);
+      b[it][2] = (int)(base / nxy);
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = min(lo[d], b[it][d]);
+        hi[d] = max(hi[d], b[it][d]);
+      }
     }
+  }
+  if (t < 6) red[t] = t < 3 ? INT_MAX : INT_MIN;
+  __syncthreads();
+  for (int d = 0; d < 3; ++d) {
+    const int a = wave_min(lo[d]), c = wave_max(hi[d]);
+    if ((t & 63) == 0) {
+      atomicMin(&red[d], a);
+      atomicMax(&red[3 + d], c);
+    }
+  }
+  __syncthreads();
+  const int o0 = red[0], o1 = red[1], o2 = red[2];
+  const int e0 = red[3] - o0 + NS, e1 = red[4] - o1 + NS, e2 = red[5] - o2 + NS;
+  const long long vol = (long long)e0 * e1 * e2;
+  if (vol <= kTileNodes) {
+    for (int e = t; e < vol; e += kThreads) tile[e] = (R)0;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kDepItems; ++it) {
+      if (!ok[it]) continue;
+      Stencil<R, ORDER> S(m[it].fx, m[it].fy, m[it].fz);
+      const int tb = ((b[it][2] - o2) * e1 + (b[it][1] - o1)) * e0 + (b[it][0] - o0);
+#pragma unroll
+      for (int c = 0; c < NS; ++c)
+#pragma unroll
+        for (int bb = 0; bb < NS; ++bb) {
+          const R wyz = q[it] * S.w[1][bb] * S.w[2][c];
+#pragma unroll
+          for (int a = 0; a < NS; ++a) atomicAdd(&tile[tb + (c * e1 + bb) * e0 + a], wyz * S.w[0][a]);
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < vol; e += kThreads) {
+      const R v = tile[e];
+      if (v != (R)0) {
+        const int ex = e % e0, ey = (e / e0) % e1, ez = e / (e0 * e1);
+        atomicAdd(Q + ((long long)(o2 + ez) * ny + (o1 + ey)) * nx + (o0 + ex), v);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < kDepItems; ++it) {
+      if (!ok[it]) continue;
+      Stencil<R, ORDER> S(m[it].fx, m[it].fy, m[it].fz);
+#pragma unroll
+      for (int c = 0; c < NS; ++c)
+#pragma unroll
+        for (int bb = 0; bb < NS; ++bb) {
+          const R wyz = q[it] * S.w[1][bb] * S.w[2][c];
+          R* row = Q + m[it].base + c * nxy + (long long)bb * nx;
+#pragma unroll
+          for (int a = 0; a < NS; ++a) atomicAdd(row + a, wyz * S.w[0][a]);
+        }
+    }
+  }
 }
 
 template <typename R, int ORDER>
@@ -226,10 +315,11 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) /
 template <typename R>
 void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, R* Q,
                     hipStream_t st) {
+  const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
   if (geo.order == 1)
-    k_deposit<R, 1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, 1><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
   else
-    k_deposit<R, 2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, 2><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
 }
 
 template <typename R>

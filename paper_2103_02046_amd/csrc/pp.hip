@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(kThreads) k_pp(int64_t n, const PPRec<R>* __re
                                                  PPRec<R>* __restrict__ out, double* __restrict__ energy) {
   const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   double e_acc = 0.0;
+  int pairs = 0;
   if (j < n) {
     const PPRec<R> me = rec[j];
     const uint32_t key = keys[j];
@@ -118,7 +119,10 @@ __global__ void __launch_bounds__(kThreads) k_pp(int64_t n, const PPRec<R>* __re
               R ep;
               const R g = pair_scalar(r2, o.w, kappa, c2k, ENERGY ? &ep : nullptr);
               acc.add(g * ddx, g * ddy, g * ddz);
-              if (ENERGY) e_acc += (double)ep;
+              if (ENERGY) {
+                e_acc += (double)ep;
+                ++pairs;
+              }
             }
           }
         }
@@ -133,15 +137,22 @@ __global__ void __launch_bounds__(kThreads) k_pp(int64_t n, const PPRec<R>* __re
     e_acc *= 0.5 * (double)me.w;   // each unordered pair is met twice
   }
   if (ENERGY) {
-    // block reduction, one float64 atomic per block
-    __shared__ double s[kThreads];
-    s[threadIdx.x] = e_acc;
+    // block reduction, one float64 atomic per block; energy[2] counts pairs
+    __shared__ double s[2][kThreads];
+    s[0][threadIdx.x] = e_acc;
+    s[1][threadIdx.x] = (double)pairs;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+      if ((int)threadIdx.x < w) {
+        s[0][threadIdx.x] += s[0][threadIdx.x + w];
+        s[1][threadIdx.x] += s[1][threadIdx.x + w];
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(energy, s[0]);
+    if (threadIdx.x == 0) {
+      atomicAdd(energy, s[0][0]);
+      atomicAdd(energy + 2, s[1][0]);
+    }
   }
 }
 

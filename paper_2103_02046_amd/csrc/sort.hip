@@ -134,16 +134,19 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter(
   }
 }
 
-// cell_start[c] = first sorted index with key >= c, for c in [0, ncells].
+// cell_start[c] = first sorted index with key >= c, for c in [0, ncells]:
+// one thread per cell, binary search in the sorted keys.
 __global__ void k_cell_start(int64_t n, const uint32_t* __restrict__ keys, int* __restrict__ cs,
                              long long ncells) {
-  int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (j >= n) return;
-  long long k = keys[j];
-  long long prev = j ? (long long)keys[j - 1] : -1;
-  for (long long c = prev + 1; c <= k; ++c) cs[c] = (int)j;
-  if (j == n - 1)
-    for (long long c = k + 1; c <= ncells; ++c) cs[c] = (int)n;
+  const long long c = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (c > ncells) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((long long)keys[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  cs[c] = (int)lo;
 }
 
 template <typename R>
@@ -237,7 +240,7 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
     uint32_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;
   }
-  k_cell_start<<<blocks_for(n), kThreads, 0, st>>>(n, ka, b.cell_start, geo.ncells);
+  k_cell_start<<<blocks_for(geo.ncells + 1), kThreads, 0, st>>>(n, ka, b.cell_start, geo.ncells);
   *keys = ka;
   *perm = va;
 }

@@ -24,8 +24,9 @@ PLACEMENT_DOUBLES = 4
 SYMBOLS = (
     "p3m_default_opts", "p3m_create", "p3m_forces", "p3m_forces_ex", "p3m_step", "p3m_hvp",
     "p3m_backward", "p3m_diagnostics", "p3m_mesh", "p3m_status_sync", "p3m_info",
-    "p3m_last_error", "p3m_destroy",
+    "p3m_last_error", "p3m_destroy", "p3m_profile_begin", "p3m_profile_end",
 )
+STAGES = ("push+placement", "sort", "reorder", "pp", "deposit", "fft", "gather")
 
 
 class P3MError(RuntimeError):
@@ -44,7 +45,7 @@ class Diag(ctypes.Structure):
     _fields_ = [("momentum", ctypes.c_double * 3), ("kinetic", ctypes.c_double),
                 ("u_pp", ctypes.c_double), ("u_pm", ctypes.c_double), ("mean", ctypes.c_double * 3),
                 ("rms", ctypes.c_double * 3), ("emit_n", ctypes.c_double * 3),
-                ("zoom", ctypes.c_double), ("charge", ctypes.c_double)]
+                ("zoom", ctypes.c_double), ("charge", ctypes.c_double), ("pairs", ctypes.c_double)]
 
 
 _lib = None
@@ -72,6 +73,8 @@ def lib():
             "p3m_info": (i32, [P, P]),
             "p3m_last_error": (ctypes.c_char_p, [P]),
             "p3m_destroy": (None, [P]),
+            "p3m_profile_begin": (i32, [P, i32]),
+            "p3m_profile_end": (i32, [P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -178,7 +181,17 @@ class Context:
                                           _stream()))
         return {"momentum": list(d.momentum), "kinetic": d.kinetic, "u_pp": d.u_pp, "u_pm": d.u_pm,
                 "mean": list(d.mean), "rms": list(d.rms), "emit_n": list(d.emit_n), "zoom": d.zoom,
-                "charge": d.charge}
+                "charge": d.charge, "pairs": d.pairs}
+
+    def profile_begin(self, max_records=1 << 16):
+        self._check(lib().p3m_profile_begin(self._ctx, int(max_records)))
+
+    def profile_end(self):
+        """Per-stage (milliseconds summed, launches) since profile_begin; synchronises."""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        self._check(lib().p3m_profile_end(self._ctx, ms, cnt, _stream()))
+        return {name: (ms[k], cnt[k]) for k, name in enumerate(STAGES)}
 
     def mesh(self, which):
         g = self.grid
