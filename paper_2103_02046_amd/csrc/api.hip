@@ -46,6 +46,8 @@ struct p3m_ctx {
   int64_t cap = 0;
   // sort
   SortBufs sb{};
+  int2* groups = nullptr;       // PP work groups
+  int* group_scratch = nullptr; // per-row group offsets
   int sort_nb_cap = 0;
   // placement, status, small scratch
   Place* place = nullptr;
@@ -158,6 +160,7 @@ p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   dfree(ctx->sb.keys_b);
   dfree(ctx->sb.vals_b);
   dfree(ctx->sb.counts);
+  dfree(ctx->groups);
   dfree(ctx->fcache);
   dfree(ctx->v_sorted);
   dfree(ctx->hpp);
@@ -171,6 +174,7 @@ p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   HIPCHK(dalloc(&ctx->sb.keys_b, (size_t)n));
   HIPCHK(dalloc(&ctx->sb.vals_b, (size_t)n));
   HIPCHK(dalloc(&ctx->sb.counts, (size_t)256 * sort_blocks(n)));
+  HIPCHK(dalloc(&ctx->groups, (size_t)pp_group_bound(n, ctx->geo)));
   HIPCHK(dalloc(&ctx->fcache, (size_t)3 * n));
   ctx->cap = n;
   return P3M_OK;
@@ -236,7 +240,8 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, int64_t n, const double* x, cons
   }
   {
     StageTimer t(ctx, 3, st);
-    launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, E.fpp, e_pp, st);
+    launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, ctx->group_scratch,
+                 E.fpp, e_pp, st);
   }
   {
     StageTimer t(ctx, 4, st);
@@ -359,8 +364,9 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   hipStream_t st = 0;
   if (dalloc(&ctx->place, 1) != hipSuccess || dalloc(&ctx->status, 1) != hipSuccess ||
       dalloc(&ctx->bbox_part, 6 * 1024) != hipSuccess || dalloc(&ctx->acc, 64) != hipSuccess ||
-      dalloc(&ctx->sb.ghist, 4 * 256) != hipSuccess ||
-      dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess)
+      dalloc(&ctx->sb.ghist, 4 * 256) != hipSuccess || dalloc(&ctx->sb.counter, 2) != hipSuccess ||
+      dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess ||
+      dalloc(&ctx->group_scratch, (size_t)pp_scratch_ints(g)) != hipSuccess)
     return bail(P3M_ENOMEM);
   if (hipMemset(ctx->status, 0, sizeof(int)) != hipSuccess) return bail(P3M_EHIP);
   // Fourier table of the mesh kernel (float64), built once.
@@ -628,6 +634,9 @@ void p3m_destroy(p3m_ctx* ctx) {
   dfree(ctx->sb.vals_b);
   dfree(ctx->sb.counts);
   dfree(ctx->sb.ghist);
+  dfree(ctx->sb.counter);
+  dfree(ctx->groups);
+  dfree(ctx->group_scratch);
   dfree(ctx->sb.cell_start);
   dfree(ctx->place);
   dfree(ctx->status);

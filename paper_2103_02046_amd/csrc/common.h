@@ -11,6 +11,7 @@ constexpr int kBitDomain = 1;     // a particle outside the mesh with zoom off
 constexpr int kBitNonFinite = 2;  // a non-finite position
 
 constexpr int kThreads = 256;     // block size of the particle kernels
+constexpr int kXcds = 8;          // MI355X: work-groups are dealt round-robin to 8 XCDs
 
 // Placement of one evaluation, written on the device by the finalize kernel.
 // Lengths inside the kernels are measured in the unit Lu = s * r_c, in which

@@ -20,6 +20,7 @@ struct SortBufs {
   int* counts;      // [256][nblocks]
   int* ghist;       // [passes][256]
   int* cell_start;  // [ncells + 1]
+  int* counter;     // [0] PP groups built, [1] PP groups taken; cleared by the key kernel
 };
 int sort_passes(long long ncells);
 int sort_blocks(int64_t n);
@@ -34,9 +35,14 @@ template <typename R>
 void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out, hipStream_t st);
 
 // ---- pair forces (pp.hip) ------------------------------------------------
+// Upper bound of the number of PP work groups (runs of <= 64 particles per cell row).
+int pp_group_bound(int64_t n, const Geo& geo);
+// Ints of scratch the group builder needs.
+int pp_scratch_ints(const Geo& geo);
 template <typename R>
 void launch_pp(int64_t n, const PPRec<R>* rec, const uint32_t* keys, const int* cell_start,
-               const Geo& geo, PPRec<R>* out, double* energy, hipStream_t st);
+               const Geo& geo, int2* desc, int* counter, int* scratch, PPRec<R>* out, double* energy,
+               hipStream_t st);
 void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
                    const int* cell_start, const Geo& geo, const double* v_sorted,
                    double* out_sorted, hipStream_t st);

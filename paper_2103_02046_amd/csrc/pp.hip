@@ -9,10 +9,12 @@
 // Sec. 2.5, eq. eom_p3m_coord second term). Coincident particles (rho = 0,
 // the particle itself included) contribute nothing.
 //
-// float form: erfc(x) = exp(-x^2) t P(t), t = 1/(1 + x/2), with the polynomial
-// fitted in this repository (fit_erfcx.py; relative error < 2e-7 in float),
-// the exp(-x^2) shared with the second term; per-particle sums are Kahan
-// compensated. double form: the device library's erfc and exp.
+// float form: erfc(x) = exp(-x^2) t P(t), t = 1/(1 + x/2), with the degree-6
+// polynomial fitted in this repository on 0 <= x <= 6 (fit_erfcx.py; relative
+// error < 5e-7 in float; beyond x = 6 both terms of the pair force are below
+// 2e-16 of their value at 0), the exp(-x^2) shared with the second term;
+// per-particle sums are Kahan compensated. double form: the device
+// library's erfc and exp.
 #include "erfcx_fit.h"
 #include "launch.h"
 
@@ -47,7 +49,7 @@ __device__ __forceinline__ float pair_scalar(float r2, float wj, float kappa, fl
   float r = r2 * rinv;
   float x = kappa * r;
   float e = __builtin_amdgcn_exp2f(-x * x * kLog2e);
-  float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+  float t = fmaxf(__builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f)), P3M_ERFCX_TMIN);
   float erfc_x = e * t * erfcx_poly(t);
   if (epair) *epair = erfc_x * rinv * wj;
   return (erfc_x * rinv + c2k * e) * (rinv * rinv) * wj;
@@ -77,81 +79,316 @@ struct Acc3<double> {
   __device__ __forceinline__ double get(int d) const { return s[d]; }
 };
 
+// Work groups: runs of at most 16 consecutive sorted particles of one cell.
+// The candidates of every particle of a group lie in 9 contiguous ranges:
+// cells cx-1 .. cx+1 of the 3 x 3 neighbouring rows (a row of cells is
+// contiguous in the sorted order). Groups are listed in cell order (count
+// per cell, prefix sum, emit), so consecutive groups are spatial neighbours.
+constexpr int kGroupMax = 16;
+constexpr int kScanItems = 256;   // block totals per thread in the middle scan
+
+__global__ void __launch_bounds__(kThreads) k_pp_groups_count(const int* __restrict__ cs, long long ncells,
+                                                              int* __restrict__ celloff, int* __restrict__ btot) {
+  const long long c = blockIdx.x * (long long)kThreads + threadIdx.x;
+  const int ng = c < ncells ? (cs[c + 1] - cs[c] + kGroupMax - 1) / kGroupMax : 0;
+  __shared__ int s[kThreads];
+  const int t = threadIdx.x;
+  s[t] = ng;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    const int add = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  if (c < ncells) celloff[c] = s[t] - ng;
+  if (t == kThreads - 1) btot[blockIdx.x] = s[t];
+}
+
+// One block: exclusive scan of the block totals in place; counter[0] = total.
+__global__ void __launch_bounds__(kThreads) k_pp_groups_scan(int* __restrict__ btot, int nblk,
+                                                             int* __restrict__ counter) {
+  const int t = threadIdx.x;
+  const int per = (nblk + kThreads - 1) / kThreads;
+  const int b0 = t * per, b1 = min(nblk, b0 + per);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += btot[b];
+  __shared__ int s[kThreads];
+  s[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    const int add = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int run = s[t] - sum;
+  for (int b = b0; b < b1; ++b) {
+    const int v = btot[b];
+    btot[b] = run;
+    run += v;
+  }
+  if (t == kThreads - 1) counter[0] = s[t];
+}
+
+__global__ void __launch_bounds__(kThreads) k_pp_groups_emit(const int* __restrict__ cs, long long ncells,
+                                                             const int* __restrict__ celloff,
+                                                             const int* __restrict__ boff,
+                                                             int2* __restrict__ desc) {
+  const long long c = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (c >= ncells) return;
+  const int b = cs[c], cnt = cs[c + 1] - b;
+  int g = boff[blockIdx.x] + celloff[c];
+  for (int k = 0; k < cnt; k += kGroupMax) desc[g++] = make_int2(b + k, min(kGroupMax, cnt - k));
+}
+
+// (m << 1) | sign(v): one v_alignbit_b32 for float; the sign of a double is
+// the top bit of its high word.
+__device__ __forceinline__ uint32_t mask_shift_in(uint32_t m, float v) {
+  return __builtin_amdgcn_alignbit(m, __float_as_uint(v), 31u);
+}
+__device__ __forceinline__ uint32_t mask_shift_in(uint32_t m, double v) {
+  return __builtin_amdgcn_alignbit(m, (uint32_t)(__double_as_longlong(v) >> 32), 31u);
+}
+
+template <typename R>
+struct Vec4;
+template <>
+struct Vec4<float> { using T = float4; };
+template <>
+struct Vec4<double> { using T = double4; };
+
+constexpr int kWaveGroups = 4;           // groups per wave (16 lanes each)
+constexpr int kSlabs = 4;                // slabs of quads per XCD
+constexpr int kTileK = 64;               // candidates per group per tile
+constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
+
+// Pair forces of four groups in one wave (lanes 16q .. 16q+15 hold the
+// targets of group q).
+// The candidates of a group are the concatenation of its 9 row ranges, L of
+// them. With S = ceil(L / 64) tiles, tile t holds candidates t, t+S, t+2S, ...:
+// an evenly spread sample of the whole neighbourhood, so the hits of a tile
+// spread evenly over the group's targets. Per tile:
+//   1. each group stages its 64 candidates in LDS (loaded one tile ahead);
+//   2. each lane tests its group's 64 candidates against its target, with
+//      positions relative to the group's first cell corner (a few cell
+//      edges at most): a 64-bit hit mask;
+//   3. each lane evaluates its own hits, the separation formed from
+//      cell-local positions plus the cell-corner offsets (at most two cell
+//      edges, exact multiples), so its float rounding is that of one cell
+//      edge; the tile sum is added to the per-particle total with Kahan
+//      compensation (float form).
 template <typename R, bool ENERGY>
-__global__ void __launch_bounds__(kThreads) k_pp(int64_t n, const PPRec<R>* __restrict__ rec,
-                                                 const uint32_t* __restrict__ keys,
-                                                 const int* __restrict__ cs, Geo geo,
-                                                 PPRec<R>* __restrict__ out, double* __restrict__ energy) {
-  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+__global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* __restrict__ counter,
+                                           const PPRec<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
+                                           const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
+                                           double* __restrict__ energy) {
+  using V4 = typename Vec4<R>::T;
+  // per-group tiles padded by one element so the four groups' broadcast
+  // reads fall in different LDS banks
+  constexpr int TS = kTileK + 1;
+  constexpr int NT = kWaveGroups * TS;
+  __shared__ V4 tile[NT];      // group-relative x, y, z (cutoff test)
+  __shared__ V4 tloc[NT];      // cell-local x, y, z and the charge weight
+  __shared__ V4 toff[NT];      // cell-corner offset from the group's first cell (exact)
+  __shared__ int rstart[kWaveGroups][9], rpre[kWaveGroups][10];
+  __shared__ int gtot[kWaveGroups];
+  // XCD-aware order: work-groups are dealt round-robin to the 8 XCDs. The
+  // quads (in cell order: spatial neighbours) are cut into 8 kSlabs slabs;
+  // XCD x takes slabs x, x + 8, ..., one after another, so its L2 holds the
+  // particles of the slab being worked on for all their re-reads, and every
+  // XCD gets slabs from all over the bunch (balanced work).
+  const int ngroups = counter[0];
+  const int nquads = (ngroups + kWaveGroups - 1) / kWaveGroups;
+  const int qps = (nquads + kXcds * kSlabs - 1) / (kXcds * kSlabs);   // quads per slab
+  const int local = blockIdx.x / kXcds;
+  if (local >= qps * kSlabs) return;
+  const int quad = ((local / qps) * kXcds + (int)(blockIdx.x % kXcds)) * qps + local % qps;
+  const int gbase = quad * kWaveGroups;
+  if (gbase >= ngroups) return;
+  const int lane = threadIdx.x, q = lane >> 4, ql = lane & 15;
+  const int gid = gbase + q;
+  const bool gvalid = gid < ngroups;
+  int2 gd = make_int2(0, 0);
+  if (gvalid) gd = desc[gid];
+  const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
+  const R cux = (R)geo.cu[0], cuy = (R)geo.cu[1], cuz = (R)geo.cu[2];
+  int cx0 = 0, cy = 0, cz = 0;
+  if (gvalid) {
+    const uint32_t k0 = keys[gd.x];
+    cx0 = (int)(k0 % (uint32_t)nx);
+    cy = (int)((k0 / (uint32_t)nx) % (uint32_t)ny);
+    cz = (int)(k0 / ((uint32_t)nx * (uint32_t)ny));
+  }
+  // 9 candidate ranges per group (lanes 0..8 of each quarter): cells
+  // cx0-1 .. cx0+1 of the rows (cy+dy, cz+dz), row r = (dy+1) + 3 (dz+1)
+  int len = 0;
+  if (ql < 9) {
+    const int dy = ql % 3 - 1, dz = ql / 3 - 1;
+    const int y = cy + dy, z = cz + dz;
+    int b = 0, e = 0;
+    if (gvalid && y >= 0 && y < ny && z >= 0 && z < nz) {
+      const int row = (z * ny + y) * nx;
+      const int xlo = cx0 > 0 ? cx0 - 1 : 0, xhi = cx0 + 1 < nx ? cx0 + 1 : nx - 1;
+      b = cs[row + xlo];
+      e = cs[row + xhi + 1];
+    }
+    rstart[q][ql] = b;
+    len = e - b;
+  }
+  int inc = len;
+  for (int off = 1; off < 16; off <<= 1) {
+    const int v = __shfl_up(inc, off, 16);
+    if (ql >= off) inc += v;
+  }
+  if (ql < 9) rpre[q][ql + 1] = inc;
+  if (ql == 0) rpre[q][0] = 0;
+  if (ql == 8) gtot[q] = inc;
+  __syncthreads();
+  // the target of this lane
+  const bool active = gvalid && ql < gd.y;
+  R lx = 0, ly = 0, lz = 0, tw = 0;
+  int tdc = 0;
+  if (active) {
+    const int j = gd.x + ql;
+    const PPRec<R> me = rec[j];
+    tdc = (int)(keys[j] % (uint32_t)nx) - cx0;
+    lx = me.x;
+    ly = me.y;
+    lz = me.z;
+    tw = me.w;
+  }
+  const R tox = (R)tdc * cux;   // 0: every target of a group is in its first cell
+  const R tx = active ? lx + tox : (R)1e18, ty = ly, tz = lz;
+  const int L = gtot[q];
+  const int S = (L + kTileK - 1) / kTileK;
+  const int nt = max(max((gtot[0] + kTileK - 1) / kTileK, (gtot[1] + kTileK - 1) / kTileK),
+                     max((gtot[2] + kTileK - 1) / kTileK, (gtot[3] + kTileK - 1) / kTileK));
+  // slot 16h + ql of tile t holds candidate (16h + ql) S + t; its row range
+  // index advances monotonically with t
+  int cq[kPerLane], cr[kPerLane];
+#pragma unroll
+  for (int h = 0; h < kPerLane; ++h) {
+    cq[h] = (16 * h + ql) * S;
+    int r = 0;
+#pragma unroll
+    for (int k = 1; k < 9; ++k) r += (cq[h] >= rpre[q][k]) ? 1 : 0;
+    cr[h] = r;
+  }
+  PPRec<R> nx_o[kPerLane];
+  int nx_c[kPerLane];
+  bool nx_ok[kPerLane];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int h = 0; h < kPerLane; ++h) {
+      const int qi = cq[h] + t;
+      nx_ok[h] = t < S && qi < L;
+      if (nx_ok[h]) {
+        while (qi >= rpre[q][cr[h] + 1]) ++cr[h];
+        const int k = rstart[q][cr[h]] + (qi - rpre[q][cr[h]]);
+        nx_o[h] = rec[k];
+        nx_c[h] = (int)(keys[k] % (uint32_t)nx) - cx0;
+      }
+    }
+  };
+  fetch(0);
+  const R kappa = (R)geo.kappa;
+  const R c2k = (R)(kTwoOverSqrtPi * geo.kappa);
+  Acc3<R> acc;
   double e_acc = 0.0;
   int pairs = 0;
-  if (j < n) {
-    const PPRec<R> me = rec[j];
-    const uint32_t key = keys[j];
-    const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
-    const int cx = (int)(key % (uint32_t)nx);
-    const int cy = (int)((key / (uint32_t)nx) % (uint32_t)ny);
-    const int cz = (int)(key / ((uint32_t)nx * (uint32_t)ny));
-    const R kappa = (R)geo.kappa;
-    const R c2k = (R)(kTwoOverSqrtPi * geo.kappa);
-    const R cux = (R)geo.cu[0], cuy = (R)geo.cu[1], cuz = (R)geo.cu[2];
-    Acc3<R> acc;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int z = cz + dz;
-      if (z < 0 || z >= nz) continue;
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int y = cy + dy;
-        if (y < 0 || y >= ny) continue;
-        const int rowc = (z * ny + y) * nx;
-        // offsets of the neighbour cell corner relative to the own one
-        const R oy = me.y - (R)dy * cuy;
-        const R oz = me.z - (R)dz * cuz;
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int xx = cx + dx;
-          if (xx < 0 || xx >= nx) continue;
-          const R ox = me.x - (R)dx * cux;
-          const int b = cs[rowc + xx], e = cs[rowc + xx + 1];
-          for (int k = b; k < e; ++k) {
-            const PPRec<R> o = rec[k];
-            const R ddx = ox - o.x, ddy = oy - o.y, ddz = oz - o.z;
-            const R r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-            if (r2 < (R)1 && r2 > (R)0) {
-              R ep;
-              const R g = pair_scalar(r2, o.w, kappa, c2k, ENERGY ? &ep : nullptr);
-              acc.add(g * ddx, g * ddy, g * ddz);
-              if (ENERGY) {
-                e_acc += (double)ep;
-                ++pairs;
-              }
-            }
-          }
+  for (int t = 0; t < nt; ++t) {
+    // 1. stage the prefetched candidates
+#pragma unroll
+    for (int h = 0; h < kPerLane; ++h) {
+      V4 c{(R)1e18, (R)0, (R)0, (R)0}, cl{(R)0, (R)0, (R)0, (R)0}, co{(R)0, (R)0, (R)0, (R)0};
+      if (nx_ok[h]) {
+        const int dy = cr[h] % 3 - 1, dz = cr[h] / 3 - 1;
+        cl = V4{nx_o[h].x, nx_o[h].y, nx_o[h].z, nx_o[h].w};
+        co = V4{(R)nx_c[h] * cux, (R)dy * cuy, (R)dz * cuz, (R)0};
+        c.x = cl.x + co.x;
+        c.y = cl.y + co.y;
+        c.z = cl.z + co.z;
+      }
+      tile[TS * q + 16 * h + ql] = c;
+      tloc[TS * q + 16 * h + ql] = cl;
+      toff[TS * q + 16 * h + ql] = co;
+    }
+    __syncthreads();
+    fetch(t + 1);
+    // 2. hit masks (group-relative positions). The sign bit of r2 - 1 is
+    //    shifted into the mask (alignbit: m = (m << 1) | (bits >> 31)), so
+    //    candidate k of a half-tile ends at bit 31 - k. The test is made a
+    //    little generous (2e-6 of the cutoff); the evaluation below repeats
+    //    it exactly on the precise separation.
+    const V4* tq = tile + TS * q;
+    uint32_t m0 = 0u, m1 = 0u;
+    const R lim = (R)(-(1.0 + 2e-6));
+#pragma unroll 4
+    for (int k = 0; k < 32; ++k) {
+      const V4 c = tq[k];
+      const R dx = tx - c.x, dy = ty - c.y, dz = tz - c.z;
+      const R r2m1 = dz * dz + (dy * dy + (dx * dx + lim));
+      m0 = mask_shift_in(m0, r2m1);
+    }
+#pragma unroll 4
+    for (int k = 0; k < 32; ++k) {
+      const V4 c = tq[32 + k];
+      const R dx = tx - c.x, dy = ty - c.y, dz = tz - c.z;
+      const R r2m1 = dz * dz + (dy * dy + (dx * dx + lim));
+      m1 = mask_shift_in(m1, r2m1);
+    }
+    if (!active) m0 = m1 = 0u;
+    // 3. own hits (the particle itself and coincident ones give r2 = 0)
+    R sx = 0, sy = 0, sz = 0;
+    while (m0 | m1) {
+      int k;
+      if (m0) {
+        k = __clz(m0);
+        m0 &= ~(0x80000000u >> k);
+      } else {
+        const int b = __clz(m1);
+        m1 &= ~(0x80000000u >> b);
+        k = 32 + b;
+      }
+      const V4 cl = tloc[TS * q + k];
+      const V4 co = toff[TS * q + k];
+      const R dx = (lx - cl.x) + (tox - co.x);
+      const R dy = (ly - cl.y) - co.y;
+      const R dz = (lz - cl.z) - co.z;
+      const R r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 > (R)0 && r2 < (R)1) {
+        R ep;
+        const R g = pair_scalar(r2, cl.w, kappa, c2k, ENERGY ? &ep : nullptr);
+        sx += g * dx;
+        sy += g * dy;
+        sz += g * dz;
+        if (ENERGY) {
+          e_acc += (double)ep;
+          ++pairs;
         }
       }
     }
+    acc.add(sx, sy, sz);
+    __syncthreads();
+  }
+  if (active) {
     PPRec<R> f;
-    f.x = acc.get(0) * me.w;
-    f.y = acc.get(1) * me.w;
-    f.z = acc.get(2) * me.w;
+    f.x = acc.get(0) * tw;
+    f.y = acc.get(1) * tw;
+    f.z = acc.get(2) * tw;
     f.w = (R)0;
-    out[j] = f;
-    e_acc *= 0.5 * (double)me.w;   // each unordered pair is met twice
+    out[gd.x + ql] = f;
   }
   if (ENERGY) {
-    // block reduction, one float64 atomic per block; energy[2] counts pairs
-    __shared__ double s[2][kThreads];
-    s[0][threadIdx.x] = e_acc;
-    s[1][threadIdx.x] = (double)pairs;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-        s[0][threadIdx.x] += s[0][threadIdx.x + w];
-        s[1][threadIdx.x] += s[1][threadIdx.x + w];
-      }
-      __syncthreads();
+    e_acc *= 0.5 * (double)tw;   // each unordered pair is met twice
+    for (int off = 32; off > 0; off >>= 1) {
+      e_acc += __shfl_xor(e_acc, off);
+      pairs += __shfl_xor(pairs, off);
     }
-    if (threadIdx.x == 0) {
-      atomicAdd(energy, s[0][0]);
-      atomicAdd(energy + 2, s[1][0]);
+    if (lane == 0) {
+      atomicAdd(energy, e_acc);
+      atomicAdd(energy + 2, (double)pairs);
     }
   }
 }
@@ -213,14 +450,38 @@ __global__ void __launch_bounds__(kThreads) k_pp_hvp(int64_t n, const PPRec<doub
 
 }  // namespace
 
+int pp_group_bound(int64_t n, const Geo& geo) {
+  // runs of <= 16 particles of one cell: at most n/16 full runs plus one
+  // partial run per cell, and never more than n
+  long long b = n / kGroupMax + geo.ncells + 1;
+  if (b > n + 1) b = n + 1;
+  return (int)b;
+}
+
+int pp_scratch_ints(const Geo& geo) {
+  return (int)(geo.ncells + (geo.ncells + kThreads - 1) / kThreads);
+}
+
 template <typename R>
 void launch_pp(int64_t n, const PPRec<R>* rec, const uint32_t* keys, const int* cell_start,
-               const Geo& geo, PPRec<R>* out, double* energy, hipStream_t st) {
-  unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
+               const Geo& geo, int2* desc, int* counter, int* scratch, PPRec<R>* out, double* energy,
+               hipStream_t st) {
+  const long long nc = geo.ncells;
+  const int cb = (int)((nc + kThreads - 1) / kThreads);
+  int* celloff = scratch;
+  int* btot = scratch + nc;
+  k_pp_groups_count<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot);
+  k_pp_groups_scan<<<1, kThreads, 0, st>>>(btot, cb, counter);
+  k_pp_groups_emit<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot, desc);
+  // one wave per quad of groups, XCD-major slab order; waves beyond the
+  // groups built leave at once
+  const long long qb = (pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups;
+  const long long per = kSlabs * ((qb + kXcds * kSlabs - 1) / (kXcds * kSlabs));
+  const unsigned blocks = (unsigned)(kXcds * per);
   if (energy)
-    k_pp<R, true><<<blocks, kThreads, 0, st>>>(n, rec, keys, cell_start, geo, out, energy);
+    k_pp<R, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
   else
-    k_pp<R, false><<<blocks, kThreads, 0, st>>>(n, rec, keys, cell_start, geo, out, nullptr);
+    k_pp<R, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr);
 }
 
 void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys, const int* cell_start,
@@ -230,8 +491,8 @@ void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys, co
 }
 
 template void launch_pp<float>(int64_t, const PPRec<float>*, const uint32_t*, const int*, const Geo&,
-                               PPRec<float>*, double*, hipStream_t);
+                               int2*, int*, int*, PPRec<float>*, double*, hipStream_t);
 template void launch_pp<double>(int64_t, const PPRec<double>*, const uint32_t*, const int*, const Geo&,
-                                PPRec<double>*, double*, hipStream_t);
+                                int2*, int*, int*, PPRec<double>*, double*, hipStream_t);
 
 }  // namespace p3m

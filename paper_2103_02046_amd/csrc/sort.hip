@@ -21,9 +21,12 @@ __global__ void __launch_bounds__(kThreads) k_keys(int64_t n, const double* __re
                                                    const Place* __restrict__ pl, Geo geo,
                                                    uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals,
-                                                   int* __restrict__ ghist, int nhist) {
-  if (blockIdx.x == 0)
+                                                   int* __restrict__ ghist, int nhist,
+                                                   int* __restrict__ counter) {
+  if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < nhist; k += kThreads) ghist[k] = 0;
+    if (threadIdx.x < 2) counter[threadIdx.x] = 0;
+  }
   int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (i >= n) return;
   const Place P = *pl;
@@ -230,7 +233,8 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
                       uint32_t** keys, uint32_t** perm, hipStream_t st) {
   const int passes = sort_passes(geo.ncells);
   const int nb = sort_blocks(n);
-  k_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_a, b.vals_a, b.ghist, passes * 256);
+  k_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_a, b.vals_a, b.ghist, passes * 256,
+                                             b.counter);
   uint32_t *ka = b.keys_a, *va = b.vals_a, *kb = b.keys_b, *vb = b.vals_b;
   for (int p = 0; p < passes; ++p) {
     int* gh = b.ghist + p * 256;
