@@ -74,7 +74,7 @@ int oracle_placement(int64_t n, const double *x, const int32_t *grid,
     double s = 1.0;
     for (int d = 0; d < 3; ++d) {
         double usable = (double)(order == 1 ? grid[d] - 1 : grid[d] - 2);
-        double need = (hi[d] - lo[d]) * (1.0 + 1e-9) / (usable * h[d]);
+        double need = (hi[d] - lo[d]) * (1.0 + 1e-6) / (usable * h[d]);
         if (need > s) s = need;
     }
     if (s > 1.0 && !zoom) return OR_EDOMAIN;

@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kThreads) k_place_finalize(int nblk, const dou
       double a = s[d][0], b = s[3 + d][0];
       if (!(a <= b)) { a = 0.0; b = 0.0; }  // no finite position on this axis
       double usable = (double)(geo.order == 1 ? geo.grid[d] - 1 : geo.grid[d] - 2);
-      double need = (b - a) * (1.0 + 1e-9) / (usable * geo.h[d]);
+      double need = (b - a) * (1.0 + 1e-6) / (usable * geo.h[d]);
       if (need > zoom) zoom = need;
     }
     if (zoom > 1.0 && !geo.zoom) atomicOr(status, kBitDomain);
