@@ -61,6 +61,17 @@ typedef int32_t p3m_status;
                               /* compensated pair sums; float64 Green's table,  */
                               /* positions, momenta and reductions              */
 
+/* Mesh precision of the P3M_FP32C form (the P3M_FP64 form is float64
+ * throughout). The mesh force is a difference of node potentials, so a
+ * float32 potential carries a relative force error of about 6e-8 times the
+ * bunch extent in cells: below 1e-5 up to ~150 cells. AUTO takes float32
+ * while every grid axis has at most P3M_MESH_AUTO_F32_MAX nodes, else
+ * float64 (charge, transform and potential; pair forces stay float32). */
+#define P3M_MESH_AUTO 0
+#define P3M_MESH_F32  1
+#define P3M_MESH_F64  2
+#define P3M_MESH_AUTO_F32_MAX 128
+
 #define P3M_CIC 1             /* linear B-spline b1 (2 nodes per axis)          */
 #define P3M_TSC 2             /* quadratic B-spline b2 (3 nodes per axis)       */
 
@@ -74,6 +85,8 @@ typedef struct {
     int32_t zoom;       /* 1: zoom the mesh to fit the bunch; 0: EDOMAIN    [1]    */
     int32_t keep_mesh;  /* 1: keep the charge mesh of the last evaluation for
                            p3m_mesh (one extra clear per evaluation)        [0]    */
+    int32_t mesh_precision; /* P3M_MESH_AUTO, _F32 or _F64 (P3M_FP32C only) [AUTO] */
+    int32_t reserved;   /* must be 0                                               */
     double ke;          /* Coulomb constant 1/(4 pi eps0)     [8.9875517923e9]    */
     double q;           /* macro-particle charge, C                        [1.0]  */
     double m;           /* macro-particle mass, kg                         [1.0]  */

@@ -67,8 +67,9 @@ struct p3m_ctx {
   Engine<double> e64;
   uint32_t* keys = nullptr;     // sorted keys of the last evaluation
   uint32_t* perm = nullptr;     // sorted -> caller index of the last evaluation
-  int last_precision = -1;      // engine of the last evaluation
+  int last_precision = -1;      // mesh precision of the last evaluation
   bool keep_mesh = false;
+  bool mesh64 = false;          // float32 particle path with a float64 mesh
   // stage timing
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -222,12 +223,13 @@ void place(p3m_ctx* ctx, int64_t n, const double* x, const double* place_in, dou
   launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_in, ctx->place, place_out, ctx->status, st);
 }
 
-// Everything after the placement: linked cells, PP, mesh, gather.
-template <typename R>
-p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, int64_t n, const double* x, const double* qw,
-                    GatherOut out, double* e_pp, double* e_pm, hipStream_t st) {
+// Everything after the placement: linked cells, PP, mesh, gather. Particle
+// records in R, the mesh (charge, transform, potential) of engine EM in M.
+template <typename R, typename M>
+p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const double* x,
+                    const double* qw, GatherOut out, double* e_pp, double* e_pm, hipStream_t st) {
   p3m_status s;
-  if ((s = engine_mesh_alloc(ctx, E)) != P3M_OK) return s;
+  if ((s = engine_mesh_alloc(ctx, EM)) != P3M_OK) return s;
   if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
   const Geo& g = ctx->geo;
   {
@@ -245,26 +247,29 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, int64_t n, const double* x, cons
   }
   {
     StageTimer t(ctx, 4, st);
-    if (ctx->keep_mesh) launch_fill(E.Q, mesh_nodes(g) * sizeof(R), st);
-    launch_deposit<R>(n, E.pp, E.mesh, g, E.Q, st);
+    if (ctx->keep_mesh) launch_fill(EM.Q, mesh_nodes(g) * sizeof(M), st);
+    launch_deposit<R, M>(n, E.pp, E.mesh, g, EM.Q, st);
   }
   {
     StageTimer t(ctx, 5, st);
-    const C2<R>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
-    launch_convolve<R>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, ctx->keep_mesh ? 0 : 1, st);
+    const C2<M>* tw[3] = {EM.tw[0], EM.tw[1], EM.tw[2]};
+    launch_convolve<M>(g, EM.Q, EM.spec, ctx->ghat, tw, EM.phi, ctx->keep_mesh ? 0 : 1, st);
   }
   {
     StageTimer t(ctx, 6, st);
-    launch_gather<R>(n, E.pp, E.mesh, E.fpp, ctx->perm, g, ctx->place, E.phi, out, e_pm, st);
+    launch_gather<R, M>(n, E.pp, E.mesh, E.fpp, ctx->perm, g, ctx->place, EM.phi, out, e_pm, st);
   }
-  ctx->last_precision = sizeof(R) == 4 ? P3M_FP32C : P3M_FP64;
+  ctx->last_precision = sizeof(M) == 4 ? P3M_FP32C : P3M_FP64;
   return P3M_OK;
 }
 
 p3m_status evaluate_any(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, GatherOut out,
                         double* e_pp, double* e_pm, hipStream_t st) {
-  if (ctx->opts.precision == P3M_FP32C) return evaluate<float>(ctx, ctx->e32, n, x, qw, out, e_pp, e_pm, st);
-  return evaluate<double>(ctx, ctx->e64, n, x, qw, out, e_pp, e_pm, st);
+  if (ctx->opts.precision == P3M_FP32C) {
+    if (ctx->mesh64) return evaluate<float, double>(ctx, ctx->e32, ctx->e64, n, x, qw, out, e_pp, e_pm, st);
+    return evaluate<float, float>(ctx, ctx->e32, ctx->e32, n, x, qw, out, e_pp, e_pm, st);
+  }
+  return evaluate<double, double>(ctx, ctx->e64, ctx->e64, n, x, qw, out, e_pp, e_pm, st);
 }
 
 p3m_status check_last(p3m_ctx* ctx) {
@@ -288,7 +293,7 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
   launch_fill(E.Q, mesh_nodes(g) * sizeof(double), st);
-  launch_deposit<double>(n, E.pp, E.mesh, g, E.Q, st);
+  launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, st);
   launch_convolve<double>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, 1, st);
   launch_fill(ctx->Rm, mesh_nodes(g) * sizeof(double), st);
   launch_deposit_grad(n, E.pp, E.mesh, ctx->v_sorted, g, ctx->Rm, st);
@@ -324,6 +329,9 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   else p3m_default_opts(&o);
   if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
   if (o.precision != P3M_FP64 && o.precision != P3M_FP32C) return P3M_EINVAL;
+  if (o.mesh_precision != P3M_MESH_AUTO && o.mesh_precision != P3M_MESH_F32 &&
+      o.mesh_precision != P3M_MESH_F64)
+    return P3M_EINVAL;
   if (!(o.m > 0) || !std::isfinite(o.ke) || !std::isfinite(o.q)) return P3M_EINVAL;
   if (!(r_cut > 0) || !std::isfinite(r_cut) || !(split >= 0) || !std::isfinite(split)) return P3M_EINVAL;
   for (int d = 0; d < 3; ++d) {
@@ -334,6 +342,11 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   if (!ctx) return P3M_ENOMEM;
   ctx->opts = o;
   ctx->keep_mesh = o.keep_mesh != 0;
+  if (o.precision == P3M_FP32C)
+    ctx->mesh64 = o.mesh_precision == P3M_MESH_F64 ||
+                  (o.mesh_precision == P3M_MESH_AUTO &&
+                   (grid[0] > P3M_MESH_AUTO_F32_MAX || grid[1] > P3M_MESH_AUTO_F32_MAX ||
+                    grid[2] > P3M_MESH_AUTO_F32_MAX));
   Geo& g = ctx->geo;
   g.rc = r_cut;
   g.kappa = split * r_cut;

@@ -48,8 +48,9 @@ void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
                    double* out_sorted, hipStream_t st);
 
 // ---- mesh assignment (mesh.hip) --------------------------------------------
-template <typename R>
-void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, R* Q,
+// Deposit into a mesh of type M (float or double) from records of type R.
+template <typename R, typename M>
+void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st);
 // Gather modes: write the total force, the two parts, or (step) total + half kick.
 struct GatherOut {
@@ -59,9 +60,9 @@ struct GatherOut {
   double* p;        // momenta to kick by half_dt * f (may be NULL)
   double half_dt;
 };
-template <typename R>
+template <typename R, typename M>
 void launch_gather(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
-                   const uint32_t* perm, const Geo& geo, const Place* pl, const R* phi,
+                   const uint32_t* perm, const Geo& geo, const Place* pl, const M* phi,
                    GatherOut out, double* energy, hipStream_t st);
 void launch_deposit_grad(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,
                          const double* v_sorted, const Geo& geo, double* R, hipStream_t st);

@@ -65,13 +65,13 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-template <typename R, int ORDER>
+template <typename R, typename M, int ORDER>
 __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>* __restrict__ pp,
                                                       const MeshRec<R>* __restrict__ mesh, Geo geo,
-                                                      R* __restrict__ Q) {
-  constexpr int kTileNodes = 32768 / (int)sizeof(R);
+                                                      M* __restrict__ Q) {
+  constexpr int kTileNodes = 32768 / (int)sizeof(M);
   constexpr int NS = ORDER + 1;
-  __shared__ R tile[kTileNodes];
+  __shared__ M tile[kTileNodes];
   __shared__ int red[6];
   const int t = threadIdx.x;
   const int nx = geo.grid[0], ny = geo.grid[1];
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>*
   const int e0 = red[3] - o0 + NS, e1 = red[4] - o1 + NS, e2 = red[5] - o2 + NS;
   const long long vol = (long long)e0 * e1 * e2;
   if (vol <= kTileNodes) {
-    for (int e = t; e < vol; e += kThreads) tile[e] = (R)0;
+    for (int e = t; e < vol; e += kThreads) tile[e] = (M)0;
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kDepItems; ++it) {
@@ -126,13 +126,13 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>*
         for (int bb = 0; bb < NS; ++bb) {
           const R wyz = q[it] * S.w[1][bb] * S.w[2][c];
 #pragma unroll
-          for (int a = 0; a < NS; ++a) atomicAdd(&tile[tb + (c * e1 + bb) * e0 + a], wyz * S.w[0][a]);
+          for (int a = 0; a < NS; ++a) atomicAdd(&tile[tb + (c * e1 + bb) * e0 + a], (M)(wyz * S.w[0][a]));
         }
     }
     __syncthreads();
     for (int e = t; e < vol; e += kThreads) {
-      const R v = tile[e];
-      if (v != (R)0) {
+      const M v = tile[e];
+      if (v != (M)0) {
         const int ex = e % e0, ey = (e / e0) % e1, ez = e / (e0 * e1);
         atomicAdd(Q + ((long long)(o2 + ez) * ny + (o1 + ey)) * nx + (o0 + ex), v);
       }
@@ -147,41 +147,43 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>*
 #pragma unroll
         for (int bb = 0; bb < NS; ++bb) {
           const R wyz = q[it] * S.w[1][bb] * S.w[2][c];
-          R* row = Q + m[it].base + c * nxy + (long long)bb * nx;
+          M* row = Q + m[it].base + c * nxy + (long long)bb * nx;
 #pragma unroll
-          for (int a = 0; a < NS; ++a) atomicAdd(row + a, wyz * S.w[0][a]);
+          for (int a = 0; a < NS; ++a) atomicAdd(row + a, (M)(wyz * S.w[0][a]));
         }
     }
   }
 }
 
-template <typename R, int ORDER>
+// The stencil sums run in the mesh precision M (the potential differences
+// that make the force are small against the potential itself).
+template <typename R, typename M, int ORDER>
 __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPRec<R>* __restrict__ pp,
                                                      const MeshRec<R>* __restrict__ mesh,
                                                      const PPRec<R>* __restrict__ fpp,
                                                      const uint32_t* __restrict__ perm, Geo geo,
                                                      const Place* __restrict__ pl,
-                                                     const R* __restrict__ phi, GatherOut out,
+                                                     const M* __restrict__ phi, GatherOut out,
                                                      double* __restrict__ energy) {
   const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   double e_acc = 0.0;
   if (j < n) {
     const MeshRec<R> m = mesh[j];
     const R q = pp[j].w;
-    Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
+    Stencil<M, ORDER> S((M)m.fx, (M)m.fy, (M)m.fz);
     const int nx = geo.grid[0];
     const long long nxy = (long long)nx * geo.grid[1];
-    R g[3] = {0, 0, 0};
-    R pot = 0;
+    M g[3] = {0, 0, 0};
+    M pot = 0;
 #pragma unroll
     for (int c = 0; c < S.N; ++c)
 #pragma unroll
       for (int b = 0; b < S.N; ++b) {
-        const R* row = phi + m.base + c * nxy + (long long)b * nx;
-        R sx = 0, sdx = 0;
+        const M* row = phi + m.base + c * nxy + (long long)b * nx;
+        M sx = 0, sdx = 0;
 #pragma unroll
         for (int a = 0; a < S.N; ++a) {
-          const R v = row[a];
+          const M v = row[a];
           sx += v * S.w[0][a];
           sdx += v * S.dw[0][a];
         }
@@ -312,24 +314,24 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) /
 
 }  // namespace
 
-template <typename R>
-void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, R* Q,
+template <typename R, typename M>
+void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st) {
   const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
   if (geo.order == 1)
-    k_deposit<R, 1><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, M, 1><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
   else
-    k_deposit<R, 2><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, M, 2><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
 }
 
-template <typename R>
+template <typename R, typename M>
 void launch_gather(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
-                   const uint32_t* perm, const Geo& geo, const Place* pl, const R* phi,
+                   const uint32_t* perm, const Geo& geo, const Place* pl, const M* phi,
                    GatherOut out, double* energy, hipStream_t st) {
   if (geo.order == 1)
-    k_gather<R, 1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
+    k_gather<R, M, 1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
   else
-    k_gather<R, 2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
+    k_gather<R, M, 2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
 }
 
 void launch_deposit_grad(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,
@@ -359,16 +361,16 @@ void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale
   k_mesh_export<R><<<blocks_for(count), kThreads, 0, st>>>(count, src, pl, scale_phi, out);
 }
 
-template void launch_deposit<float>(int64_t, const PPRec<float>*, const MeshRec<float>*, const Geo&,
-                                    float*, hipStream_t);
-template void launch_deposit<double>(int64_t, const PPRec<double>*, const MeshRec<double>*, const Geo&,
-                                     double*, hipStream_t);
-template void launch_gather<float>(int64_t, const PPRec<float>*, const MeshRec<float>*, const PPRec<float>*,
-                                   const uint32_t*, const Geo&, const Place*, const float*, GatherOut,
-                                   double*, hipStream_t);
-template void launch_gather<double>(int64_t, const PPRec<double>*, const MeshRec<double>*,
-                                    const PPRec<double>*, const uint32_t*, const Geo&, const Place*,
-                                    const double*, GatherOut, double*, hipStream_t);
+#define P3M_MESH_INST(R, M)                                                                        \
+  template void launch_deposit<R, M>(int64_t, const PPRec<R>*, const MeshRec<R>*, const Geo&, M*,         \
+                                     hipStream_t);                                                        \
+  template void launch_gather<R, M>(int64_t, const PPRec<R>*, const MeshRec<R>*, const PPRec<R>*,        \
+                                    const uint32_t*, const Geo&, const Place*, const M*, GatherOut,       \
+                                    double*, hipStream_t);
+P3M_MESH_INST(float, float)
+P3M_MESH_INST(float, double)
+P3M_MESH_INST(double, double)
+#undef P3M_MESH_INST
 template void launch_mesh_export<float>(const Geo&, const float*, const Place*, int, double*, hipStream_t);
 template void launch_mesh_export<double>(const Geo&, const double*, const Place*, int, double*, hipStream_t);
 

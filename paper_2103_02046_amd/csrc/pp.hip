@@ -159,16 +159,17 @@ template <>
 struct Vec4<double> { using T = double4; };
 
 constexpr int kWaveGroups = 4;           // groups per wave (16 lanes each)
-constexpr int kSlabs = 4;                // slabs of quads per XCD
+constexpr int kRun = 8;                  // consecutive candidates read together
 constexpr int kTileK = 64;               // candidates per group per tile
 constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
 
 // Pair forces of four groups in one wave (lanes 16q .. 16q+15 hold the
 // targets of group q).
 // The candidates of a group are the concatenation of its 9 row ranges, L of
-// them. With S = ceil(L / 64) tiles, tile t holds candidates t, t+S, t+2S, ...:
-// an evenly spread sample of the whole neighbourhood, so the hits of a tile
-// spread evenly over the group's targets. Per tile:
+// them, read in runs of 8 consecutive ones (8 lanes, 128 contiguous bytes).
+// With S = ceil(L / 64) tiles, tile t holds runs t, t+S, ..., t+7S: an evenly
+// spread sample of the whole neighbourhood, so the hits of a tile spread
+// evenly over the group's targets. Per tile:
 //   1. each group stages its 64 candidates in LDS (loaded one tile ahead);
 //   2. each lane tests its group's 64 candidates against its target, with
 //      positions relative to the group's first cell corner (a few cell
@@ -193,18 +194,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
   __shared__ V4 toff[NT];      // cell-corner offset from the group's first cell (exact)
   __shared__ int rstart[kWaveGroups][9], rpre[kWaveGroups][10];
   __shared__ int gtot[kWaveGroups];
-  // XCD-aware order: work-groups are dealt round-robin to the 8 XCDs. The
-  // quads (in cell order: spatial neighbours) are cut into 8 kSlabs slabs;
-  // XCD x takes slabs x, x + 8, ..., one after another, so its L2 holds the
-  // particles of the slab being worked on for all their re-reads, and every
-  // XCD gets slabs from all over the bunch (balanced work).
   const int ngroups = counter[0];
-  const int nquads = (ngroups + kWaveGroups - 1) / kWaveGroups;
-  const int qps = (nquads + kXcds * kSlabs - 1) / (kXcds * kSlabs);   // quads per slab
-  const int local = blockIdx.x / kXcds;
-  if (local >= qps * kSlabs) return;
-  const int quad = ((local / qps) * kXcds + (int)(blockIdx.x % kXcds)) * qps + local % qps;
-  const int gbase = quad * kWaveGroups;
+  const int gbase = blockIdx.x * kWaveGroups;
   if (gbase >= ngroups) return;
   const int lane = threadIdx.x, q = lane >> 4, ql = lane & 15;
   const int gid = gbase + q;
@@ -264,12 +255,13 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
   const int S = (L + kTileK - 1) / kTileK;
   const int nt = max(max((gtot[0] + kTileK - 1) / kTileK, (gtot[1] + kTileK - 1) / kTileK),
                      max((gtot[2] + kTileK - 1) / kTileK, (gtot[3] + kTileK - 1) / kTileK));
-  // slot 16h + ql of tile t holds candidate (16h + ql) S + t; its row range
-  // index advances monotonically with t
+  // slot s = 16h + ql of tile t holds candidate ((s/8) S + t) 8 + s%8; it
+  // advances by 8 per tile and its row range index monotonically
   int cq[kPerLane], cr[kPerLane];
 #pragma unroll
   for (int h = 0; h < kPerLane; ++h) {
-    cq[h] = (16 * h + ql) * S;
+    const int slot = 16 * h + ql;
+    cq[h] = (slot / kRun) * S * kRun + slot % kRun;
     int r = 0;
 #pragma unroll
     for (int k = 1; k < 9; ++k) r += (cq[h] >= rpre[q][k]) ? 1 : 0;
@@ -281,7 +273,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
   auto fetch = [&](int t) {
 #pragma unroll
     for (int h = 0; h < kPerLane; ++h) {
-      const int qi = cq[h] + t;
+      const int qi = cq[h] + kRun * t;
       nx_ok[h] = t < S && qi < L;
       if (nx_ok[h]) {
         while (qi >= rpre[q][cr[h] + 1]) ++cr[h];
@@ -473,11 +465,8 @@ void launch_pp(int64_t n, const PPRec<R>* rec, const uint32_t* keys, const int* 
   k_pp_groups_count<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot);
   k_pp_groups_scan<<<1, kThreads, 0, st>>>(btot, cb, counter);
   k_pp_groups_emit<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot, desc);
-  // one wave per quad of groups, XCD-major slab order; waves beyond the
-  // groups built leave at once
-  const long long qb = (pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups;
-  const long long per = kSlabs * ((qb + kXcds * kSlabs - 1) / (kXcds * kSlabs));
-  const unsigned blocks = (unsigned)(kXcds * per);
+  // one wave per quad of groups; waves beyond the groups built leave at once
+  const unsigned blocks = (unsigned)((pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups);
   if (energy)
     k_pp<R, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
   else

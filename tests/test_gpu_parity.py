@@ -138,6 +138,25 @@ def test_fp32c_parity_aniso():
     assert e < TOL32 and e_pp < TOL32 and e_pm < TOL32
 
 
+def test_mesh_precision_option():
+    """FP32C with a float64 mesh reproduces the float64 mesh force to rounding
+    of the float32 records; explicit float32 and float64 meshes both run."""
+    wl = small_aniso(n=1 << 15, grid=32)
+    x, _ = wl.draw()
+    xd = dev(x)
+    f64 = ctx_for(wl, p3m.FP64).forces_parts(xd)[1]
+    e = {}
+    for mp in (p3m.MESH_F32, p3m.MESH_F64, p3m.MESH_AUTO):
+        fpm = ctx_for(wl, p3m.FP32C, mesh_precision=mp).forces_parts(xd)[1]
+        e[mp] = rms_err(host(fpm), host(f64))
+    print("mesh force error vs float64 by mesh precision", e)
+    assert e[p3m.MESH_F64] < 1e-6 and e[p3m.MESH_F32] < TOL32
+    # 32^3 mesh: auto takes float32 (same error level, not that of float64)
+    assert e[p3m.MESH_AUTO] > 100 * e[p3m.MESH_F64]
+    with pytest.raises(p3m.P3MError):
+        ctx_for(wl, p3m.FP32C, mesh_precision=7)
+
+
 def test_fp32c_vs_fp64_same_gpu():
     wl = small_aniso(n=1 << 16, grid=64)
     x, _ = wl.draw()
