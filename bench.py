@@ -1,7 +1,7 @@
 """Throughput of the P3M leapfrog step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload aniso1m]
-                    [--precision fp32c|fp64] [--cpu-steps 2] [--no-cpu-baseline]
+                    [--precision fp32c|fp64] [--cpu-steps 6] [--no-cpu-baseline]
 
 One step = one kick-drift-kick leapfrog step of the whole bunch: push,
 placement, linked-cell sort, PP pair forces, deposit, FFT convolution,
@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="aniso1m")
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp64"])
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")

@@ -25,7 +25,7 @@ constexpr double kCLight = 299792458.0;
 template <typename R>
 struct Engine {
   // per-particle
-  PPRec<R>* pp = nullptr;
+  PPPos<R>* pp = nullptr;
   MeshRec<R>* mesh = nullptr;
   PPRec<R>* fpp = nullptr;
   // mesh

@@ -65,9 +65,19 @@ template <typename T>
 __device__ __forceinline__ C2<T> cmul_mi(C2<T> a) { return {a.y, -a.x}; }
 
 // Sorted particle records.
-template <typename R> struct PPRec;              // position in the own PP cell + weight
+template <typename R> struct PPRec;              // per-particle vector + weight (PP force output)
 template <> struct alignas(16) PPRec<float> { float x, y, z, w; };
 template <> struct alignas(32) PPRec<double> { double x, y, z, w; };
+
+// Position in the own PP cell + weight. float form: fixed point, the cell
+// edge per axis is 2^kFixBits units, so separations of particles in
+// neighbouring cells are exact integers (rounded once, to float, after the
+// subtraction). double form: offset from the cell corner in units of Lu.
+constexpr int kFixBits = 29;
+struct alignas(16) PPFix { int x, y, z; float w; };
+template <typename R> struct PPPosOf { using type = PPRec<R>; };
+template <> struct PPPosOf<float> { using type = PPFix; };
+template <typename R> using PPPos = typename PPPosOf<R>::type;
 
 template <typename R> struct MeshRec;            // stencil origin node + fractional offsets
 template <> struct alignas(16) MeshRec<float> { float fx, fy, fz; int base; };

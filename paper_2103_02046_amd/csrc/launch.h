@@ -29,7 +29,7 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
                       uint32_t** keys, uint32_t** perm, hipStream_t st);
 template <typename R>
 void launch_reorder(int64_t n, const double* x, const double* qw, const uint32_t* perm,
-                    const uint32_t* keys, const Place* pl, const Geo& geo, PPRec<R>* pp,
+                    const uint32_t* keys, const Place* pl, const Geo& geo, PPPos<R>* pp,
                     MeshRec<R>* mesh, int* status, hipStream_t st);
 template <typename R>
 void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out, hipStream_t st);
@@ -40,7 +40,7 @@ int pp_group_bound(int64_t n, const Geo& geo);
 // Ints of scratch the group builder needs.
 int pp_scratch_ints(const Geo& geo);
 template <typename R>
-void launch_pp(int64_t n, const PPRec<R>* rec, const uint32_t* keys, const int* cell_start,
+void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, int2* desc, int* counter, int* scratch, PPRec<R>* out, double* energy,
                hipStream_t st);
 void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
@@ -50,7 +50,7 @@ void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
 // ---- mesh assignment (mesh.hip) --------------------------------------------
 // Deposit into a mesh of type M (float or double) from records of type R.
 template <typename R, typename M>
-void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
+void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st);
 // Gather modes: write the total force, the two parts, or (step) total + half kick.
 struct GatherOut {
@@ -61,7 +61,7 @@ struct GatherOut {
   double half_dt;
 };
 template <typename R, typename M>
-void launch_gather(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
+void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
                    const uint32_t* perm, const Geo& geo, const Place* pl, const M* phi,
                    GatherOut out, double* energy, hipStream_t st);
 void launch_deposit_grad(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,

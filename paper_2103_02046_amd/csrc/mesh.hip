@@ -66,7 +66,7 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 template <typename R, typename M, int ORDER>
-__global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>* __restrict__ pp,
+__global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>* __restrict__ pp,
                                                       const MeshRec<R>* __restrict__ mesh, Geo geo,
                                                       M* __restrict__ Q) {
   constexpr int kTileNodes = 32768 / (int)sizeof(M);
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPRec<R>*
 // The stencil sums run in the mesh precision M (the potential differences
 // that make the force are small against the potential itself).
 template <typename R, typename M, int ORDER>
-__global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPRec<R>* __restrict__ pp,
+__global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* __restrict__ pp,
                                                      const MeshRec<R>* __restrict__ mesh,
                                                      const PPRec<R>* __restrict__ fpp,
                                                      const uint32_t* __restrict__ perm, Geo geo,
@@ -315,7 +315,7 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) /
 }  // namespace
 
 template <typename R, typename M>
-void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
+void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st) {
   const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
   if (geo.order == 1)
@@ -325,7 +325,7 @@ void launch_deposit(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const
 }
 
 template <typename R, typename M>
-void launch_gather(int64_t n, const PPRec<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
+void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
                    const uint32_t* perm, const Geo& geo, const Place* pl, const M* phi,
                    GatherOut out, double* energy, hipStream_t st) {
   if (geo.order == 1)
@@ -362,9 +362,9 @@ void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale
 }
 
 #define P3M_MESH_INST(R, M)                                                                        \
-  template void launch_deposit<R, M>(int64_t, const PPRec<R>*, const MeshRec<R>*, const Geo&, M*,         \
+  template void launch_deposit<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const Geo&, M*,         \
                                      hipStream_t);                                                        \
-  template void launch_gather<R, M>(int64_t, const PPRec<R>*, const MeshRec<R>*, const PPRec<R>*,        \
+  template void launch_gather<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const PPRec<R>*,          \
                                     const uint32_t*, const Geo&, const Place*, const M*, GatherOut,       \
                                     double*, hipStream_t);
 P3M_MESH_INST(float, float)

@@ -15,6 +15,8 @@
 // 2e-16 of their value at 0), the exp(-x^2) shared with the second term;
 // per-particle sums are Kahan compensated. double form: the device
 // library's erfc and exp.
+#include <type_traits>
+
 #include "erfcx_fit.h"
 #include "launch.h"
 
@@ -174,14 +176,16 @@ constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
 //   2. each lane tests its group's 64 candidates against its target, with
 //      positions relative to the group's first cell corner (a few cell
 //      edges at most): a 64-bit hit mask;
-//   3. each lane evaluates its own hits, the separation formed from
-//      cell-local positions plus the cell-corner offsets (at most two cell
-//      edges, exact multiples), so its float rounding is that of one cell
-//      edge; the tile sum is added to the per-particle total with Kahan
-//      compensation (float form).
+//   3. each lane evaluates its own hits from the exact separation: in the
+//      float form the difference of fixed-point positions relative to the
+//      group's first cell corner (cell offsets are whole multiples of
+//      2^kFixBits), an integer rounded once to float; in the double form
+//      cell-local positions plus cell-corner offsets (exact multiples of the
+//      cell edge). The tile sum is added to the per-particle total with
+//      Kahan compensation (float form).
 template <typename R, bool ENERGY>
 __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* __restrict__ counter,
-                                           const PPRec<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
+                                           const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
                                            const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
                                            double* __restrict__ energy) {
   using V4 = typename Vec4<R>::T;
@@ -189,9 +193,11 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
   // reads fall in different LDS banks
   constexpr int TS = kTileK + 1;
   constexpr int NT = kWaveGroups * TS;
-  __shared__ V4 tile[NT];      // group-relative x, y, z (cutoff test)
-  __shared__ V4 tloc[NT];      // cell-local x, y, z and the charge weight
-  __shared__ V4 toff[NT];      // cell-corner offset from the group's first cell (exact)
+  constexpr bool kFix = std::is_same<R, float>::value;
+  __shared__ V4 tile[NT];                   // group-relative x, y, z (cutoff test)
+  __shared__ int4 tfix[kFix ? NT : 1];      // float: fixed-point x, y, z from the group's corner; weight bits
+  __shared__ V4 tloc[kFix ? 1 : NT];        // double: cell-local x, y, z and the charge weight
+  __shared__ V4 toff[kFix ? 1 : NT];        // double: cell-corner offset from the group's first cell
   __shared__ int rstart[kWaveGroups][9], rpre[kWaveGroups][10];
   __shared__ int gtot[kWaveGroups];
   const int ngroups = counter[0];
@@ -204,6 +210,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
   if (gvalid) gd = desc[gid];
   const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
   const R cux = (R)geo.cu[0], cuy = (R)geo.cu[1], cuz = (R)geo.cu[2];
+  constexpr int kOne = 1 << kFixBits;
+  const R fsx = (R)(geo.cu[0] / kOne), fsy = (R)(geo.cu[1] / kOne), fsz = (R)(geo.cu[2] / kOne);
   int cx0 = 0, cy = 0, cz = 0;
   if (gvalid) {
     const uint32_t k0 = keys[gd.x];
@@ -239,18 +247,34 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
   // the target of this lane
   const bool active = gvalid && ql < gd.y;
   R lx = 0, ly = 0, lz = 0, tw = 0;
+  int ix = 0, iy = 0, iz = 0;
   int tdc = 0;
   if (active) {
     const int j = gd.x + ql;
-    const PPRec<R> me = rec[j];
-    tdc = (int)(keys[j] % (uint32_t)nx) - cx0;
-    lx = me.x;
-    ly = me.y;
-    lz = me.z;
+    const PPPos<R> me = rec[j];
+    tdc = (int)(keys[j] % (uint32_t)nx) - cx0;   // 0: every target of a group is in its first cell
+    if constexpr (kFix) {
+      ix = me.x + tdc * kOne;
+      iy = me.y;
+      iz = me.z;
+    } else {
+      lx = me.x;
+      ly = me.y;
+      lz = me.z;
+    }
     tw = me.w;
   }
-  const R tox = (R)tdc * cux;   // 0: every target of a group is in its first cell
-  const R tx = active ? lx + tox : (R)1e18, ty = ly, tz = lz;
+  const R tox = (R)tdc * cux;
+  R tx, ty, tz;
+  if constexpr (kFix) {
+    tx = active ? (R)ix * fsx : (R)1e18;
+    ty = (R)iy * fsy;
+    tz = (R)iz * fsz;
+  } else {
+    tx = active ? lx + tox : (R)1e18;
+    ty = ly;
+    tz = lz;
+  }
   const int L = gtot[q];
   const int S = (L + kTileK - 1) / kTileK;
   const int nt = max(max((gtot[0] + kTileK - 1) / kTileK, (gtot[1] + kTileK - 1) / kTileK),
@@ -267,7 +291,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
     for (int k = 1; k < 9; ++k) r += (cq[h] >= rpre[q][k]) ? 1 : 0;
     cr[h] = r;
   }
-  PPRec<R> nx_o[kPerLane];
+  PPPos<R> nx_o[kPerLane];
   int nx_c[kPerLane];
   bool nx_ok[kPerLane];
   auto fetch = [&](int t) {
@@ -293,18 +317,31 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
     // 1. stage the prefetched candidates
 #pragma unroll
     for (int h = 0; h < kPerLane; ++h) {
-      V4 c{(R)1e18, (R)0, (R)0, (R)0}, cl{(R)0, (R)0, (R)0, (R)0}, co{(R)0, (R)0, (R)0, (R)0};
-      if (nx_ok[h]) {
-        const int dy = cr[h] % 3 - 1, dz = cr[h] / 3 - 1;
-        cl = V4{nx_o[h].x, nx_o[h].y, nx_o[h].z, nx_o[h].w};
-        co = V4{(R)nx_c[h] * cux, (R)dy * cuy, (R)dz * cuz, (R)0};
-        c.x = cl.x + co.x;
-        c.y = cl.y + co.y;
-        c.z = cl.z + co.z;
+      V4 c{(R)1e18, (R)0, (R)0, (R)0};
+      const int dy = cr[h] % 3 - 1, dz = cr[h] / 3 - 1;
+      if constexpr (kFix) {
+        int4 fx = make_int4(0, 0, 0, 0);
+        if (nx_ok[h]) {
+          fx = make_int4(nx_o[h].x + nx_c[h] * kOne, nx_o[h].y + dy * kOne, nx_o[h].z + dz * kOne,
+                         __float_as_int(nx_o[h].w));
+          c.x = (R)fx.x * fsx;
+          c.y = (R)fx.y * fsy;
+          c.z = (R)fx.z * fsz;
+        }
+        tfix[TS * q + 16 * h + ql] = fx;
+      } else {
+        V4 cl{(R)0, (R)0, (R)0, (R)0}, co{(R)0, (R)0, (R)0, (R)0};
+        if (nx_ok[h]) {
+          cl = V4{nx_o[h].x, nx_o[h].y, nx_o[h].z, nx_o[h].w};
+          co = V4{(R)nx_c[h] * cux, (R)dy * cuy, (R)dz * cuz, (R)0};
+          c.x = cl.x + co.x;
+          c.y = cl.y + co.y;
+          c.z = cl.z + co.z;
+        }
+        tloc[TS * q + 16 * h + ql] = cl;
+        toff[TS * q + 16 * h + ql] = co;
       }
       tile[TS * q + 16 * h + ql] = c;
-      tloc[TS * q + 16 * h + ql] = cl;
-      toff[TS * q + 16 * h + ql] = co;
     }
     __syncthreads();
     fetch(t + 1);
@@ -343,15 +380,25 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* _
         m1 &= ~(0x80000000u >> b);
         k = 32 + b;
       }
-      const V4 cl = tloc[TS * q + k];
-      const V4 co = toff[TS * q + k];
-      const R dx = (lx - cl.x) + (tox - co.x);
-      const R dy = (ly - cl.y) - co.y;
-      const R dz = (lz - cl.z) - co.z;
+      R dx, dy, dz, wj;
+      if constexpr (kFix) {
+        const int4 cf = tfix[TS * q + k];
+        dx = (R)(ix - cf.x) * fsx;
+        dy = (R)(iy - cf.y) * fsy;
+        dz = (R)(iz - cf.z) * fsz;
+        wj = __int_as_float(cf.w);
+      } else {
+        const V4 cl = tloc[TS * q + k];
+        const V4 co = toff[TS * q + k];
+        dx = (lx - cl.x) + (tox - co.x);
+        dy = (ly - cl.y) - co.y;
+        dz = (lz - cl.z) - co.z;
+        wj = cl.w;
+      }
       const R r2 = dx * dx + dy * dy + dz * dz;
       if (r2 > (R)0 && r2 < (R)1) {
         R ep;
-        const R g = pair_scalar(r2, cl.w, kappa, c2k, ENERGY ? &ep : nullptr);
+        const R g = pair_scalar(r2, wj, kappa, c2k, ENERGY ? &ep : nullptr);
         sx += g * dx;
         sy += g * dy;
         sz += g * dz;
@@ -455,7 +502,7 @@ int pp_scratch_ints(const Geo& geo) {
 }
 
 template <typename R>
-void launch_pp(int64_t n, const PPRec<R>* rec, const uint32_t* keys, const int* cell_start,
+void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, int2* desc, int* counter, int* scratch, PPRec<R>* out, double* energy,
                hipStream_t st) {
   const long long nc = geo.ncells;
@@ -479,9 +526,9 @@ void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys, co
   k_pp_hvp<<<blocks, kThreads, 0, st>>>(n, rec, keys, cell_start, geo, v_sorted, out_sorted);
 }
 
-template void launch_pp<float>(int64_t, const PPRec<float>*, const uint32_t*, const int*, const Geo&,
+template void launch_pp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
                                int2*, int*, int*, PPRec<float>*, double*, hipStream_t);
-template void launch_pp<double>(int64_t, const PPRec<double>*, const uint32_t*, const int*, const Geo&,
+template void launch_pp<double>(int64_t, const PPPos<double>*, const uint32_t*, const int*, const Geo&,
                                 int2*, int*, int*, PPRec<double>*, double*, hipStream_t);
 
 }  // namespace p3m

@@ -153,10 +153,31 @@ __global__ void k_cell_start(int64_t n, const uint32_t* __restrict__ keys, int* 
 }
 
 template <typename R>
+__device__ __forceinline__ PPPos<R> make_pos(const double* loc, const double* cu, double w);
+template <>
+__device__ __forceinline__ PPPos<double> make_pos<double>(const double* loc, const double*, double w) {
+  return PPPos<double>{loc[0], loc[1], loc[2], w};
+}
+// Nearest fixed-point value. Inside the mesh a particle lies in [0, 1] cell
+// edges of its cell's corner; one outside it (reported as a domain error)
+// is clamped to [-1/2, 3/2) edges, which keeps every PP separation, cell
+// offsets included, below 2^31 units.
+template <>
+__device__ __forceinline__ PPPos<float> make_pos<float>(const double* loc, const double* cu, double w) {
+  int v[3];
+  for (int d = 0; d < 3; ++d) {
+    double u = loc[d] / cu[d];
+    u = fmin(fmax(u, -0.5), 1.4999999);
+    v[d] = (int)rint(u * (double)(1 << kFixBits));
+  }
+  return PPFix{v[0], v[1], v[2], (float)w};
+}
+
+template <typename R>
 __global__ void __launch_bounds__(kThreads) k_reorder(
     int64_t n, const double* __restrict__ x, const double* __restrict__ qw,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ keys,
-    const Place* __restrict__ pl, Geo geo, PPRec<R>* __restrict__ pp, MeshRec<R>* __restrict__ mesh,
+    const Place* __restrict__ pl, Geo geo, PPPos<R>* __restrict__ pp, MeshRec<R>* __restrict__ mesh,
     int* __restrict__ status) {
   int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (j >= n) return;
@@ -168,14 +189,11 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
                     (int)(key / ((uint32_t)geo.ncell[0] * (uint32_t)geo.ncell[1]))};
   double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
   const double w = qw ? qw[i] : 1.0;
-  // PP record: offset from the own cell corner in units of the cutoff Lu,
-  // formed in float64 before rounding.
-  PPRec<R> r;
-  r.x = (R)((xi[0] - P.x0[0]) * P.inv_lu - c[0] * geo.cu[0]);
-  r.y = (R)((xi[1] - P.x0[1]) * P.inv_lu - c[1] * geo.cu[1]);
-  r.z = (R)((xi[2] - P.x0[2]) * P.inv_lu - c[2] * geo.cu[2]);
-  r.w = (R)w;
-  pp[j] = r;
+  // PP record: offset from the own cell corner, formed in float64 before
+  // rounding (units of Lu, or fixed point of the cell edge).
+  double loc[3];
+  for (int d = 0; d < 3; ++d) loc[d] = (xi[d] - P.x0[d]) * P.inv_lu - c[d] * geo.cu[d];
+  pp[j] = make_pos<R>(loc, geo.cu, w);
   // Mesh record: stencil origin and fractional offset (Sec. 2.4.2 B-splines).
   // CIC: base floor(u), offset u - base in [0, 1).
   // TSC: centre floor(u + 1/2), offset u - centre in [-1/2, 1/2), base centre - 1.
@@ -251,7 +269,7 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
 
 template <typename R>
 void launch_reorder(int64_t n, const double* x, const double* qw, const uint32_t* perm,
-                    const uint32_t* keys, const Place* pl, const Geo& geo, PPRec<R>* pp,
+                    const uint32_t* keys, const Place* pl, const Geo& geo, PPPos<R>* pp,
                     MeshRec<R>* mesh, int* status, hipStream_t st) {
   k_reorder<R><<<blocks_for(n), kThreads, 0, st>>>(n, x, qw, perm, keys, pl, geo, pp, mesh, status);
 }
@@ -262,10 +280,10 @@ void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out
 }
 
 template void launch_reorder<float>(int64_t, const double*, const double*, const uint32_t*,
-                                    const uint32_t*, const Place*, const Geo&, PPRec<float>*,
+                                    const uint32_t*, const Place*, const Geo&, PPPos<float>*,
                                     MeshRec<float>*, int*, hipStream_t);
 template void launch_reorder<double>(int64_t, const double*, const double*, const uint32_t*,
-                                     const uint32_t*, const Place*, const Geo&, PPRec<double>*,
+                                     const uint32_t*, const Place*, const Geo&, PPPos<double>*,
                                      MeshRec<double>*, int*, hipStream_t);
 template void launch_sort_vector<float>(int64_t, const double*, const uint32_t*, float*, hipStream_t);
 template void launch_sort_vector<double>(int64_t, const double*, const uint32_t*, double*, hipStream_t);
