@@ -202,8 +202,9 @@ p3m_status p3m_mesh(p3m_ctx *ctx, int32_t which, double *out, void *stream);
 
 /* Stage timing with HIP events recorded on the calling stream around every
  * stage of every evaluation, for at most max_records stage launches:
- *   0 push + placement, 1 linked-cell sort, 2 reorder, 3 PP pair forces,
- *   4 deposit, 5 FFT convolution (five passes), 6 gather.
+ *   0 push + placement, 1 linked-cell sort and PP work groups, 2 reorder,
+ *   3 PP pair forces (the pair kernel alone), 4 deposit, 5 FFT convolution
+ *   (five passes), 6 gather.
  * p3m_profile_end synchronises `stream`, writes the summed milliseconds and
  * the number of timed launches per stage (arrays of 8, host) and stops. */
 p3m_status p3m_profile_begin(p3m_ctx *ctx, int32_t max_records);

@@ -235,6 +235,7 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   {
     StageTimer t(ctx, 1, st);
     launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
+    launch_pp_groups(ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, ctx->group_scratch, st);
   }
   {
     StageTimer t(ctx, 2, st);
@@ -242,8 +243,7 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   }
   {
     StageTimer t(ctx, 3, st);
-    launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, ctx->group_scratch,
-                 E.fpp, e_pp, st);
+    launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, E.fpp, e_pp, st);
   }
   {
     StageTimer t(ctx, 4, st);

@@ -39,9 +39,13 @@ void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out
 int pp_group_bound(int64_t n, const Geo& geo);
 // Ints of scratch the group builder needs.
 int pp_scratch_ints(const Geo& geo);
+// Work groups of the PP kernel (runs of at most 16 particles of one cell, in
+// cell order) from the cell starts; counter[0] receives their number.
+void launch_pp_groups(const int* cell_start, const Geo& geo, int2* desc, int* counter, int* scratch,
+                      hipStream_t st);
 template <typename R>
 void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
-               const Geo& geo, int2* desc, int* counter, int* scratch, PPRec<R>* out, double* energy,
+               const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
                hipStream_t st);
 void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
                    const int* cell_start, const Geo& geo, const double* v_sorted,

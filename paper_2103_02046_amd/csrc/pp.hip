@@ -184,7 +184,7 @@ constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
 //      cell edge). The tile sum is added to the per-particle total with
 //      Kahan compensation (float form).
 template <typename R, bool ENERGY>
-__global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, int* __restrict__ counter,
+__global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter,
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
                                            const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
                                            double* __restrict__ energy) {
@@ -501,10 +501,8 @@ int pp_scratch_ints(const Geo& geo) {
   return (int)(geo.ncells + (geo.ncells + kThreads - 1) / kThreads);
 }
 
-template <typename R>
-void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
-               const Geo& geo, int2* desc, int* counter, int* scratch, PPRec<R>* out, double* energy,
-               hipStream_t st) {
+void launch_pp_groups(const int* cell_start, const Geo& geo, int2* desc, int* counter, int* scratch,
+                      hipStream_t st) {
   const long long nc = geo.ncells;
   const int cb = (int)((nc + kThreads - 1) / kThreads);
   int* celloff = scratch;
@@ -512,6 +510,12 @@ void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* 
   k_pp_groups_count<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot);
   k_pp_groups_scan<<<1, kThreads, 0, st>>>(btot, cb, counter);
   k_pp_groups_emit<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot, desc);
+}
+
+template <typename R>
+void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
+               const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
+               hipStream_t st) {
   // one wave per quad of groups; waves beyond the groups built leave at once
   const unsigned blocks = (unsigned)((pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups);
   if (energy)
@@ -527,8 +531,8 @@ void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys, co
 }
 
 template void launch_pp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
-                               int2*, int*, int*, PPRec<float>*, double*, hipStream_t);
+                               const int2*, int*, PPRec<float>*, double*, hipStream_t);
 template void launch_pp<double>(int64_t, const PPPos<double>*, const uint32_t*, const int*, const Geo&,
-                                int2*, int*, int*, PPRec<double>*, double*, hipStream_t);
+                                const int2*, int*, PPRec<double>*, double*, hipStream_t);
 
 }  // namespace p3m
