@@ -83,8 +83,7 @@ typedef struct {
     int32_t order;      /* P3M_CIC or P3M_TSC                               [TSC]  */
     int32_t precision;  /* P3M_FP64 or P3M_FP32C                            [FP64] */
     int32_t zoom;       /* 1: zoom the mesh to fit the bunch; 0: EDOMAIN    [1]    */
-    int32_t keep_mesh;  /* 1: keep the charge mesh of the last evaluation for
-                           p3m_mesh (one extra clear per evaluation)        [0]    */
+    int32_t reserved0;  /* must be 0                                               */
     int32_t mesh_precision; /* P3M_MESH_AUTO, _F32 or _F64 (P3M_FP32C only) [AUTO] */
     int32_t reserved;   /* must be 0                                               */
     double ke;          /* Coulomb constant 1/(4 pi eps0)     [8.9875517923e9]    */

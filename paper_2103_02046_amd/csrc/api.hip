@@ -68,7 +68,6 @@ struct p3m_ctx {
   uint32_t* keys = nullptr;     // sorted keys of the last evaluation
   uint32_t* perm = nullptr;     // sorted -> caller index of the last evaluation
   int last_precision = -1;      // mesh precision of the last evaluation
-  bool keep_mesh = false;
   bool mesh64 = false;          // float32 particle path with a float64 mesh
   // stage timing
   bool prof_on = false;
@@ -247,13 +246,12 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   }
   {
     StageTimer t(ctx, 4, st);
-    if (ctx->keep_mesh) launch_fill(EM.Q, mesh_nodes(g) * sizeof(M), st);
     launch_deposit<R, M>(n, E.pp, E.mesh, g, EM.Q, st);
   }
   {
     StageTimer t(ctx, 5, st);
     const C2<M>* tw[3] = {EM.tw[0], EM.tw[1], EM.tw[2]};
-    launch_convolve<M>(g, EM.Q, EM.spec, ctx->ghat, tw, EM.phi, ctx->keep_mesh ? 0 : 1, st);
+    launch_convolve<M>(g, EM.Q, EM.spec, ctx->ghat, tw, EM.phi, st);
   }
   {
     StageTimer t(ctx, 6, st);
@@ -292,12 +290,11 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   launch_sort_vector<double>(n, v, ctx->perm, ctx->v_sorted, st);
   launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
-  launch_fill(E.Q, mesh_nodes(g) * sizeof(double), st);
   launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, st);
-  launch_convolve<double>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, 1, st);
+  launch_convolve<double>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, st);
   launch_fill(ctx->Rm, mesh_nodes(g) * sizeof(double), st);
   launch_deposit_grad(n, E.pp, E.mesh, ctx->v_sorted, g, ctx->Rm, st);
-  launch_convolve<double>(g, ctx->Rm, E.spec, ctx->ghat, tw, ctx->psi, 1, st);
+  launch_convolve<double>(g, ctx->Rm, E.spec, ctx->ghat, tw, ctx->psi, st);
   launch_gather_hvp(n, E.pp, E.mesh, ctx->hpp, ctx->v_sorted, ctx->perm, g, ctx->place, E.phi, ctx->psi,
                     out, st);
   ctx->last_precision = -1;
@@ -328,6 +325,7 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   if (opts) o = *opts;
   else p3m_default_opts(&o);
   if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
+  if (o.reserved0 != 0 || o.reserved != 0) return P3M_EINVAL;
   if (o.precision != P3M_FP64 && o.precision != P3M_FP32C) return P3M_EINVAL;
   if (o.mesh_precision != P3M_MESH_AUTO && o.mesh_precision != P3M_MESH_F32 &&
       o.mesh_precision != P3M_MESH_F64)
@@ -341,7 +339,6 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   p3m_ctx* ctx = new (std::nothrow) p3m_ctx();
   if (!ctx) return P3M_ENOMEM;
   ctx->opts = o;
-  ctx->keep_mesh = o.keep_mesh != 0;
   if (o.precision == P3M_FP32C)
     ctx->mesh64 = o.mesh_precision == P3M_MESH_F64 ||
                   (o.mesh_precision == P3M_MESH_AUTO &&
@@ -567,8 +564,6 @@ p3m_status p3m_diagnostics(p3m_ctx* ctx, int64_t n, const double* x, const doubl
 p3m_status p3m_mesh(p3m_ctx* ctx, int32_t which, double* out, void* stream) {
   if (!ctx || !out || (which != 0 && which != 1)) return P3M_EINVAL;
   if (ctx->last_precision < 0) return fail(ctx, P3M_ESTATE, "no force evaluation yet");
-  if (which == 0 && !ctx->keep_mesh)
-    return fail(ctx, P3M_ESTATE, "the charge mesh is cleared by the transform unless keep_mesh is set");
   hipStream_t st = (hipStream_t)stream;
   if (ctx->last_precision == P3M_FP32C)
     launch_mesh_export<float>(ctx->geo, which ? ctx->e32.phi : ctx->e32.Q, ctx->place, which, out, st);

@@ -134,9 +134,9 @@ __device__ __forceinline__ void fft_lines(C2<T>* s, const C2<T>* __restrict__ tw
 
 // ---- x pass, forward: two real rows -> one complex line -> two half spectra
 template <typename T, int L>
-__global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, T* __restrict__ Q,
+__global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, const T* __restrict__ Q,
                                                            C2<T>* __restrict__ S,
-                                                           const C2<T>* __restrict__ tw, int clearQ) {
+                                                           const C2<T>* __restrict__ tw) {
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2, K = N + 1;
   __shared__ C2<T> s[L * B];
@@ -150,7 +150,6 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, T* __restric
     const long long gr = row0 + r;
     if (gr < rows) {
       T v = Q[gr * N + p];
-      if (clearQ) Q[gr * N + p] = (T)0;
       if (r & 1) s[p * B + (r >> 1)].y = v;
       else s[p * B + (r >> 1)].x = v;
     }
@@ -317,11 +316,11 @@ __global__ void k_green_dct(int axis, Geo geo, const double* __restrict__ in, do
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 template <typename T, int L>
-void run_x_fwd(const Geo& g, T* Q, C2<T>* S, const C2<T>* tw, int clear, hipStream_t st) {
+void run_x_fwd(const Geo& g, const T* Q, C2<T>* S, const C2<T>* tw, hipStream_t st) {
   constexpr int B = Cfg<T, L>::B;
   long long rows = (long long)g.grid[1] * g.grid[2];
   unsigned blocks = (unsigned)((rows + 2 * B - 1) / (2 * B));
-  k_fft_x_fwd<T, L><<<blocks, kFftThreads, 0, st>>>(g, Q, S, tw, clear);
+  k_fft_x_fwd<T, L><<<blocks, kFftThreads, 0, st>>>(g, Q, S, tw);
 }
 template <typename T, int L>
 void run_x_inv(const Geo& g, const C2<T>* S, T* phi, const C2<T>* tw, hipStream_t st) {
@@ -370,10 +369,10 @@ size_t spectrum_elems(const Geo& g) {
 }
 
 template <typename R>
-void launch_convolve(const Geo& g, R* Q, C2<R>* S, const double* ghat, const C2<R>* tw[3], R* phi,
-                     int clearQ, hipStream_t st) {
+void launch_convolve(const Geo& g, const R* Q, C2<R>* S, const double* ghat, const C2<R>* tw[3], R* phi,
+                     hipStream_t st) {
   const int Lx = 2 * g.grid[0], Ly = 2 * g.grid[1], Lz = 2 * g.grid[2];
-#define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], clearQ, st)
+#define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], st)
 #define YF(L) run_y<R, L, false>(g, S, tw[1], st)
 #define ZZ(L) run_z<R, L>(g, S, ghat, tw[2], st)
 #define YI(L) run_y<R, L, true>(g, S, tw[1], st)
@@ -408,10 +407,10 @@ void build_green_table(const Geo& g, double* table, double* scratch, double* con
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(2, g, scratch, table, cosv[2], scale);
 }
 
-template void launch_convolve<float>(const Geo&, float*, C2<float>*, const double*, const C2<float>*[3],
-                                     float*, int, hipStream_t);
-template void launch_convolve<double>(const Geo&, double*, C2<double>*, const double*,
-                                      const C2<double>*[3], double*, int, hipStream_t);
+template void launch_convolve<float>(const Geo&, const float*, C2<float>*, const double*, const C2<float>*[3],
+                                     float*, hipStream_t);
+template void launch_convolve<double>(const Geo&, const double*, C2<double>*, const double*,
+                                      const C2<double>*[3], double*, hipStream_t);
 template void make_twiddles<float>(int, C2<float>*);
 template void make_twiddles<double>(int, C2<double>*);
 

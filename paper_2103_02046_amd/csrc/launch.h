@@ -52,7 +52,8 @@ void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
                    double* out_sorted, hipStream_t st);
 
 // ---- mesh assignment (mesh.hip) --------------------------------------------
-// Deposit into a mesh of type M (float or double) from records of type R.
+// Deposit into a mesh of type M (float or double) from records of type R in
+// PP-cell order; clears Q first.
 template <typename R, typename M>
 void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st);
@@ -82,10 +83,10 @@ void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale
 bool fft_supported(int nodes);
 // Spectrum buffer: complex, grid[2] x 2 grid[1] x (grid[0] + 1).
 size_t spectrum_elems(const Geo& geo);
-// phi = G (x) Q on the mesh (internal units). Q is cleared on the way if clearQ.
+// phi = G (x) Q on the mesh (internal units).
 template <typename R>
-void launch_convolve(const Geo& geo, R* Q, C2<R>* spec, const double* ghat, const C2<R>* tw[3],
-                     R* phi, int clearQ, hipStream_t st);
+void launch_convolve(const Geo& geo, const R* Q, C2<R>* spec, const double* ghat, const C2<R>* tw[3],
+                     R* phi, hipStream_t st);
 template <typename R>
 void make_twiddles(int L, C2<R>* host_out);
 // Fourier transform of the sampled kernel erf(kappa rho)/rho on the doubled

@@ -46,15 +46,21 @@ struct Stencil {
   }
 };
 
-// Deposit, privatised in LDS: a block takes 1024 consecutive sorted
-// particles. Sorted by PP cell, they usually cover a small box of nodes
-// (dense core: a few cells along one x row); the block then accumulates
-// their weights in an LDS tile of that box and adds the tile to the mesh
-// with one global atomic per touched node. When the box does not fit the
-// tile (sparse halo, where particles rarely share nodes) each particle adds
-// its weights to the mesh directly.
+// Deposit. A block takes 1024 consecutive sorted particles; sorted by PP
+// cell they usually cover a small box of nodes. The block accumulates their
+// weights in an LDS tile of that box in 64-bit fixed point (integer LDS
+// atomics: exact, order-independent, and far cheaper than float LDS
+// atomics), then adds the nonzero nodes to the mesh with one float atomic
+// each, consecutive lanes on consecutive nodes. A box larger than the tile
+// is covered in pieces (z-slabs, or y-bands of one plane), each a pass over
+// the block's particles; past kMaxPieces (very sparse bunches) each particle
+// adds its weights to the mesh directly. The fixed-point unit is 2^-s of the
+// block's largest |charge weight| with s chosen so that 1024 contributions
+// cannot overflow: a node value keeps 50 bits below that weight.
 constexpr int kDepItems = 4;
 constexpr int kDepChunk = kThreads * kDepItems;
+constexpr int kTileNodes = 8192;     // 64 KB of int64
+constexpr int kMaxPieces = 16;
 
 __device__ __forceinline__ int wave_min(int v) {
   for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
@@ -64,38 +70,47 @@ __device__ __forceinline__ int wave_max(int v) {
   for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
   return v;
 }
+__device__ __forceinline__ double wave_maxd(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Stencil origin of a sorted particle from its mesh record.
+template <typename R>
+__device__ __forceinline__ void unpack_base(const MeshRec<R>& m, int nx, unsigned nxy, int b[3]) {
+  const unsigned base = (unsigned)m.base;   // < 2^30: at most 1024 nodes per axis
+  const unsigned bz = base / nxy, rem = base - bz * nxy;
+  const unsigned by = rem / (unsigned)nx;
+  b[0] = (int)(rem - by * (unsigned)nx);
+  b[1] = (int)by;
+  b[2] = (int)bz;
+}
 
 template <typename R, typename M, int ORDER>
 __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>* __restrict__ pp,
                                                       const MeshRec<R>* __restrict__ mesh, Geo geo,
                                                       M* __restrict__ Q) {
-  constexpr int kTileNodes = 32768 / (int)sizeof(M);
   constexpr int NS = ORDER + 1;
-  __shared__ M tile[kTileNodes];
+  __shared__ long long tile[kTileNodes];
   __shared__ int red[6];
+  __shared__ double qred[kThreads / 64];
   const int t = threadIdx.x;
   const int nx = geo.grid[0], ny = geo.grid[1];
-  const long long nxy = (long long)nx * ny;
+  const unsigned nxy = (unsigned)nx * (unsigned)ny;
   const int64_t j0 = (int64_t)blockIdx.x * kDepChunk;
-  MeshRec<R> m[kDepItems];
-  R q[kDepItems];
-  int b[kDepItems][3];
-  bool ok[kDepItems];
   int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+  double qmax = 0.0;
 #pragma unroll
   for (int it = 0; it < kDepItems; ++it) {
     const int64_t j = j0 + it * kThreads + t;
-    ok[it] = j < n;
-    if (ok[it]) {
-      m[it] = mesh[j];
-      q[it] = pp[j].w;
-      const long long base = m[it].base;
-      b[it][0] = (int)(base % nx);
-      b[it][1] = (int)((base / nx) % ny);
-      b[it][2] = (int)(base / nxy);
+    if (j < n) {
+      int b[3];
+      unpack_base(mesh[j], nx, nxy, b);
+      qmax = fmax(qmax, fabs((double)pp[j].w));
+#pragma unroll
       for (int d = 0; d < 3; ++d) {
-        lo[d] = min(lo[d], b[it][d]);
-        hi[d] = max(hi[d], b[it][d]);
+        lo[d] = min(lo[d], b[d]);
+        hi[d] = max(hi[d], b[d]);
       }
     }
   }
@@ -108,46 +123,90 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
       atomicMax(&red[3 + d], c);
     }
   }
+  qmax = wave_maxd(qmax);
+  if ((t & 63) == 0) qred[t >> 6] = qmax;
   __syncthreads();
+  qmax = qred[0];
+  for (int k = 1; k < kThreads / 64; ++k) qmax = fmax(qmax, qred[k]);
+  if (red[0] == INT_MAX || qmax == 0.0) return;   // nothing to add (uniform across the block)
   const int o0 = red[0], o1 = red[1], o2 = red[2];
   const int e0 = red[3] - o0 + NS, e1 = red[4] - o1 + NS, e2 = red[5] - o2 + NS;
-  const long long vol = (long long)e0 * e1 * e2;
-  if (vol <= kTileNodes) {
-    for (int e = t; e < vol; e += kThreads) tile[e] = (M)0;
-    __syncthreads();
+  const long long plane = (long long)e0 * e1;
+  int hz, hy;
+  if (plane <= kTileNodes) {
+    hz = (int)(kTileNodes / plane);
+    hy = e1;
+  } else {
+    hz = 1;
+    hy = kTileNodes / e0;   // e0 <= 1026 < kTileNodes
+  }
+  const long long pieces = (long long)((e2 + hz - 1) / hz) * ((e1 + hy - 1) / hy);
+  if (pieces <= kMaxPieces) {
+    // unit 2^-s with qmax < 2^(ex+1): 1024 * 2^(ex+1) * 2^s <= 2^61
+    const int ex = ilogb(qmax);
+    const double toFix = ldexp(1.0, 50 - ex), fromFix = ldexp(1.0, ex - 50);
+    for (int pz = 0; pz < e2; pz += hz) {
+      const int pe2 = min(hz, e2 - pz);
+      for (int py = 0; py < e1; py += hy) {
+        const int pe1 = min(hy, e1 - py);
+        const int pvol = e0 * pe1 * pe2;
+        for (int e = t; e < pvol; e += kThreads) tile[e] = 0;
+        __syncthreads();
+#pragma unroll 1
+        for (int it = 0; it < kDepItems; ++it) {
+          const int64_t j = j0 + it * kThreads + t;
+          if (j >= n) continue;
+          const MeshRec<R> m = mesh[j];
+          const R q = pp[j].w;
+          int b[3];
+          unpack_base(m, nx, nxy, b);
+          const int rx = b[0] - o0, ry = b[1] - o1 - py, rz = b[2] - o2 - pz;
+          if (rz >= pe2 || rz + NS <= 0 || ry >= pe1 || ry + NS <= 0) continue;
+          const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
 #pragma unroll
-    for (int it = 0; it < kDepItems; ++it) {
-      if (!ok[it]) continue;
-      Stencil<R, ORDER> S(m[it].fx, m[it].fy, m[it].fz);
-      const int tb = ((b[it][2] - o2) * e1 + (b[it][1] - o1)) * e0 + (b[it][0] - o0);
+          for (int c = 0; c < NS; ++c) {
+            const int z = rz + c;
+            if ((unsigned)z >= (unsigned)pe2) continue;
 #pragma unroll
-      for (int c = 0; c < NS; ++c)
+            for (int bb = 0; bb < NS; ++bb) {
+              const int y = ry + bb;
+              if ((unsigned)y >= (unsigned)pe1) continue;
+              const double wyz = (double)(q * S.w[1][bb] * S.w[2][c]) * toFix;
+              unsigned long long* row = reinterpret_cast<unsigned long long*>(tile) + (z * pe1 + y) * e0 + rx;
 #pragma unroll
-        for (int bb = 0; bb < NS; ++bb) {
-          const R wyz = q[it] * S.w[1][bb] * S.w[2][c];
-#pragma unroll
-          for (int a = 0; a < NS; ++a) atomicAdd(&tile[tb + (c * e1 + bb) * e0 + a], (M)(wyz * S.w[0][a]));
+              for (int a = 0; a < NS; ++a)
+                atomicAdd(row + a, (unsigned long long)__double2ll_rn(wyz * (double)S.w[0][a]));
+            }
+          }
         }
-    }
-    __syncthreads();
-    for (int e = t; e < vol; e += kThreads) {
-      const M v = tile[e];
-      if (v != (M)0) {
-        const int ex = e % e0, ey = (e / e0) % e1, ez = e / (e0 * e1);
-        atomicAdd(Q + ((long long)(o2 + ez) * ny + (o1 + ey)) * nx + (o0 + ex), v);
+        __syncthreads();
+        for (int e = t; e < pvol; e += kThreads) {
+          const long long v = tile[e];
+          if (v != 0) {
+            const int ex0 = e % e0, ey = (e / e0) % pe1, ez = e / (e0 * pe1);
+            atomicAdd(Q + ((long long)(o2 + pz + ez) * ny + (o1 + py + ey)) * nx + (o0 + ex0),
+                      (M)((double)v * fromFix));
+          }
+        }
+        __syncthreads();
       }
     }
   } else {
-#pragma unroll
+#pragma unroll 1
     for (int it = 0; it < kDepItems; ++it) {
-      if (!ok[it]) continue;
-      Stencil<R, ORDER> S(m[it].fx, m[it].fy, m[it].fz);
+      const int64_t j = j0 + it * kThreads + t;
+      if (j >= n) continue;
+      const MeshRec<R> m = mesh[j];
+      const R q = pp[j].w;
+      int b[3];
+      unpack_base(m, nx, nxy, b);
+      const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
 #pragma unroll
       for (int c = 0; c < NS; ++c)
 #pragma unroll
         for (int bb = 0; bb < NS; ++bb) {
-          const R wyz = q[it] * S.w[1][bb] * S.w[2][c];
-          M* row = Q + m[it].base + c * nxy + (long long)bb * nx;
+          const R wyz = q * S.w[1][bb] * S.w[2][c];
+          M* row = Q + ((long long)(b[2] + c) * ny + (b[1] + bb)) * nx + b[0];
 #pragma unroll
           for (int a = 0; a < NS; ++a) atomicAdd(row + a, (M)(wyz * S.w[0][a]));
         }
@@ -317,7 +376,9 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) /
 template <typename R, typename M>
 void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st) {
+  launch_fill(Q, (size_t)geo.grid[0] * geo.grid[1] * geo.grid[2] * sizeof(M), st);
   const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
+  if (blocks == 0) return;
   if (geo.order == 1)
     k_deposit<R, M, 1><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
   else
@@ -362,7 +423,7 @@ void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale
 }
 
 #define P3M_MESH_INST(R, M)                                                                        \
-  template void launch_deposit<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const Geo&, M*,         \
+  template void launch_deposit<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const Geo&, M*,        \
                                      hipStream_t);                                                        \
   template void launch_gather<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const PPRec<R>*,          \
                                     const uint32_t*, const Geo&, const Place*, const M*, GatherOut,       \

@@ -40,7 +40,7 @@ MESH_AUTO, MESH_F32, MESH_F64 = 0, 1, 2
 
 class Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("zoom", ctypes.c_int32),
-                ("keep_mesh", ctypes.c_int32), ("mesh_precision", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("mesh_precision", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("ke", ctypes.c_double), ("q", ctypes.c_double),
                 ("m", ctypes.c_double)]
 
@@ -105,11 +105,11 @@ class Context:
     cutoff r_cut (m), Ewald split parameter `split` (1/m)."""
 
     def __init__(self, grid, h, r_cut, split, order=TSC, precision=FP64, zoom=True, ke=8.9875517923e9,
-                 q=1.0, m=1.0, keep_mesh=False, mesh_precision=MESH_AUTO):
+                 q=1.0, m=1.0, mesh_precision=MESH_AUTO):
         L = lib()
         o = Opts()
         L.p3m_default_opts(ctypes.byref(o))
-        o.order, o.precision, o.zoom, o.keep_mesh = int(order), int(precision), int(bool(zoom)), int(bool(keep_mesh))
+        o.order, o.precision, o.zoom = int(order), int(precision), int(bool(zoom))
         o.ke, o.q, o.m = float(ke), float(q), float(m)
         o.mesh_precision = int(mesh_precision)
         g = (ctypes.c_int32 * 3)(*[int(v) for v in grid])

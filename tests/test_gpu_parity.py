@@ -96,7 +96,7 @@ def test_total_force_fp64_gauss4k_and_vs_coulomb():
 def test_mesh_charge_and_potential_fp64(order):
     wl = small_aniso(n=5000, grid=16)
     x, _ = wl.draw()
-    c = p3m.Context(wl.grid, wl.h, wl.r_cut, wl.split, order=order, q=wl.q, m=wl.m, keep_mesh=True)
+    c = p3m.Context(wl.grid, wl.h, wl.r_cut, wl.split, order=order, q=wl.q, m=wl.m)
     c.forces(dev(x))
     Q, phi = host(c.mesh(0)), host(c.mesh(1))
     prm = O.Params(wl.grid, wl.h, wl.r_cut, wl.split, order, wl.ke_q2)
@@ -113,7 +113,7 @@ def test_ragged_meshes_and_tiny_grids(grid):
     rng = np.random.default_rng(1)
     x = rng.standard_normal((700, 3)) * np.array([1.0, 0.7, 1.3])
     h = (0.4, 0.3, 0.5)
-    c = p3m.Context(grid, h, 0.7, 3.0 / 0.7, order=2, ke=1.0, q=1.0, keep_mesh=True)
+    c = p3m.Context(grid, h, 0.7, 3.0 / 0.7, order=2, ke=1.0, q=1.0)
     fpp, fpm, _ = c.forces_parts(dev(x))
     phi = host(c.mesh(1))
     prm = O.Params(grid, h, 0.7, 3.0 / 0.7, 2, 1.0)
