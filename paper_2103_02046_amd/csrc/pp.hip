@@ -265,6 +265,11 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     tw = me.w;
   }
   const R tox = (R)tdc * cux;
+  // cutoff test: r^2 - lim = (|t|^2 + (|c|^2 - lim)) - 2 t.c with lim =
+  // 1 + margin; the margin covers the rounding of the expanded form for
+  // positions within two cell edges of the group's corner (|c|^2 <= 12 cu^2)
+  const double cmax = fmax(geo.cu[0], fmax(geo.cu[1], geo.cu[2]));
+  const R lim = (R)(1.0 + 1e-5 * fmax(1.0, 4.0 * cmax * cmax));
   R tx, ty, tz;
   if constexpr (kFix) {
     tx = active ? (R)ix * fsx : (R)1e18;
@@ -275,6 +280,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     ty = ly;
     tz = lz;
   }
+  const R t2x = (R)-2 * tx, t2y = (R)-2 * ty, t2z = (R)-2 * tz;
+  const R tt = tx * tx + ty * ty + tz * tz;
   const int L = gtot[q];
   const int S = (L + kTileK - 1) / kTileK;
   const int nt = max(max((gtot[0] + kTileK - 1) / kTileK, (gtot[1] + kTileK - 1) / kTileK),
@@ -317,7 +324,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     // 1. stage the prefetched candidates
 #pragma unroll
     for (int h = 0; h < kPerLane; ++h) {
-      V4 c{(R)1e18, (R)0, (R)0, (R)0};
+      V4 c{(R)1e18, (R)0, (R)0, (R)1e30};
       const int dy = cr[h] % 3 - 1, dz = cr[h] / 3 - 1;
       if constexpr (kFix) {
         int4 fx = make_int4(0, 0, 0, 0);
@@ -327,6 +334,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
           c.x = (R)fx.x * fsx;
           c.y = (R)fx.y * fsy;
           c.z = (R)fx.z * fsz;
+          c.w = c.x * c.x + c.y * c.y + c.z * c.z - lim;
         }
         tfix[TS * q + 16 * h + ql] = fx;
       } else {
@@ -337,6 +345,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
           c.x = cl.x + co.x;
           c.y = cl.y + co.y;
           c.z = cl.z + co.z;
+          c.w = c.x * c.x + c.y * c.y + c.z * c.z - lim;
         }
         tloc[TS * q + 16 * h + ql] = cl;
         toff[TS * q + 16 * h + ql] = co;
@@ -345,27 +354,24 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     }
     __syncthreads();
     fetch(t + 1);
-    // 2. hit masks (group-relative positions). The sign bit of r2 - 1 is
+    // 2. hit masks (group-relative positions). The sign bit of r2 - lim is
     //    shifted into the mask (alignbit: m = (m << 1) | (bits >> 31)), so
-    //    candidate k of a half-tile ends at bit 31 - k. The test is made a
-    //    little generous (2e-6 of the cutoff); the evaluation below repeats
-    //    it exactly on the precise separation.
+    //    candidate k of a half-tile ends at bit 31 - k. The test is a little
+    //    generous; the evaluation below repeats it exactly on the precise
+    //    separation.
     const V4* tq = tile + TS * q;
     uint32_t m0 = 0u, m1 = 0u;
-    const R lim = (R)(-(1.0 + 2e-6));
 #pragma unroll 4
     for (int k = 0; k < 32; ++k) {
       const V4 c = tq[k];
-      const R dx = tx - c.x, dy = ty - c.y, dz = tz - c.z;
-      const R r2m1 = dz * dz + (dy * dy + (dx * dx + lim));
-      m0 = mask_shift_in(m0, r2m1);
+      const R v = fma(t2z, c.z, fma(t2y, c.y, fma(t2x, c.x, tt + c.w)));
+      m0 = mask_shift_in(m0, v);
     }
 #pragma unroll 4
     for (int k = 0; k < 32; ++k) {
       const V4 c = tq[32 + k];
-      const R dx = tx - c.x, dy = ty - c.y, dz = tz - c.z;
-      const R r2m1 = dz * dz + (dy * dy + (dx * dx + lim));
-      m1 = mask_shift_in(m1, r2m1);
+      const R v = fma(t2z, c.z, fma(t2y, c.y, fma(t2x, c.x, tt + c.w)));
+      m1 = mask_shift_in(m1, v);
     }
     if (!active) m0 = m1 = 0u;
     // 3. own hits (the particle itself and coincident ones give r2 = 0)
