@@ -69,15 +69,23 @@ template <typename R> struct PPRec;              // per-particle vector + weight
 template <> struct alignas(16) PPRec<float> { float x, y, z, w; };
 template <> struct alignas(32) PPRec<double> { double x, y, z, w; };
 
-// Position in the own PP cell + weight. float form: fixed point, the cell
-// edge per axis is 2^kFixBits units, so separations of particles in
-// neighbouring cells are exact integers (rounded once, to float, after the
-// subtraction). double form: offset from the cell corner in units of Lu.
+// Position in the own PP cell + weight. float form: fixed point in one
+// unit for all axes, fix_unit = (largest cell edge) / 2^kFixBits Lu; the
+// cell edge of axis d is the integer fix_edge(d) units, so separations of
+// particles in neighbouring cells are exact integers (rounded once, to
+// float, after the subtraction). double form: offset from the cell corner
+// in units of Lu.
 constexpr int kFixBits = 29;
 struct alignas(16) PPFix { int x, y, z; float w; };
 template <typename R> struct PPPosOf { using type = PPRec<R>; };
 template <> struct PPPosOf<float> { using type = PPFix; };
 template <typename R> using PPPos = typename PPPosOf<R>::type;
+
+__host__ __device__ inline double fix_unit(const double cu[3]) {
+  const double m = cu[0] > cu[1] ? (cu[0] > cu[2] ? cu[0] : cu[2]) : (cu[1] > cu[2] ? cu[1] : cu[2]);
+  return m / (double)(1 << kFixBits);
+}
+__host__ __device__ inline int fix_edge(const double cu[3], int d) { return (int)rint(cu[d] / fix_unit(cu)); }
 
 template <typename R> struct MeshRec;            // stencil origin node + fractional offsets
 template <> struct alignas(16) MeshRec<float> { float fx, fy, fz; int base; };

@@ -45,19 +45,28 @@ __device__ __forceinline__ float erfcx_poly(float t) {
   return acc;
 }
 
-// Scalar g(rho) w_j with F = g d; float.
-__device__ __forceinline__ float pair_scalar(float r2, float wj, float kappa, float c2k, float* epair) {
-  float rinv = __builtin_amdgcn_rsqf(r2);
-  float r = r2 * rinv;
-  float x = kappa * r;
-  float e = __builtin_amdgcn_exp2f(-x * x * kLog2e);
-  float t = fmaxf(__builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f)), P3M_ERFCX_TMIN);
-  float erfc_x = e * t * erfcx_poly(t);
-  if (epair) *epair = erfc_x * rinv * wj;
-  return (erfc_x * rinv + c2k * e) * (rinv * rinv) * wj;
+// Constants of the pair kernel in units of the cutoff.
+template <typename R>
+struct PairK {
+  R kappa, c2k;     // kappa = a r_c, 2 kappa / sqrt(pi)
+  R half_kappa;     // kappa / 2
+  R ek;             // -kappa^2 log2(e)
+};
+
+// Scalar g(rho) w_j with F = g d; float. With x = kappa rho, e = exp(-x^2)
+// and erfc(x) = e t P(t): g = (e / rho^2) (t P(t) / rho + 2 kappa/sqrt(pi)).
+__device__ __forceinline__ float pair_scalar(float r2, float wj, const PairK<float>& K, float* epair) {
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r = r2 * rinv;
+  const float t = fmaxf(__builtin_amdgcn_rcpf(fmaf(K.half_kappa, r, 1.0f)), P3M_ERFCX_TMIN);
+  const float e = __builtin_amdgcn_exp2f(K.ek * r2);
+  const float tp = t * erfcx_poly(t);
+  if (epair) *epair = e * tp * rinv * wj;
+  return (e * (rinv * rinv)) * fmaf(tp, rinv, K.c2k) * wj;
 }
 
-__device__ __forceinline__ double pair_scalar(double r2, double wj, double kappa, double c2k, double* epair) {
+__device__ __forceinline__ double pair_scalar(double r2, double wj, const PairK<double>& K, double* epair) {
+  const double kappa = K.kappa, c2k = K.c2k;
   double r = sqrt(r2);
   double x = kappa * r;
   double e = exp(-x * x);
@@ -210,8 +219,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   if (gvalid) gd = desc[gid];
   const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
   const R cux = (R)geo.cu[0], cuy = (R)geo.cu[1], cuz = (R)geo.cu[2];
-  constexpr int kOne = 1 << kFixBits;
-  const R fsx = (R)(geo.cu[0] / kOne), fsy = (R)(geo.cu[1] / kOne), fsz = (R)(geo.cu[2] / kOne);
+  const int kex = fix_edge(geo.cu, 0), key_ = fix_edge(geo.cu, 1), kez = fix_edge(geo.cu, 2);
+  const R fu = (R)fix_unit(geo.cu), fu2 = fu * fu;
   int cx0 = 0, cy = 0, cz = 0;
   if (gvalid) {
     const uint32_t k0 = keys[gd.x];
@@ -254,7 +263,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     const PPPos<R> me = rec[j];
     tdc = (int)(keys[j] % (uint32_t)nx) - cx0;   // 0: every target of a group is in its first cell
     if constexpr (kFix) {
-      ix = me.x + tdc * kOne;
+      ix = me.x + tdc * kex;
       iy = me.y;
       iz = me.z;
     } else {
@@ -272,9 +281,9 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   const R lim = (R)(1.0 + 1e-5 * fmax(1.0, 4.0 * cmax * cmax));
   R tx, ty, tz;
   if constexpr (kFix) {
-    tx = active ? (R)ix * fsx : (R)1e18;
-    ty = (R)iy * fsy;
-    tz = (R)iz * fsz;
+    tx = active ? (R)ix * fu : (R)1e18;
+    ty = (R)iy * fu;
+    tz = (R)iz * fu;
   } else {
     tx = active ? lx + tox : (R)1e18;
     ty = ly;
@@ -315,8 +324,11 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     }
   };
   fetch(0);
-  const R kappa = (R)geo.kappa;
-  const R c2k = (R)(kTwoOverSqrtPi * geo.kappa);
+  PairK<R> pk;
+  pk.kappa = (R)geo.kappa;
+  pk.c2k = (R)(kTwoOverSqrtPi * geo.kappa);
+  pk.half_kappa = (R)(0.5 * geo.kappa);
+  pk.ek = (R)(-geo.kappa * geo.kappa * 1.44269504088896340736);
   Acc3<R> acc;
   double e_acc = 0.0;
   int pairs = 0;
@@ -329,11 +341,11 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       if constexpr (kFix) {
         int4 fx = make_int4(0, 0, 0, 0);
         if (nx_ok[h]) {
-          fx = make_int4(nx_o[h].x + nx_c[h] * kOne, nx_o[h].y + dy * kOne, nx_o[h].z + dz * kOne,
+          fx = make_int4(nx_o[h].x + nx_c[h] * kex, nx_o[h].y + dy * key_, nx_o[h].z + dz * kez,
                          __float_as_int(nx_o[h].w));
-          c.x = (R)fx.x * fsx;
-          c.y = (R)fx.y * fsy;
-          c.z = (R)fx.z * fsz;
+          c.x = (R)fx.x * fu;
+          c.y = (R)fx.y * fu;
+          c.z = (R)fx.z * fu;
           c.w = c.x * c.x + c.y * c.y + c.z * c.z - lim;
         }
         tfix[TS * q + 16 * h + ql] = fx;
@@ -374,25 +386,24 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       m1 = mask_shift_in(m1, v);
     }
     if (!active) m0 = m1 = 0u;
-    // 3. own hits (the particle itself and coincident ones give r2 = 0)
+    // 3. own hits (the particle itself and coincident ones give r2 = 0).
+    //    As one 64-bit word (m0 high), bit b is candidate 63 - b; the lowest
+    //    set bit is taken and cleared each round. Float form: separations
+    //    in fixed-point units, the unit applied to r2 here and to the sums
+    //    at the end.
     R sx = 0, sy = 0, sz = 0;
-    while (m0 | m1) {
-      int k;
-      if (m0) {
-        k = __clz(m0);
-        m0 &= ~(0x80000000u >> k);
-      } else {
-        const int b = __clz(m1);
-        m1 &= ~(0x80000000u >> b);
-        k = 32 + b;
-      }
-      R dx, dy, dz, wj;
+    uint64_t hm = ((uint64_t)m0 << 32) | m1;
+    while (hm) {
+      const int k = 63 - (int)__builtin_ctzll(hm);
+      hm &= hm - 1;
+      R dx, dy, dz, wj, r2;
       if constexpr (kFix) {
         const int4 cf = tfix[TS * q + k];
-        dx = (R)(ix - cf.x) * fsx;
-        dy = (R)(iy - cf.y) * fsy;
-        dz = (R)(iz - cf.z) * fsz;
+        dx = (R)(ix - cf.x);
+        dy = (R)(iy - cf.y);
+        dz = (R)(iz - cf.z);
         wj = __int_as_float(cf.w);
+        r2 = (dx * dx + dy * dy + dz * dz) * fu2;
       } else {
         const V4 cl = tloc[TS * q + k];
         const V4 co = toff[TS * q + k];
@@ -400,11 +411,11 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         dy = (ly - cl.y) - co.y;
         dz = (lz - cl.z) - co.z;
         wj = cl.w;
+        r2 = dx * dx + dy * dy + dz * dz;
       }
-      const R r2 = dx * dx + dy * dy + dz * dz;
       if (r2 > (R)0 && r2 < (R)1) {
         R ep;
-        const R g = pair_scalar(r2, wj, kappa, c2k, ENERGY ? &ep : nullptr);
+        const R g = pair_scalar(r2, wj, pk, ENERGY ? &ep : nullptr);
         sx += g * dx;
         sy += g * dy;
         sz += g * dz;
@@ -418,10 +429,11 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     __syncthreads();
   }
   if (active) {
+    const R unit = kFix ? fu : (R)1;
     PPRec<R> f;
-    f.x = acc.get(0) * tw;
-    f.y = acc.get(1) * tw;
-    f.z = acc.get(2) * tw;
+    f.x = acc.get(0) * (tw * unit);
+    f.y = acc.get(1) * (tw * unit);
+    f.z = acc.get(2) * (tw * unit);
     f.w = (R)0;
     out[gd.x + ql] = f;
   }

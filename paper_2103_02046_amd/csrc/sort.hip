@@ -161,14 +161,16 @@ __device__ __forceinline__ PPPos<double> make_pos<double>(const double* loc, con
 // Nearest fixed-point value. Inside the mesh a particle lies in [0, 1] cell
 // edges of its cell's corner; one outside it (reported as a domain error)
 // is clamped to [-1/2, 3/2) edges, which keeps every PP separation, cell
-// offsets included, below 2^31 units.
+// offsets included, below 2^31 units (an edge is at most 2^29 units).
 template <>
 __device__ __forceinline__ PPPos<float> make_pos<float>(const double* loc, const double* cu, double w) {
+  const double unit = fix_unit(cu);
   int v[3];
   for (int d = 0; d < 3; ++d) {
-    double u = loc[d] / cu[d];
-    u = fmin(fmax(u, -0.5), 1.4999999);
-    v[d] = (int)rint(u * (double)(1 << kFixBits));
+    const double e = (double)fix_edge(cu, d);
+    double u = loc[d] / unit;
+    u = fmin(fmax(u, -0.5 * e), 1.4999999 * e);
+    v[d] = (int)rint(u);
   }
   return PPFix{v[0], v[1], v[2], (float)w};
 }
