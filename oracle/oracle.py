@@ -66,7 +66,7 @@ def lib():
         P = ctypes.c_void_p
         i64, dbl, i32 = ctypes.c_int64, ctypes.c_double, ctypes.c_int
         sig = {
-            "oracle_placement": (i32, [i64, P, P, P, i32, i32, P]),
+            "oracle_placement": (i32, [i64, P, P, P, i32, i32, i32, P]),
             "oracle_pp_brute": (None, [i64, P, P, dbl, dbl, dbl, P]),
             "oracle_pp_cells": (i32, [i64, P, P, dbl, dbl, dbl, P]),
             "oracle_pp_sample": (i32, [i64, P, P, dbl, dbl, dbl, i64, P, P]),
@@ -77,6 +77,7 @@ def lib():
             "oracle_phi_at": (None, [P, P, dbl, P, i64, P, P]),
             "oracle_stencil_nodes": (i32, [P, P, P, P, i32, P]),
             "oracle_gather": (i32, [i64, P, P, P, P, P, i32, P, dbl, P]),
+            "oracle_gather_momentum": (i32, [i64, P, P, P, P, P, i32, P, dbl, P]),
             "oracle_pp_hvp": (None, [i64, P, P, dbl, dbl, dbl, P, P]),
             "oracle_deposit_grad": (i32, [i64, P, P, P, P, P, i32, P, P]),
             "oracle_gather_hvp": (i32, [i64, P, P, P, P, P, i32, P, P, P, dbl, P]),
@@ -106,7 +107,8 @@ def _check(code, what):
 class Params:
     """Run parameters of one P3M configuration (SI units)."""
 
-    def __init__(self, grid, h, r_cut, split, order, ke_q2, m=1.0, dt=0.0, zoom=True, qw=None):
+    def __init__(self, grid, h, r_cut, split, order, ke_q2, m=1.0, dt=0.0, zoom=True, qw=None,
+                 gather="variational"):
         self.grid = np.asarray(grid, dtype=np.int32)
         self.h = np.asarray(h, dtype=np.float64)
         self.r_cut = float(r_cut)
@@ -117,6 +119,9 @@ class Params:
         self.dt = float(dt)
         self.zoom = bool(zoom)
         self.qw = None if qw is None else _f64(qw)
+        if gather not in ("variational", "momentum"):
+            raise ValueError(gather)
+        self.gather = gather
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -131,11 +136,13 @@ def threads():
 # ---- placement --------------------------------------------------------------
 
 def placement(x, prm):
-    """Mesh origin, zoom and zoomed spacing for positions x (reading of Sec. 2.4.2)."""
+    """Mesh origin, zoom and zoomed spacing for positions x (reading of Sec. 2.4.2).
+    The momentum-conserving gather keeps every stencil one node inside the mesh."""
     x = _f64(x)
     out = np.zeros(8)
+    margin = 1 if prm.gather == "momentum" else 0
     _check(lib().oracle_placement(len(x), _p(x), _p(prm.grid), _p(prm.h), prm.order,
-                                  int(prm.zoom), _p(out)), "placement")
+                                  int(prm.zoom), margin, _p(out)), "placement")
     s = out[3]
     return {"x0": out[0:3].copy(), "s": s, "hp": out[4:7].copy(),
             "rc": prm.r_cut * s, "a": prm.split / s}
@@ -239,12 +246,15 @@ def stencil_nodes(xi, prm, pl):
 
 
 def gather(x, prm, pl, phi):
-    """Mesh force -k_e q^2 qw_i sum_m phi_m grad W_m(x_i) (Sec. 2.5 eq. eom_p3m_coord)."""
+    """Mesh force at the particles from the mesh potential phi.
+    variational: -k_e q^2 qw_i sum_m phi_m grad W_m(x_i) (Sec. 2.5 eq. eom_p3m_coord);
+    momentum: k_e q^2 qw_i sum_m W_m(x_i) E_m with E the central difference of -phi."""
     x = _f64(x)
     phi = _f64(phi)
     f = np.zeros_like(x)
-    _check(lib().oracle_gather(len(x), _p(x), _p(prm.qw), _p(prm.grid), _p(pl["x0"]),
-                               _p(pl["hp"]), prm.order, _p(phi), prm.ke_q2, _p(f)), "gather")
+    fn = lib().oracle_gather_momentum if prm.gather == "momentum" else lib().oracle_gather
+    _check(fn(len(x), _p(x), _p(prm.qw), _p(prm.grid), _p(pl["x0"]), _p(pl["hp"]), prm.order,
+              _p(phi), prm.ke_q2, _p(f)), "gather")
     return f
 
 
@@ -328,6 +338,8 @@ def hvp(x, v, prm, pl, brute=True):
     PP part: sum_j K_ij (v_i - v_j); PM part: gather of psi = G (x) R plus the
     second derivative of the weights against phi (derivatives of Sec. 2.5
     eq. eom_p3m_coord)."""
+    if prm.gather != "variational":
+        raise ValueError("the Hessian is that of the variational force")
     x = _f64(x)
     v = _f64(v)
     out_pp = np.zeros_like(x)

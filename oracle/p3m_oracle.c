@@ -59,9 +59,9 @@ static double qweight(const double *qw, int64_t i) { return qw ? qw[i] : 1.0; }
  * out[0..2] = x0 (position of node 0), out[3] = s, out[4..6] = s*h.
  * ---------------------------------------------------------------------- */
 int oracle_placement(int64_t n, const double *x, const int32_t *grid,
-                     const double *h, int order, int zoom, double *out)
+                     const double *h, int order, int zoom, int margin, double *out)
 {
-    if (n < 1 || (order != 1 && order != 2)) return OR_EINVAL;
+    if (n < 1 || (order != 1 && order != 2) || margin < 0) return OR_EINVAL;
     double lo[3], hi[3];
     for (int d = 0; d < 3; ++d) { lo[d] = INFINITY; hi[d] = -INFINITY; }
     for (int64_t i = 0; i < n; ++i)
@@ -73,7 +73,8 @@ int oracle_placement(int64_t n, const double *x, const int32_t *grid,
         }
     double s = 1.0;
     for (int d = 0; d < 3; ++d) {
-        double usable = (double)(order == 1 ? grid[d] - 1 : grid[d] - 2);
+        double usable = (double)((order == 1 ? grid[d] - 1 : grid[d] - 2) - 2 * margin);
+        if (usable <= 0) return OR_EINVAL;
         double need = (hi[d] - lo[d]) * (1.0 + 1e-6) / (usable * h[d]);
         if (need > s) s = need;
     }
@@ -408,6 +409,47 @@ int oracle_gather(int64_t n, const double *x, const double *qw, const int32_t *g
         f[3 * i] = s * gx / hp[0];
         f[3 * i + 1] = s * gy / hp[1];
         f[3 * i + 2] = s * gz / hp[2];
+    }
+    return bad ? OR_EDOMAIN : OR_OK;
+}
+
+/* Momentum-conserving alternative to the variational force (the reading of
+ * the remark after Sec. 2.5, eq. eom_p3m_coord that differences the mesh
+ * potential first): the mesh field by central differences,
+ *   E_{m,d} = -(phi_{m+e_d} - phi_{m-e_d}) / (2 h'_d),
+ * interpolated with the assignment weights,
+ *   F_{i,d} = k_e q^2 qw_i sum_m b_p(u_i - m) E_{m,d}.
+ * Needs the stencil one node inside the mesh (placement margin 1); a
+ * stencil touching the outer nodes is EDOMAIN. Overwrites f. */
+int oracle_gather_momentum(int64_t n, const double *x, const double *qw, const int32_t *grid,
+                           const double *x0, const double *hp, int order, const double *phi,
+                           double ke_q2, double *f)
+{
+    int64_t nx = grid[0], ny = grid[1];
+    int ns = order + 1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t i = 0; i < n; ++i) {
+        double w[3][3], dw[3][3];
+        int64_t b[3];
+        for (int d = 0; d < 3; ++d) {
+            double u = (x[3 * i + d] - x0[d]) / hp[d];
+            b[d] = stencil(order, u, grid[d], w[d], dw[d]);
+            if (b[d] < 1 || b[d] + ns - 1 > grid[d] - 2) bad = 1;
+        }
+        if (bad) continue;
+        const int64_t step[3] = {1, nx, nx * ny};
+        double e[3] = {0, 0, 0};
+        for (int c = 0; c < ns; ++c)
+            for (int bb = 0; bb < ns; ++bb)
+                for (int a = 0; a < ns; ++a) {
+                    int64_t m = ((b[2] + c) * ny + (b[1] + bb)) * nx + (b[0] + a);
+                    double wm = w[0][a] * w[1][bb] * w[2][c];
+                    for (int d = 0; d < 3; ++d)
+                        e[d] += wm * -(phi[m + step[d]] - phi[m - step[d]]) / (2.0 * hp[d]);
+                }
+        double s = ke_q2 * qweight(qw, i);
+        for (int d = 0; d < 3; ++d) f[3 * i + d] = s * e[d];
     }
     return bad ? OR_EDOMAIN : OR_OK;
 }

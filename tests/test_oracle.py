@@ -247,6 +247,106 @@ def test_pm_two_particles_far_limit():
     assert max(errs) < 0.03
 
 
+# ---- momentum-conserving gather (mesh E by central differences) -------------------
+
+def _pm_momentum(x, prm):
+    pl = O.placement(x, prm)
+    Q = O.deposit(x, prm, pl)
+    phi = O.conv_fft(Q, prm.grid, pl["hp"], pl["a"])
+    return O.gather(x, prm, pl, phi), pl
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_momentum_gather_total_force_vanishes(order):
+    """With E = -D phi, D the antisymmetric central difference, and phi = G (x) Q
+    for a symmetric G, sum_i F_i = sum_m Q_m E_m = 0 (the variational force has
+    no such property, which the second assertion confirms on the same bunch)."""
+    x = _rand_bunch(300, 21, scale=0.6, aniso=(1, 1, 2))
+    qw = np.random.default_rng(22).random(len(x)) + 0.5
+    prm = O.Params((14, 12, 16), (0.3, 0.35, 0.4), 0.6, 3.0 / 0.6, order, 1.0, qw=qw, gather="momentum")
+    f, _ = _pm_momentum(x, prm)
+    scale = np.abs(f).sum(axis=0)
+    assert np.all(np.abs(f.sum(axis=0)) <= 1e-13 * scale)
+    prm_v = O.Params((14, 12, 16), (0.3, 0.35, 0.4), 0.6, 3.0 / 0.6, order, 1.0, qw=qw)
+    fv, _ = _pm_momentum(x, prm_v)
+    assert np.abs(fv.sum(axis=0)).max() > 1e-8 * np.abs(fv).sum(axis=0).max()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_momentum_gather_no_self_force(order):
+    """A lone particle feels no mesh force from its own charge (the single-particle
+    case of the vanishing total), wherever it sits between nodes."""
+    rng = np.random.default_rng(23)
+    for _ in range(8):
+        x = rng.random((1, 3)) * 0.3
+        x2 = np.vstack([x, x + 0.9])       # a second particle sets the placement scale only
+        prm = O.Params((12, 12, 12), (0.25, 0.25, 0.25), 0.5, 3.0 / 0.5, order, 1.0, gather="momentum")
+        pl = O.placement(x2, prm)
+        Q = O.deposit(x, prm, pl)
+        phi = O.conv_fft(Q, prm.grid, pl["hp"], pl["a"])
+        f = O.gather(x, prm, pl, phi)
+        prm_v = O.Params((12, 12, 12), (0.25, 0.25, 0.25), 0.5, 3.0 / 0.5, order, 1.0)
+        fv = O.gather(x, prm_v, pl, phi)
+        ref = max(np.abs(fv).max(), np.abs(phi).max() / pl["hp"][0])
+        assert np.abs(f).max() <= 1e-13 * ref
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_momentum_gather_linear_potential(order):
+    """Central differences of a linear potential are exact and the weights sum
+    to one: F = -k q^2 qw grad(phi) exactly."""
+    grid = (10, 12, 9)
+    x = _rand_bunch(200, 24, scale=0.3)
+    qw = np.random.default_rng(25).random(len(x)) + 0.5
+    prm = O.Params(grid, (0.3, 0.25, 0.4), 0.5, 1.0, order, 2.0, qw=qw, gather="momentum")
+    pl = O.placement(x, prm)
+    c = np.array([1.5, -0.7, 0.4])
+    nz, ny, nx = grid[2], grid[1], grid[0]
+    gz, gy, gx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = 3.0 + c[0] * (pl["x0"][0] + gx * pl["hp"][0]) + c[1] * (pl["x0"][1] + gy * pl["hp"][1]) \
+        + c[2] * (pl["x0"][2] + gz * pl["hp"][2])
+    f = O.gather(x, prm, pl, phi)
+    np.testing.assert_allclose(f, -2.0 * qw[:, None] * c[None, :], rtol=1e-11)
+
+
+def test_momentum_placement_keeps_stencils_off_the_edge():
+    """The momentum form needs phi one node beyond every stencil node: the zoom
+    leaves the outer node layer free."""
+    x = _rand_bunch(400, 26, scale=5.0)
+    for order in (1, 2):
+        prm = O.Params((16, 16, 16), (0.2, 0.2, 0.2), 0.4, 7.5, order, 1.0, gather="momentum")
+        pl = O.placement(x, prm)
+        nodes = np.concatenate([O.stencil_nodes(xi, prm, pl) for xi in x])
+        nz = nodes // 256
+        ny = (nodes // 16) % 16
+        nx = nodes % 16
+        for v in (nx, ny, nz):
+            assert v.min() >= 1 and v.max() <= 14
+
+
+def test_momentum_two_particles_far_limit():
+    """Far apart (8h, a h = 0.25) the momentum-conserving mesh force also
+    approaches the closed-form erf(a r)/r pair force, and the pair is exactly
+    action-reaction."""
+    from scipy.special import erf
+    rng = np.random.default_rng(27)
+    h, a = 1.0, 0.25
+    errs = []
+    for _ in range(10):
+        c = rng.random(3)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        x = np.array([c, c + 8 * h * d])
+        prm = O.Params((32, 32, 32), (h, h, h), 1e-9, a, 2, 1.0, gather="momentum")
+        f, _ = _pm_momentum(x, prm)
+        assert np.abs(f[0] + f[1]).max() <= 1e-13 * np.abs(f).max()
+        r = 8.0 * h
+        g = (erf(a * r) / r - 2 * a / math.sqrt(math.pi) * math.exp(-(a * r) ** 2)) / r ** 2
+        exact = g * (x[0] - x[1])
+        errs.append(np.linalg.norm(f[0] - exact) / np.linalg.norm(exact))
+    assert max(errs) < 0.03
+
+
 # ---- whole force ----------------------------------------------------------------
 
 def test_alpha_zero_large_cutoff_equals_coulomb():
