@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="aniso1m")
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--gather", default="variational", choices=["variational", "momentum"],
+                    help="mesh force at the particles: variational (default) or momentum-conserving")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -111,11 +113,12 @@ def main():
     dev = torch.device("cuda:0")
     x = torch.tensor(x0, dtype=torch.float64, device=dev)
     p = torch.tensor(p0, dtype=torch.float64, device=dev)
-    ctx = p3m.Context.from_workload(wl, precision=prec)
+    gmode = p3m.GATHER_MOMENTUM if args.gather == "momentum" else p3m.GATHER_VARIATIONAL
+    ctx = p3m.Context.from_workload(wl, precision=prec, gather=gmode)
 
     # accuracy of this precision against the float64 path on the same GPU
     f_this = ctx.forces(x)
-    f64 = p3m.Context.from_workload(wl, precision=p3m.FP64).forces(x)
+    f64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode).forces(x)
     err = float(torch.sqrt(((f_this - f64) ** 2).sum() / (f64 ** 2).sum()))
     d0 = ctx.diagnostics(x, p)
 
@@ -209,6 +212,7 @@ def main():
             if args.workload == "aniso1m" else args.workload,
             "precision": "fp32 pair forces and FFT with Kahan sums; fp64 table, push, reductions"
             if prec == p3m.FP32C else "fp64",
+            "gather": args.gather,
             "force_rms_err_vs_fp64": err,
             "pp_pairs_per_s": pairs * args.steps / wall,
             "pairs_per_eval": pairs,

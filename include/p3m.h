@@ -72,6 +72,19 @@ typedef int32_t p3m_status;
 #define P3M_MESH_F64  2
 #define P3M_MESH_AUTO_F32_MAX 128
 
+/* Mesh force at the particles (p3m_opts.gather).
+ * VARIATIONAL: F_i = -w_i sum_m phi_m grad W_m(x_i), minus the gradient of
+ *   the discrete energy (Sec. 2.5, eq. eom_p3m_coord, first term).
+ * MOMENTUM: the mesh field by central differences,
+ *   E_m = -(phi_{m+e_d} - phi_{m-e_d}) / (2 h_d), interpolated with the
+ *   assignment weights, F_i = w_i sum_m W_m(x_i) E_m: a reading of the
+ *   remark after that equation (the weight gradient as a finite difference
+ *   of the potential). The total mesh force and the self-force vanish; the
+ *   force is not the gradient of an energy. The placement keeps every
+ *   stencil off the outer node layer (usable span 2 nodes shorter). */
+#define P3M_GATHER_VARIATIONAL 0
+#define P3M_GATHER_MOMENTUM    1
+
 #define P3M_CIC 1             /* linear B-spline b1 (2 nodes per axis)          */
 #define P3M_TSC 2             /* quadratic B-spline b2 (3 nodes per axis)       */
 
@@ -83,7 +96,7 @@ typedef struct {
     int32_t order;      /* P3M_CIC or P3M_TSC                               [TSC]  */
     int32_t precision;  /* P3M_FP64 or P3M_FP32C                            [FP64] */
     int32_t zoom;       /* 1: zoom the mesh to fit the bunch; 0: EDOMAIN    [1]    */
-    int32_t reserved0;  /* must be 0                                               */
+    int32_t gather;     /* P3M_GATHER_VARIATIONAL or _MOMENTUM     [VARIATIONAL]  */
     int32_t mesh_precision; /* P3M_MESH_AUTO, _F32 or _F64 (P3M_FP32C only) [AUTO] */
     int32_t reserved;   /* must be 0                                               */
     double ke;          /* Coulomb constant 1/(4 pi eps0)     [8.9875517923e9]    */
@@ -153,6 +166,7 @@ p3m_status p3m_step(p3m_ctx *ctx, int64_t n, double *x, double *p, const double 
  * the placement fixed at place (device, P3M_PLACEMENT_DOUBLES; NULL = the
  * bounding-box placement of x). H is symmetric because F = -grad U, so this
  * is also the vector-Jacobian product. v and out are device [n][3] float64.
+ * P3M_ESTATE with the momentum-conserving gather (its force has no potential).
  */
 p3m_status p3m_hvp(p3m_ctx *ctx, int64_t n, const double *x, const double *qw,
                    const double *v, const double *place, double *out, void *stream);
@@ -165,6 +179,7 @@ p3m_status p3m_hvp(p3m_ctx *ctx, int64_t n, const double *x, const double *qw,
  *   xb = xbar_np1 + dt/2 H(x_np1) pbar_np1;  pb = pbar_np1 + dt/m xb;
  *   xbar_n = xb + dt/2 H(x_n) pb;  pbar_n = pb.
  * All arrays device [n][3] float64; outputs may alias the inputs.
+ * P3M_ESTATE with the momentum-conserving gather.
  */
 p3m_status p3m_backward(p3m_ctx *ctx, int64_t n, const double *x_n, const double *x_np1,
                         const double *qw, const double *xbar_np1, const double *pbar_np1,

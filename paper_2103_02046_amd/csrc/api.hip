@@ -325,7 +325,8 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   if (opts) o = *opts;
   else p3m_default_opts(&o);
   if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
-  if (o.reserved0 != 0 || o.reserved != 0) return P3M_EINVAL;
+  if (o.gather != P3M_GATHER_VARIATIONAL && o.gather != P3M_GATHER_MOMENTUM) return P3M_EINVAL;
+  if (o.reserved != 0) return P3M_EINVAL;
   if (o.precision != P3M_FP64 && o.precision != P3M_FP32C) return P3M_EINVAL;
   if (o.mesh_precision != P3M_MESH_AUTO && o.mesh_precision != P3M_MESH_F32 &&
       o.mesh_precision != P3M_MESH_F64)
@@ -350,6 +351,7 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   g.ke_q2 = o.ke * o.q * o.q;
   g.order = o.order;
   g.zoom = o.zoom ? 1 : 0;
+  g.gather = o.gather == P3M_GATHER_MOMENTUM ? 1 : 0;
   g.ncells = 1;
   for (int d = 0; d < 3; ++d) {
     g.grid[d] = grid[d];
@@ -363,7 +365,9 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
     g.cu[d] = span / (double)nc / r_cut;
     g.ncells *= nc;
   }
-  if (g.ncells > (1ll << 31) - 2) {
+  bool roomy = true;
+  for (int d = 0; d < 3; ++d) roomy = roomy && usable_nodes(g, d) >= 1.0;
+  if (g.ncells > (1ll << 31) - 2 || !roomy) {
     delete ctx;
     return P3M_EINVAL;
   }
@@ -479,6 +483,7 @@ p3m_status p3m_hvp(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, c
                    const double* place_in, double* out, void* stream) {
   if (!ctx) return P3M_EINVAL;
   if (n < 0 || (n > 0 && (!x || !v || !out))) return fail(ctx, P3M_EINVAL, "bad hvp arguments");
+  if (ctx->geo.gather) return fail(ctx, P3M_ESTATE, "the Hessian is that of the variational force");
   ctx->force_cached = false;
   if (n == 0) return P3M_OK;
   hipStream_t st = (hipStream_t)stream;
@@ -496,6 +501,7 @@ p3m_status p3m_backward(p3m_ctx* ctx, int64_t n, const double* x_n, const double
   if (n < 0 || !std::isfinite(dt) ||
       (n > 0 && (!x_n || !x_np1 || !xbar_np1 || !pbar_np1 || !xbar_n || !pbar_n)))
     return fail(ctx, P3M_EINVAL, "bad backward arguments");
+  if (ctx->geo.gather) return fail(ctx, P3M_ESTATE, "the adjoint is that of the variational force");
   ctx->force_cached = false;
   if (n == 0) return P3M_OK;
   hipStream_t st = (hipStream_t)stream;

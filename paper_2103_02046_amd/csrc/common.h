@@ -43,7 +43,15 @@ struct Geo {
   double ke_q2;        // k_e q^2
   int order;           // 1 CIC, 2 TSC
   int zoom;            // 1 zoom on
+  int gather;          // 0 variational, 1 momentum-conserving (mesh E by central differences)
 };
+
+// Nodes the bunch may span so that every assignment stencil lies on the mesh
+// (N-1 for CIC, N-2 for TSC), less the outer node layer on each side when
+// the gather differences the potential across the stencil's nodes.
+__host__ __device__ inline double usable_nodes(const Geo& g, int d) {
+  return (double)((g.order == 1 ? g.grid[d] - 1 : g.grid[d] - 2) - (g.gather ? 2 : 0));
+}
 
 template <typename T>
 struct C2 {

@@ -216,7 +216,13 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
 
 // The stencil sums run in the mesh precision M (the potential differences
 // that make the force are small against the potential itself).
-template <typename R, typename M, int ORDER>
+// MODE 0, variational: g_d = sum_m phi_m dW_m/du_d.
+// MODE 1, momentum-conserving: the mesh field by central differences,
+// E_{m,d} = -(phi_{m+e_d} - phi_{m-e_d}) / (2 h_d), interpolated with W; on
+// the nodes this is g_d = sum_n phi_n (W(n - e_d) - W(n + e_d)) / 2 over the
+// stencil widened by one node on each side (inside the mesh: the placement
+// keeps stencils off the outer node layer in this mode).
+template <typename R, typename M, int ORDER, int MODE>
 __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* __restrict__ pp,
                                                      const MeshRec<R>* __restrict__ mesh,
                                                      const PPRec<R>* __restrict__ fpp,
@@ -234,23 +240,54 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
     const long long nxy = (long long)nx * geo.grid[1];
     M g[3] = {0, 0, 0};
     M pot = 0;
+    if constexpr (MODE == 0) {
 #pragma unroll
-    for (int c = 0; c < S.N; ++c)
+      for (int c = 0; c < S.N; ++c)
 #pragma unroll
-      for (int b = 0; b < S.N; ++b) {
-        const M* row = phi + m.base + c * nxy + (long long)b * nx;
-        M sx = 0, sdx = 0;
+        for (int b = 0; b < S.N; ++b) {
+          const M* row = phi + m.base + c * nxy + (long long)b * nx;
+          M sx = 0, sdx = 0;
 #pragma unroll
-        for (int a = 0; a < S.N; ++a) {
-          const M v = row[a];
-          sx += v * S.w[0][a];
-          sdx += v * S.dw[0][a];
+          for (int a = 0; a < S.N; ++a) {
+            const M v = row[a];
+            sx += v * S.w[0][a];
+            sdx += v * S.dw[0][a];
+          }
+          g[0] += sdx * S.w[1][b] * S.w[2][c];
+          g[1] += sx * S.dw[1][b] * S.w[2][c];
+          g[2] += sx * S.w[1][b] * S.dw[2][c];
+          pot += sx * S.w[1][b] * S.w[2][c];
         }
-        g[0] += sdx * S.w[1][b] * S.w[2][c];
-        g[1] += sx * S.dw[1][b] * S.w[2][c];
-        g[2] += sx * S.w[1][b] * S.dw[2][c];
-        pot += sx * S.w[1][b] * S.w[2][c];
+    } else {
+      constexpr int NE = ORDER + 3;   // widened stencil
+      M we[3][NE], ge[3][NE];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int i = 0; i < NE; ++i) we[d][i] = (i >= 1 && i <= S.N) ? S.w[d][i - 1] : (M)0;
+#pragma unroll
+        for (int i = 0; i < NE; ++i)
+          ge[d][i] = (M)0.5 * ((i >= 1 ? we[d][i - 1] : (M)0) - (i + 1 < NE ? we[d][i + 1] : (M)0));
       }
+      const M* corner = phi + (m.base - 1 - nx - nxy);
+#pragma unroll
+      for (int c = 0; c < NE; ++c)
+#pragma unroll
+        for (int b = 0; b < NE; ++b) {
+          const M* row = corner + c * nxy + (long long)b * nx;
+          M sw = 0, sg = 0;
+#pragma unroll
+          for (int a = 0; a < NE; ++a) {
+            const M v = row[a];
+            sw += v * we[0][a];
+            sg += v * ge[0][a];
+          }
+          g[0] += sg * we[1][b] * we[2][c];
+          g[1] += sw * ge[1][b] * we[2][c];
+          g[2] += sw * we[1][b] * ge[2][c];
+          pot += sw * we[1][b] * we[2][c];
+        }
+    }
     const double fs = pl->fscale;
     const uint32_t i = perm[j];
     double fpm[3], fp[3] = {0, 0, 0}, ft[3];
@@ -389,10 +426,16 @@ template <typename R, typename M>
 void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
                    const uint32_t* perm, const Geo& geo, const Place* pl, const M* phi,
                    GatherOut out, double* energy, hipStream_t st) {
-  if (geo.order == 1)
-    k_gather<R, M, 1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
-  else
-    k_gather<R, M, 2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy);
+#define P3M_GATHER(O, G) \
+  k_gather<R, M, O, G><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy)
+  if (geo.gather == 0) {
+    if (geo.order == 1) P3M_GATHER(1, 0);
+    else P3M_GATHER(2, 0);
+  } else {
+    if (geo.order == 1) P3M_GATHER(1, 1);
+    else P3M_GATHER(2, 1);
+  }
+#undef P3M_GATHER
 }
 
 void launch_deposit_grad(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,

@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kThreads) k_place_finalize(int nblk, const dou
     if (!(zoom >= 1.0) || !isfinite(zoom)) { zoom = 1.0; atomicOr(status, kBitDomain); }
     // a replayed placement must still hold every stencil
     for (int d = 0; d < 3; ++d) {
-      double usable = (double)(geo.order == 1 ? geo.grid[d] - 1 : geo.grid[d] - 2);
+      const double usable = usable_nodes(geo, d);
       double hp = zoom * geo.h[d];
       double c = (double)(geo.grid[d] - 1) * 0.5;
       double ulo = (s[d][0] - x0[d]) / hp, uhi = (s[3 + d][0] - x0[d]) / hp;
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(kThreads) k_place_finalize(int nblk, const dou
     for (int d = 0; d < 3; ++d) {
       double a = s[d][0], b = s[3 + d][0];
       if (!(a <= b)) { a = 0.0; b = 0.0; }  // no finite position on this axis
-      double usable = (double)(geo.order == 1 ? geo.grid[d] - 1 : geo.grid[d] - 2);
+      const double usable = usable_nodes(geo, d);
       double need = (b - a) * (1.0 + 1e-6) / (usable * geo.h[d]);
       if (need > zoom) zoom = need;
     }

@@ -204,14 +204,15 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
   bool out = false;
   for (int d = 0; d < 3; ++d) {
     double u = (xi[d] - P.x0[d]) * P.inv_hp[d];
+    const int mg = geo.gather ? 1 : 0;   // stencil kept off the outer node layer
     if (geo.order == 1) {
       double fl = floor(u);
-      b[d] = floor_clamp(u, 0, geo.grid[d] - 2);
+      b[d] = floor_clamp(u, mg, geo.grid[d] - 2 - mg);
       out |= (double)b[d] != fl;
       f[d] = u - (double)b[d];
     } else {
       double fl = floor(u + 0.5);
-      int cc = floor_clamp(u + 0.5, 1, geo.grid[d] - 2);
+      int cc = floor_clamp(u + 0.5, 1 + mg, geo.grid[d] - 2 - mg);
       out |= (double)cc != fl;
       f[d] = u - (double)cc;
       b[d] = cc - 1;

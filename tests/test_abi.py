@@ -36,7 +36,7 @@ def test_default_opts_and_argument_errors_without_gpu():
     L = p3m.lib()
     o = p3m.Opts()
     assert L.p3m_default_opts(ctypes.byref(o)) == p3m.OK
-    assert (o.order, o.precision, o.zoom, o.reserved0, o.reserved) == (p3m.TSC, p3m.FP64, 1, 0, 0)
+    assert (o.order, o.precision, o.zoom, o.gather, o.reserved) == (p3m.TSC, p3m.FP64, 1, p3m.GATHER_VARIATIONAL, 0)
     assert o.ke == pytest.approx(8.9875517923e9)
     assert L.p3m_default_opts(None) == p3m.EINVAL
     ctx = ctypes.c_void_p()
