@@ -74,6 +74,8 @@ def lib():
             "oracle_deposit": (i32, [i64, P, P, P, P, P, i32, P]),
             "oracle_green": (dbl, [i64, i64, i64, P, dbl]),
             "oracle_conv_direct": (None, [P, P, dbl, P, P]),
+            "oracle_phi_image_point": (dbl, [P, P, P, dbl, dbl, P, P]),
+            "oracle_conv_direct_image": (None, [P, P, P, dbl, dbl, P, P]),
             "oracle_phi_at": (None, [P, P, dbl, P, i64, P, P]),
             "oracle_stencil_nodes": (i32, [P, P, P, P, i32, P]),
             "oracle_gather": (i32, [i64, P, P, P, P, P, i32, P, dbl, P]),
@@ -108,7 +110,7 @@ class Params:
     """Run parameters of one P3M configuration (SI units)."""
 
     def __init__(self, grid, h, r_cut, split, order, ke_q2, m=1.0, dt=0.0, zoom=True, qw=None,
-                 gather="variational"):
+                 gather="variational", cathode_z=None):
         self.grid = np.asarray(grid, dtype=np.int32)
         self.h = np.asarray(h, dtype=np.float64)
         self.r_cut = float(r_cut)
@@ -122,6 +124,7 @@ class Params:
         if gather not in ("variational", "momentum"):
             raise ValueError(gather)
         self.gather = gather
+        self.cathode_z = None if cathode_z is None else float(cathode_z)
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -229,6 +232,63 @@ def conv_direct(Q, grid, hp, a):
     return phi
 
 
+def image_shifted_kernel(grid, hp, a, x0, zc):
+    """Kernel of the image term on the doubled mesh: with the charge reflected
+    in z (node k -> N_z - 1 - k) the mirror images sit at z-offset
+    delta_z h_z + D from the field nodes, D = (N_z - 1) h_z + 2 (z0 - zc), so the
+    image potential is an aperiodic convolution with G shifted by D (the
+    shifted Green's function of Sec. 3.1)."""
+    D = (int(grid[2]) - 1) * hp[2] + 2.0 * (x0[2] - zc)
+    axes = []
+    for d in range(3):
+        n = int(grid[d])
+        k = np.arange(2 * n)
+        k = np.where(k < n, k, k - 2 * n)
+        axes.append(k * hp[d] + (D if d == 2 else 0.0))
+    rz, ry, rx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    r = np.sqrt(rx * rx + ry * ry + rz * rz)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        g = erf(a * r) / r
+    g[r == 0] = 2.0 * a / math.sqrt(math.pi)
+    return g
+
+
+def conv_fft_image(Q, grid, hp, a, x0, zc):
+    """phi with a grounded plane z = zc: free-space convolution minus the image
+    term, both by zero padding and numpy's FFT."""
+    nz, ny, nx = Q.shape
+    Qr = np.zeros((2 * nz, 2 * ny, 2 * nx))
+    Qr[:nz, :ny, :nx] = Q[::-1, :, :]
+    Gs = np.fft.rfftn(image_shifted_kernel(grid, hp, a, x0, zc))
+    img = np.fft.irfftn(np.fft.rfftn(Qr) * Gs, s=Qr.shape, axes=(0, 1, 2))[:nz, :ny, :nx]
+    return conv_fft(Q, grid, hp, a) - img
+
+
+def conv_direct_image(Q, grid, x0, hp, a, zc):
+    """phi with images by the plain O(M^2) sum (tiny meshes only)."""
+    Q = _f64(Q)
+    phi = np.zeros_like(Q)
+    lib().oracle_conv_direct_image(_p(np.asarray(grid, np.int32)), _p(_f64(x0)), _p(_f64(hp)), a,
+                                   float(zc), _p(Q), _p(phi))
+    return phi
+
+
+def phi_image_point(Q, grid, x0, hp, a, zc, y):
+    """Potential of the mesh charge and its images at the point y."""
+    return lib().oracle_phi_image_point(_p(np.asarray(grid, np.int32)), _p(_f64(x0)), _p(_f64(hp)), a,
+                                        float(zc), _p(_f64(Q)), _p(_f64(y)))
+
+
+def mesh_potential(Q, prm, pl, direct=False):
+    """The long-range potential on the mesh: free space, or with the grounded
+    plane when prm.cathode_z is set."""
+    if prm.cathode_z is None:
+        return (conv_direct if direct else conv_fft)(Q, prm.grid, pl["hp"], pl["a"])
+    if direct:
+        return conv_direct_image(Q, prm.grid, pl["x0"], pl["hp"], pl["a"], prm.cathode_z)
+    return conv_fft_image(Q, prm.grid, pl["hp"], pl["a"], pl["x0"], prm.cathode_z)
+
+
 def phi_at(Q, grid, hp, a, nodes):
     Q = _f64(Q)
     nodes = np.ascontiguousarray(nodes, dtype=np.int64)
@@ -266,8 +326,7 @@ def forces(x, prm, parts=False, brute=False, direct=False, pl=None):
         pl = placement(x, prm)
     fpp = (pp_brute if brute else pp_cells)(x, prm, pl["rc"], pl["a"])
     Q = deposit(x, prm, pl)
-    conv = conv_direct if direct else conv_fft
-    phi = conv(Q, prm.grid, pl["hp"], pl["a"])
+    phi = mesh_potential(Q, prm, pl, direct=direct)
     fpm = gather(x, prm, pl, phi)
     if parts:
         return fpp + fpm, {"pp": fpp, "pm": fpm, "Q": Q, "phi": phi, "pl": pl}
@@ -312,7 +371,7 @@ def emittance(x, p, m, axis):
 def diagnostics(x, p, prm, brute_pp=False):
     pl = placement(x, prm)
     Q = deposit(x, prm, pl)
-    phi = conv_fft(Q, prm.grid, pl["hp"], pl["a"])
+    phi = mesh_potential(Q, prm, pl)
     if brute_pp:
         upp = pp_energy(x, prm, pl["rc"], pl["a"])
     else:
@@ -346,11 +405,11 @@ def hvp(x, v, prm, pl, brute=True):
     lib().oracle_pp_hvp(len(x), _p(x), _p(prm.qw), pl["rc"], pl["a"], prm.ke_q2, _p(v), _p(out_pp))
     g = prm.grid
     Q = deposit(x, prm, pl)
-    phi = conv_fft(Q, g, pl["hp"], pl["a"])
+    phi = mesh_potential(Q, prm, pl)
     R = np.zeros_like(Q)
     _check(lib().oracle_deposit_grad(len(x), _p(x), _p(prm.qw), _p(g), _p(pl["x0"]), _p(pl["hp"]),
                                      prm.order, _p(v), _p(R)), "deposit_grad")
-    psi = conv_fft(R, g, pl["hp"], pl["a"])
+    psi = mesh_potential(R, prm, pl)
     out_pm = np.zeros_like(x)
     _check(lib().oracle_gather_hvp(len(x), _p(x), _p(prm.qw), _p(g), _p(pl["x0"]), _p(pl["hp"]),
                                    prm.order, _p(phi), _p(psi), _p(v), prm.ke_q2, _p(out_pm)),

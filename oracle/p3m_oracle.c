@@ -359,6 +359,49 @@ void oracle_phi_at(const int32_t *grid, const double *hp, double a, const double
     }
 }
 
+/* Grounded plane z = zc (Sec. 3.1, eq. GreenFunc_planar_cathode with the
+ * mirror map of eq. symmetry_planar_cathode): every node charge acts through
+ * the screened kernel together with its mirror image of opposite sign.
+ * Potential of the mesh charge at an arbitrary point y (mesh origin x0). */
+static double green_r(double r, double a)
+{
+    if (r == 0.0) return 2.0 * a / sqrt(OR_PI);
+    return erf(a * r) / r;
+}
+
+double oracle_phi_image_point(const int32_t *grid, const double *x0, const double *hp, double a,
+                              double zc, const double *Q, const double *y)
+{
+    int64_t nx = grid[0], ny = grid[1], nz = grid[2];
+    int64_t M = nx * ny * nz;
+    double s = 0.0;
+    for (int64_t k = 0; k < M; ++k) {
+        if (Q[k] == 0.0) continue;
+        int64_t kx = k % nx, ky = (k / nx) % ny, kz = k / (nx * ny);
+        double px = x0[0] + kx * hp[0], py = x0[1] + ky * hp[1], pz = x0[2] + kz * hp[2];
+        double mz = 2.0 * zc - pz;               /* S(p) */
+        double dx = y[0] - px, dy = y[1] - py;
+        double r1 = sqrt(dx * dx + dy * dy + (y[2] - pz) * (y[2] - pz));
+        double r2 = sqrt(dx * dx + dy * dy + (y[2] - mz) * (y[2] - mz));
+        s += Q[k] * (green_r(r1, a) - green_r(r2, a));
+    }
+    return s;
+}
+
+/* phi_m for every node by the plain O(M^2) sum with images. */
+void oracle_conv_direct_image(const int32_t *grid, const double *x0, const double *hp, double a,
+                              double zc, const double *Q, double *phi)
+{
+    int64_t nx = grid[0], ny = grid[1], nz = grid[2];
+    int64_t M = nx * ny * nz;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t m = 0; m < M; ++m) {
+        int64_t mx = m % nx, my = (m / nx) % ny, mz = m / (nx * ny);
+        double y[3] = {x0[0] + mx * hp[0], x0[1] + my * hp[1], x0[2] + mz * hp[2]};
+        phi[m] = oracle_phi_image_point(grid, x0, hp, a, zc, Q, y);
+    }
+}
+
 /* Mesh nodes touched by particle i's stencil (for sampled checks). Returns
  * the count ((order+1)^3) and writes the linear node indices. */
 int oracle_stencil_nodes(const double *xi, const int32_t *grid, const double *x0,

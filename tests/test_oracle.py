@@ -347,6 +347,99 @@ def test_momentum_two_particles_far_limit():
     assert max(errs) < 0.03
 
 
+# ---- grounded planar cathode (image charges, shifted Green's function) -------------
+
+@pytest.mark.parametrize("grid,zc_off", [((4, 5, 6), -3.7), ((6, 6, 6), -0.45), ((5, 3, 4), 1.6)])
+def test_image_fft_route_equals_direct_sum(grid, zc_off):
+    """Reflected charge convolved with the shifted kernel (the FFT route) equals
+    the plain sum over every node charge and its mirror image, for a plane
+    below the mesh, just below it, and through it."""
+    rng = np.random.default_rng(31)
+    Q = rng.standard_normal(grid[::-1])
+    hp = np.array([0.3, 0.45, 0.25])
+    x0 = np.array([0.1, -0.2, 0.7])
+    zc = x0[2] + zc_off * hp[2]
+    a = 1.3
+    f = O.conv_fft_image(Q, grid, hp, a, x0, zc)
+    d = O.conv_direct_image(Q, grid, x0, hp, a, zc)
+    assert np.abs(f - d).max() <= 1e-12 * np.abs(d).max()
+
+
+def test_image_potential_vanishes_on_the_plane():
+    """Every point of the grounded plane is equidistant from a charge and its
+    image: the potential is zero there (direct sum at arbitrary points, and the
+    FFT route at mesh nodes lying on the plane)."""
+    rng = np.random.default_rng(32)
+    grid = (6, 5, 7)
+    Q = rng.random(grid[::-1])
+    Q[:3] = 0.0                         # charges only above the plane
+    hp = np.array([0.3, 0.3, 0.2])
+    x0 = np.array([0.0, 0.0, 0.0])
+    zc = x0[2] + 2 * hp[2]              # the plane through node layer z = 2
+    a = 2.0
+    scale = np.abs(Q).sum() * 2 * a / math.sqrt(math.pi)
+    for _ in range(10):
+        y = np.array([rng.random() * 2, rng.random() * 2, zc])
+        assert abs(O.phi_image_point(Q, grid, x0, hp, a, zc, y)) <= 1e-14 * scale
+    phi = O.conv_fft_image(Q, grid, hp, a, x0, zc)
+    assert np.abs(phi[2]).max() <= 1e-13 * scale
+
+
+def test_image_force_on_a_lone_charge():
+    """A charge at height d attracts to the plane like its mirror image -q at
+    distance 2d: with a smooth kernel (a h = 0.25) and 2d = 8h the mesh force
+    with the plane, less the same mesh force without it, matches the
+    closed-form erf(a r)/r pair force at r = 2d."""
+    from scipy.special import erf
+    rng = np.random.default_rng(33)
+    h, a = 1.0, 0.25
+    errs = []
+    for _ in range(6):
+        x = np.array([rng.random(3) * 0.7 + 8.0])
+        zc = x[0, 2] - 4.0 * h
+        kw = dict(grid=(24, 24, 24), h=(h, h, h), r_cut=1e-9, split=a, order=2, ke_q2=1.0)
+        prm_i = O.Params(kw["grid"], kw["h"], kw["r_cut"], a, 2, 1.0, cathode_z=zc)
+        prm_f = O.Params(kw["grid"], kw["h"], kw["r_cut"], a, 2, 1.0)
+        x2 = np.vstack([x, x + 3.0 + rng.random(3)])   # a second particle only moves the mesh
+        pl = O.placement(x2, prm_f)
+        Q = O.deposit(x, prm_f, pl)
+        f_i = O.gather(x, prm_i, pl, O.mesh_potential(Q, prm_i, pl))
+        f_f = O.gather(x, prm_f, pl, O.mesh_potential(Q, prm_f, pl))
+        r = 2 * (x[0, 2] - zc)
+        g = erf(a * r) / r ** 2 - 2 * a / math.sqrt(math.pi) * math.exp(-(a * r) ** 2) / r
+        exact = np.array([0.0, 0.0, -g])       # toward the plane
+        errs.append(np.linalg.norm((f_i - f_f)[0] - exact) / g)
+    assert max(errs) < 0.03
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_image_pm_force_is_minus_energy_gradient(order):
+    """With the plane the mesh energy is still a symmetric quadratic form of the
+    node charges (|x - S(y)| = |y - S(x)|), so F_PM = -dU_PM/dxi."""
+    x = _rand_bunch(40, 34, scale=0.5)
+    zc = x[:, 2].min() - 0.9
+    prm = O.Params((12, 12, 12), (0.4, 0.4, 0.4), 0.8, 3.0 / 0.8, order, 1.0, cathode_z=zc)
+    pl = O.placement(x, prm)
+    pl["x0"] = pl["x0"] - 0.013
+    F, parts = O.forces(x, prm, parts=True, pl=pl)
+
+    def upm(xx):
+        Q = O.deposit(xx, prm, pl)
+        return 0.5 * (Q * O.mesh_potential(Q, prm, pl)).sum()
+
+    eps = 1e-7
+    for i, d in [(0, 0), (3, 1), (17, 2), (39, 2)]:
+        u = (x[i, d] - pl["x0"][d]) / pl["hp"][d]
+        knot = u - math.floor(u) if order == 1 else u + 0.5 - math.floor(u + 0.5)
+        if min(knot, 1 - knot) < 1e-3:
+            continue
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += eps
+        xm[i, d] -= eps
+        fd = -(upm(xp) - upm(xm)) / (2 * eps)
+        assert fd == pytest.approx(parts["pm"][i, d], rel=1e-5, abs=1e-6 * np.abs(parts["pm"]).max())
+
+
 # ---- whole force ----------------------------------------------------------------
 
 def test_alpha_zero_large_cutoff_equals_coulomb():
