@@ -85,6 +85,20 @@ typedef int32_t p3m_status;
 #define P3M_GATHER_VARIATIONAL 0
 #define P3M_GATHER_MOMENTUM    1
 
+/* Boundary of the long-range (mesh) problem (p3m_opts.boundary).
+ * OPEN: free space (Sec. 2.1, eq. free_gf), by zero padding.
+ * CATHODE: a grounded plane z = cathode_z (Sec. 3.1): the mesh kernel of
+ *   every node charge is taken together with that of its mirror image of
+ *   opposite sign (eq. GreenFunc_planar_cathode, mirror map eq.
+ *   symmetry_planar_cathode), computed with the shifted Green's function of
+ *   that section so the gap to the images is never meshed. The pair (PP)
+ *   part stays free-space, as in the section's scheme: a particle closer
+ *   than r_c/2 to the plane misses the short-range part of its images. The
+ *   bunch is assumed on one side of the plane. Costs one extra table build
+ *   (three float64 FFT passes) per evaluation. */
+#define P3M_BOUNDARY_OPEN    0
+#define P3M_BOUNDARY_CATHODE 1
+
 #define P3M_CIC 1             /* linear B-spline b1 (2 nodes per axis)          */
 #define P3M_TSC 2             /* quadratic B-spline b2 (3 nodes per axis)       */
 
@@ -102,6 +116,9 @@ typedef struct {
     double ke;          /* Coulomb constant 1/(4 pi eps0)     [8.9875517923e9]    */
     double q;           /* macro-particle charge, C                        [1.0]  */
     double m;           /* macro-particle mass, kg                         [1.0]  */
+    int32_t boundary;   /* P3M_BOUNDARY_OPEN or _CATHODE                   [OPEN] */
+    int32_t reserved2;  /* must be 0                                               */
+    double cathode_z;   /* plane position for P3M_BOUNDARY_CATHODE, m       [0.0]  */
 } p3m_opts;
 
 /* Fill *opts with the defaults shown in brackets above. */

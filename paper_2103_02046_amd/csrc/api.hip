@@ -55,6 +55,10 @@ struct p3m_ctx {
   double* bbox_part = nullptr;
   double* acc = nullptr;        // 64 doubles of reduction scratch
   double* ghat = nullptr;
+  // grounded plane: image table (rebuilt per evaluation), scratch, twiddles
+  C2<double>* gimg = nullptr;
+  double *gimg_t1 = nullptr, *gimg_t2 = nullptr;
+  C2<double>* tw64[3] = {nullptr, nullptr, nullptr};
   // step
   double* fcache = nullptr;     // [cap][3]
   bool force_cached = false;
@@ -222,6 +226,15 @@ void place(p3m_ctx* ctx, int64_t n, const double* x, const double* place_in, dou
   launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_in, ctx->place, place_out, ctx->status, st);
 }
 
+// Image table for the current placement (grounded plane only); returns the
+// table to hand to the convolution, or nullptr for free space.
+const C2<double>* image_table(p3m_ctx* ctx, hipStream_t st) {
+  if (!ctx->geo.cathode) return nullptr;
+  const C2<double>* tw[3] = {ctx->tw64[0], ctx->tw64[1], ctx->tw64[2]};
+  build_image_table(ctx->geo, ctx->place, ctx->gimg_t1, ctx->gimg_t2, ctx->gimg, tw, st);
+  return ctx->gimg;
+}
+
 // Everything after the placement: linked cells, PP, mesh, gather. Particle
 // records in R, the mesh (charge, transform, potential) of engine EM in M.
 template <typename R, typename M>
@@ -251,7 +264,7 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   {
     StageTimer t(ctx, 5, st);
     const C2<M>* tw[3] = {EM.tw[0], EM.tw[1], EM.tw[2]};
-    launch_convolve<M>(g, EM.Q, EM.spec, ctx->ghat, tw, EM.phi, st);
+    launch_convolve<M>(g, EM.Q, EM.spec, ctx->ghat, image_table(ctx, st), tw, EM.phi, st);
   }
   {
     StageTimer t(ctx, 6, st);
@@ -291,10 +304,11 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
   launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, st);
-  launch_convolve<double>(g, E.Q, E.spec, ctx->ghat, tw, E.phi, st);
+  const C2<double>* gimg = image_table(ctx, st);
+  launch_convolve<double>(g, E.Q, E.spec, ctx->ghat, gimg, tw, E.phi, st);
   launch_fill(ctx->Rm, mesh_nodes(g) * sizeof(double), st);
   launch_deposit_grad(n, E.pp, E.mesh, ctx->v_sorted, g, ctx->Rm, st);
-  launch_convolve<double>(g, ctx->Rm, E.spec, ctx->ghat, tw, ctx->psi, st);
+  launch_convolve<double>(g, ctx->Rm, E.spec, ctx->ghat, gimg, tw, ctx->psi, st);
   launch_gather_hvp(n, E.pp, E.mesh, ctx->hpp, ctx->v_sorted, ctx->perm, g, ctx->place, E.phi, ctx->psi,
                     out, st);
   ctx->last_precision = -1;
@@ -326,7 +340,9 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   else p3m_default_opts(&o);
   if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
   if (o.gather != P3M_GATHER_VARIATIONAL && o.gather != P3M_GATHER_MOMENTUM) return P3M_EINVAL;
-  if (o.reserved != 0) return P3M_EINVAL;
+  if (o.reserved != 0 || o.reserved2 != 0) return P3M_EINVAL;
+  if (o.boundary != P3M_BOUNDARY_OPEN && o.boundary != P3M_BOUNDARY_CATHODE) return P3M_EINVAL;
+  if (o.boundary == P3M_BOUNDARY_CATHODE && !std::isfinite(o.cathode_z)) return P3M_EINVAL;
   if (o.precision != P3M_FP64 && o.precision != P3M_FP32C) return P3M_EINVAL;
   if (o.mesh_precision != P3M_MESH_AUTO && o.mesh_precision != P3M_MESH_F32 &&
       o.mesh_precision != P3M_MESH_F64)
@@ -352,6 +368,8 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   g.order = o.order;
   g.zoom = o.zoom ? 1 : 0;
   g.gather = o.gather == P3M_GATHER_MOMENTUM ? 1 : 0;
+  g.cathode = o.boundary == P3M_BOUNDARY_CATHODE ? 1 : 0;
+  g.zc = g.cathode ? o.cathode_z : 0.0;
   g.ncells = 1;
   for (int d = 0; d < 3; ++d) {
     g.grid[d] = grid[d];
@@ -407,6 +425,20 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   for (int d = 0; d < 3; ++d) dfree(cosv[d]);
   dfree(scratch);
   if (e != hipSuccess) return bail(P3M_EHIP);
+  if (g.cathode) {
+    const size_t ne = image_table_elems(g);
+    if (dalloc(&ctx->gimg, ne) != hipSuccess || dalloc(&ctx->gimg_t1, ne) != hipSuccess ||
+        dalloc(&ctx->gimg_t2, ne) != hipSuccess)
+      return bail(P3M_ENOMEM);
+    for (int d = 0; d < 3; ++d) {
+      const int L = 2 * grid[d];
+      std::vector<C2<double>> h(L);
+      make_twiddles<double>(L, h.data());
+      if (dalloc(&ctx->tw64[d], (size_t)L) != hipSuccess ||
+          hipMemcpy(ctx->tw64[d], h.data(), L * sizeof(C2<double>), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(P3M_ENOMEM);
+    }
+  }
   *out = ctx;
   return P3M_OK;
 }
@@ -657,6 +689,10 @@ void p3m_destroy(p3m_ctx* ctx) {
   dfree(ctx->bbox_part);
   dfree(ctx->acc);
   dfree(ctx->ghat);
+  dfree(ctx->gimg);
+  dfree(ctx->gimg_t1);
+  dfree(ctx->gimg_t2);
+  for (int d = 0; d < 3; ++d) dfree(ctx->tw64[d]);
   dfree(ctx->fcache);
   dfree(ctx->v_sorted);
   dfree(ctx->hpp);

@@ -44,6 +44,8 @@ struct Geo {
   int order;           // 1 CIC, 2 TSC
   int zoom;            // 1 zoom on
   int gather;          // 0 variational, 1 momentum-conserving (mesh E by central differences)
+  int cathode;         // 1: grounded plane z = zc (image charges on the mesh)
+  double zc;           // plane position (m)
 };
 
 // Nodes the bunch may span so that every assignment stencil lies on the mesh

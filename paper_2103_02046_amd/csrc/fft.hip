@@ -203,9 +203,10 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restric
 }
 
 // ---- z pass: forward, times Ghat, inverse, keep z < N_z
-template <typename T, int L>
+template <typename T, int L, bool IMG>
 __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restrict__ S,
                                                        const double* __restrict__ ghat,
+                                                       const C2<double>* __restrict__ gimg,
                                                        const C2<T>* __restrict__ tw) {
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2;
@@ -226,13 +227,43 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restric
   fft_lines<T, L, B>(s, tw);
   const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
   const long long gplane = (long long)(geo.grid[1] + 1) * K;
-  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
-    const int kz = e / B, b = e % B;
-    const int kzp = kz <= N ? kz : L - kz;
-    const int kx = kx0 + b < K ? kx0 + b : K - 1;
-    const T g = (T)ghat[kzp * gplane + (long long)kyp * K + kx];
-    C2<T> v = s[e];
-    s[e] = C2<T>{g * v.x, -(g * v.y)};   // conj(g Z): input of the inverse
+  if constexpr (!IMG) {
+    for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+      const int kz = e / B, b = e % B;
+      const int kzp = kz <= N ? kz : L - kz;
+      const int kx = kx0 + b < K ? kx0 + b : K - 1;
+      const T g = (T)ghat[kzp * gplane + (long long)kyp * K + kx];
+      C2<T> v = s[e];
+      s[e] = C2<T>{g * v.x, -(g * v.y)};   // conj(g Z): input of the inverse
+    }
+  } else {
+    // grounded plane: minus the image term, Gs(k) Z(kx, ky, -kz) (the reflected
+    // charge's spectrum), Gs the shifted kernel's table with phase and scale
+    constexpr int PER = (L * B + kFftThreads - 1) / kFftThreads;
+    C2<T> nv[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int e = threadIdx.x + it * kFftThreads;
+      if (e < L * B) {
+        const int kz = e / B, b = e % B;
+        const int kzp = kz <= N ? kz : L - kz;
+        const int kzm = kz == 0 ? 0 : L - kz;
+        const int kx = kx0 + b < K ? kx0 + b : K - 1;
+        const T g = (T)ghat[kzp * gplane + (long long)kyp * K + kx];
+        const C2<double> gd = gimg[(long long)kz * gplane + (long long)kyp * K + kx];
+        const C2<T> gs{(T)gd.x, (T)gd.y};
+        const C2<T> v = s[e], vm = s[kzm * B + b];
+        const T zr = g * v.x - (gs.x * vm.x - gs.y * vm.y);
+        const T zi = g * v.y - (gs.x * vm.y + gs.y * vm.x);
+        nv[it] = C2<T>{zr, -zi};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int e = threadIdx.x + it * kFftThreads;
+      if (e < L * B) s[e] = nv[it];
+    }
   }
   __syncthreads();
   fft_lines<T, L, B>(s, tw);
@@ -313,6 +344,112 @@ __global__ void k_green_dct(int axis, Geo geo, const double* __restrict__ in, do
   (void)ext;
 }
 
+// ---- Fourier table of the image term (grounded plane z = zc), float64 ------
+// With the charge reflected in z (node k -> N_z - 1 - k) the mirror images of
+// the nodes sit at z-offset delta_z h_z + D from the field nodes,
+// D = (N_z - 1) h_z + 2 (z0 - zc): the image potential is the aperiodic
+// convolution of the reflected charge with G shifted by D in z (the shifted
+// Green's function of Sec. 3.1, eq. GreenFunc_planar_cathode with the mirror
+// map of eq. symmetry_planar_cathode). The kernel is even in x and y, so its
+// table keeps k_x, k_y in [0, N]; in z it is complex over all 2 N_z
+// frequencies. The reflection becomes Z(k_z) -> e^{-2 pi i k_z (N_z-1)/L_z}
+// Z(-k_z), whose phase is folded in here with the 1/(L_x L_y L_z) of the
+// inverse. Built per evaluation (D follows the placement), in internal units.
+
+// x: sample and transform lines over x for every (y offset, z slot); keep
+// the real part (even input) for k_x in [0, N_x].
+template <int L>
+__global__ void __launch_bounds__(kFftThreads) k_gimg_x(Geo geo, const Place* __restrict__ pl,
+                                                        double* __restrict__ t1,
+                                                        const C2<double>* __restrict__ tw) {
+  constexpr int B = Cfg<double, L>::B;
+  constexpr int N = L / 2;
+  __shared__ C2<double> s[L * B];
+  const int ny1 = geo.grid[1] + 1, nz = geo.grid[2], lz = 2 * nz;
+  const long long lines = (long long)ny1 * lz;
+  const long long l0 = (long long)blockIdx.x * B;
+  const double du = (nz - 1) * geo.hu[2] + 2.0 * (pl->x0[2] - geo.zc) * pl->inv_lu;
+  const double g0 = 1.12837916709551257390 * geo.kappa;
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+    const int p = e / B, b = e % B;
+    const long long line = l0 + b;
+    double v = 0.0;
+    if (line < lines) {
+      const int iy = (int)(line % ny1), jz = (int)(line / ny1);
+      if (jz != nz) {   // slot nz (offset +-N_z) is never reached by a node pair
+        const int dx = p <= N ? p : L - p;
+        const int dz = jz < nz ? jz : jz - lz;
+        const double rx = dx * geo.hu[0], ry = iy * geo.hu[1], rz = dz * geo.hu[2] + du;
+        const double rho = sqrt(rx * rx + ry * ry + rz * rz);
+        v = rho == 0.0 ? g0 : erf(geo.kappa * rho) / rho;
+      }
+    }
+    s[e] = C2<double>{v, 0.0};
+  }
+  __syncthreads();
+  fft_lines<double, L, B>(s, tw);
+  for (int e = threadIdx.x; e < (N + 1) * B; e += kFftThreads) {
+    const int k = e / B, b = e % B;
+    const long long line = l0 + b;
+    if (line < lines) t1[line * (N + 1) + k] = s[k * B + b].x;
+  }
+}
+
+// y: even lines over y for every (k_x, z slot); real part for k_y in [0, N_y].
+template <int L>
+__global__ void __launch_bounds__(kFftThreads) k_gimg_y(Geo geo, const double* __restrict__ t1,
+                                                        double* __restrict__ t2,
+                                                        const C2<double>* __restrict__ tw) {
+  constexpr int B = Cfg<double, L>::B;
+  constexpr int N = L / 2;
+  __shared__ C2<double> s[L * B];
+  const int K = geo.grid[0] + 1, ny1 = N + 1;
+  const int nch = (K + B - 1) / B;
+  const int jz = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+    const int p = e / B, b = e % B;
+    const int iy = p <= N ? p : L - p;
+    double v = 0.0;
+    if (kx0 + b < K) v = t1[((long long)jz * ny1 + iy) * K + kx0 + b];
+    s[e] = C2<double>{v, 0.0};
+  }
+  __syncthreads();
+  fft_lines<double, L, B>(s, tw);
+  for (int e = threadIdx.x; e < ny1 * B; e += kFftThreads) {
+    const int k = e / B, b = e % B;
+    if (kx0 + b < K) t2[((long long)jz * ny1 + k) * K + kx0 + b] = s[k * B + b].x;
+  }
+}
+
+// z: complex lines over all z slots for every (k_x, k_y); phase and scale.
+template <int L>
+__global__ void __launch_bounds__(kFftThreads) k_gimg_z(Geo geo, const double* __restrict__ t2,
+                                                        C2<double>* __restrict__ gimg,
+                                                        const C2<double>* __restrict__ tw) {
+  constexpr int B = Cfg<double, L>::B;
+  __shared__ C2<double> s[L * B];
+  const int K = geo.grid[0] + 1, ny1 = geo.grid[1] + 1, nz = geo.grid[2];
+  const int nch = (K + B - 1) / B;
+  const int ky = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+    const int p = e / B, b = e % B;
+    double v = 0.0;
+    if (kx0 + b < K) v = t2[((long long)p * ny1 + ky) * K + kx0 + b];
+    s[e] = C2<double>{v, 0.0};
+  }
+  __syncthreads();
+  fft_lines<double, L, B>(s, tw);
+  const double scale = 1.0 / (8.0 * (double)geo.grid[0] * geo.grid[1] * nz);
+  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
+    const int k = e / B, b = e % B;
+    if (kx0 + b < K) {
+      const C2<double> ph = tw[((long long)k * (nz - 1)) % L];   // e^{-2 pi i k (N_z - 1) / L}
+      const C2<double> v = cmul(s[e], ph);
+      gimg[((long long)k * ny1 + ky) * K + kx0 + b] = C2<double>{v.x * scale, v.y * scale};
+    }
+  }
+}
+
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 template <typename T, int L>
@@ -337,11 +474,15 @@ void run_y(const Geo& g, C2<T>* S, const C2<T>* tw, hipStream_t st) {
   k_fft_y<T, L, INV><<<blocks, kFftThreads, 0, st>>>(g, S, tw);
 }
 template <typename T, int L>
-void run_z(const Geo& g, C2<T>* S, const double* ghat, const C2<T>* tw, hipStream_t st) {
+void run_z(const Geo& g, C2<T>* S, const double* ghat, const C2<double>* gimg, const C2<T>* tw,
+           hipStream_t st) {
   constexpr int B = Cfg<T, L>::B;
   int K = g.grid[0] + 1;
   unsigned blocks = (unsigned)(2 * g.grid[1] * ((K + B - 1) / B));
-  k_fft_z<T, L><<<blocks, kFftThreads, 0, st>>>(g, S, ghat, tw);
+  if (gimg)
+    k_fft_z<T, L, true><<<blocks, kFftThreads, 0, st>>>(g, S, ghat, gimg, tw);
+  else
+    k_fft_z<T, L, false><<<blocks, kFftThreads, 0, st>>>(g, S, ghat, nullptr, tw);
 }
 
 #define P3M_FFT_SWITCH(L_, CALL) \
@@ -369,12 +510,12 @@ size_t spectrum_elems(const Geo& g) {
 }
 
 template <typename R>
-void launch_convolve(const Geo& g, const R* Q, C2<R>* S, const double* ghat, const C2<R>* tw[3], R* phi,
-                     hipStream_t st) {
+void launch_convolve(const Geo& g, const R* Q, C2<R>* S, const double* ghat, const C2<double>* gimg,
+                     const C2<R>* tw[3], R* phi, hipStream_t st) {
   const int Lx = 2 * g.grid[0], Ly = 2 * g.grid[1], Lz = 2 * g.grid[2];
 #define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], st)
 #define YF(L) run_y<R, L, false>(g, S, tw[1], st)
-#define ZZ(L) run_z<R, L>(g, S, ghat, tw[2], st)
+#define ZZ(L) run_z<R, L>(g, S, ghat, gimg, tw[2], st)
 #define YI(L) run_y<R, L, true>(g, S, tw[1], st)
 #define XI(L) run_x_inv<R, L>(g, S, phi, tw[0], st)
   P3M_FFT_SWITCH(Lx, XF)
@@ -407,9 +548,34 @@ void build_green_table(const Geo& g, double* table, double* scratch, double* con
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(2, g, scratch, table, cosv[2], scale);
 }
 
-template void launch_convolve<float>(const Geo&, const float*, C2<float>*, const double*, const C2<float>*[3],
-                                     float*, hipStream_t);
-template void launch_convolve<double>(const Geo&, const double*, C2<double>*, const double*,
+size_t image_table_elems(const Geo& g) {
+  return (size_t)(g.grid[0] + 1) * (g.grid[1] + 1) * (2 * (size_t)g.grid[2]);
+}
+
+void build_image_table(const Geo& g, const Place* pl, double* t1, double* t2, C2<double>* gimg,
+                       const C2<double>* const tw[3], hipStream_t st) {
+  const int Lx = 2 * g.grid[0], Ly = 2 * g.grid[1], Lz = 2 * g.grid[2];
+  const long long K = g.grid[0] + 1, ny1 = g.grid[1] + 1;
+#define GX(L)                                                                                    \
+  k_gimg_x<L><<<(unsigned)((ny1 * Lz + Cfg<double, L>::B - 1) / Cfg<double, L>::B), kFftThreads, 0, \
+                st>>>(g, pl, t1, tw[0])
+#define GY(L)                                                                                 \
+  k_gimg_y<L><<<(unsigned)(Lz * ((K + Cfg<double, L>::B - 1) / Cfg<double, L>::B)), kFftThreads, 0, \
+                st>>>(g, t1, t2, tw[1])
+#define GZ(L)                                                                                  \
+  k_gimg_z<L><<<(unsigned)(ny1 * ((K + Cfg<double, L>::B - 1) / Cfg<double, L>::B)), kFftThreads, 0, \
+                st>>>(g, t2, gimg, tw[2])
+  P3M_FFT_SWITCH(Lx, GX)
+  P3M_FFT_SWITCH(Ly, GY)
+  P3M_FFT_SWITCH(Lz, GZ)
+#undef GX
+#undef GY
+#undef GZ
+}
+
+template void launch_convolve<float>(const Geo&, const float*, C2<float>*, const double*, const C2<double>*,
+                                     const C2<float>*[3], float*, hipStream_t);
+template void launch_convolve<double>(const Geo&, const double*, C2<double>*, const double*, const C2<double>*,
                                       const C2<double>*[3], double*, hipStream_t);
 template void make_twiddles<float>(int, C2<float>*);
 template void make_twiddles<double>(int, C2<double>*);

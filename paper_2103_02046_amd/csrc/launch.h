@@ -83,10 +83,17 @@ void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale
 bool fft_supported(int nodes);
 // Spectrum buffer: complex, grid[2] x 2 grid[1] x (grid[0] + 1).
 size_t spectrum_elems(const Geo& geo);
-// phi = G (x) Q on the mesh (internal units).
+// phi = G (x) Q on the mesh (internal units); with gimg (the image table of a
+// grounded plane) minus the image term.
 template <typename R>
-void launch_convolve(const Geo& geo, const R* Q, C2<R>* spec, const double* ghat, const C2<R>* tw[3],
-                     R* phi, hipStream_t st);
+void launch_convolve(const Geo& geo, const R* Q, C2<R>* spec, const double* ghat, const C2<double>* gimg,
+                     const C2<R>* tw[3], R* phi, hipStream_t st);
+// Image table of the grounded plane z = geo.zc for the placement *pl:
+// complex, [2 grid[2]][grid[1] + 1][grid[0] + 1]; t1, t2 float64 scratch of
+// image_table_elems each; tw float64 twiddles of the three doubled lengths.
+size_t image_table_elems(const Geo& geo);
+void build_image_table(const Geo& geo, const Place* pl, double* t1, double* t2, C2<double>* gimg,
+                       const C2<double>* const tw[3], hipStream_t st);
 template <typename R>
 void make_twiddles(int L, C2<R>* host_out);
 // Fourier transform of the sampled kernel erf(kappa rho)/rho on the doubled

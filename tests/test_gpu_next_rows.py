@@ -100,3 +100,62 @@ def test_momentum_gather_refuses_adjoint():
     with pytest.raises(p3m.P3MError) as e:
         c.hvp(dev(x), dev(np.ones_like(x)))
     assert e.value.code == p3m.ESTATE
+
+
+# ---- grounded planar cathode (image charges on the mesh) ------------------------
+
+def _cathode(wl, x, precision=p3m.FP64, below=0.5e-3):
+    zc = float(x[:, 2].min()) - below
+    c = p3m.Context.from_workload(wl, precision=precision, cathode_z=zc)
+    prm = O.Params.from_workload(wl, cathode_z=zc)
+    return c, prm
+
+
+@pytest.mark.parametrize("name", ["gauss4k", "aniso"])
+def test_cathode_parity_fp64(name):
+    """Mesh force with the plane (shifted Green's function, rebuilt for each
+    placement) against the oracle's numpy-FFT image convolution, which its own
+    pins tie to the plain sum over nodes and images."""
+    wl = _case(name)
+    x, _ = wl.draw()
+    c, prm = _cathode(wl, x)
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    fpp, fpm = host(fpp), host(fpm)
+    ref, parts = O.forces(x, prm, parts=True)
+    assert rms_err(fpp, parts["pp"]) < TOL64
+    assert rms_err(fpm, parts["pm"]) < TOL64
+    # the plane pulls the bunch: the mean mesh force points toward it
+    free = p3m.Context.from_workload(wl).forces_parts(dev(x))[1]
+    assert (fpm - host(free))[:, 2].mean() < 0
+    assert c.status_sync() == p3m.OK
+
+
+def test_cathode_parity_fp32c():
+    wl = W.aniso_tsc(n=1 << 16, grid=64, steps=5)
+    x, _ = wl.draw()
+    c, prm = _cathode(wl, x, p3m.FP32C)
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    fpp, fpm = host(fpp), host(fpm)
+    ref, parts = O.forces(x, prm, parts=True)
+    e_pm, e = rms_err(fpm, parts["pm"]), rms_err(fpp + fpm, ref)
+    print(f"cathode fp32c vs oracle: pm {e_pm:.2e} total {e:.2e}")
+    assert e < TOL32 and e_pm < TOL32
+
+
+def test_cathode_step_and_hvp_parity():
+    """Leapfrog with the plane (the image table follows every new placement)
+    and the Hessian-vector product, which uses the image convolution twice."""
+    wl = W.get("gauss4k")
+    x, p = wl.draw()
+    c, prm = _cathode(wl, x)
+    xd, pd = dev(x), dev(p)
+    c.step(xd, pd, wl.dt, wl.steps)
+    xg, pg = host(xd), host(pd)
+    xr, pr, _ = O.step(x, p, prm, wl.steps)
+    assert rms_err(xg - x, xr - x) < 1e-9
+    assert rms_err(pg, pr) < 1e-9
+    v = np.random.default_rng(41).standard_normal(x.shape)
+    out = host(c.hvp(dev(x), dev(v)))
+    ref = O.hvp(x, v, prm, O.placement(x, prm))
+    assert rms_err(out, ref) < 1e-10
+    assert c.status_sync() == p3m.OK
