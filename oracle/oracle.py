@@ -110,7 +110,7 @@ class Params:
     """Run parameters of one P3M configuration (SI units)."""
 
     def __init__(self, grid, h, r_cut, split, order, ke_q2, m=1.0, dt=0.0, zoom=True, qw=None,
-                 gather="variational", cathode_z=None):
+                 gather="variational", cathode_z=None, influence="sampled"):
         self.grid = np.asarray(grid, dtype=np.int32)
         self.h = np.asarray(h, dtype=np.float64)
         self.r_cut = float(r_cut)
@@ -125,6 +125,9 @@ class Params:
             raise ValueError(gather)
         self.gather = gather
         self.cathode_z = None if cathode_z is None else float(cathode_z)
+        if influence not in ("sampled", "optimal", "principal"):
+            raise ValueError(influence)
+        self.influence = influence
 
     @classmethod
     def from_workload(cls, wl, **kw):
@@ -213,13 +216,79 @@ def green_padded(grid, hp, a):
     return g
 
 
-def conv_fft(Q, grid, hp, a):
+def bspline_ft(kh, order):
+    """Fourier transform of the cardinal B-spline of the assignment along one
+    axis at k h: sinc(k h / 2)^(p+1), sinc(x) = sin(x)/x (b1 CIC p = 1, b2 TSC p = 2)."""
+    x = 0.5 * np.asarray(kh, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        s = np.where(x == 0.0, 1.0, np.sin(x) / x)
+    return s ** (order + 1)
+
+
+def alias_sum_u2(kh, order, M):
+    """sum_{m=-M..M} U^2(k h - 2 pi m) along one axis."""
+    return sum(bspline_ft(kh - 2 * math.pi * m, order) ** 2 for m in range(-M, M + 1))
+
+
+def influence_correction(grid, hp, a, order, mode, M=2):
+    """Table correction of the optimal influence function (Sec. 3.1.2, eq.
+    Ghfinal), on numpy's rfftn layout of the doubled mesh. For point particles,
+    with the Gaussian screening folded into the reference kernel
+    (R gamma)^(k) = 4 pi exp(-k^2/(4 a^2)) / k^2 and the assignment U = prod sinc^(p+1):
+      optimal:   G = sum_m U^2(k_m) (R gamma)(k_m) / [sum_m U^2(k_m)]^2, |m_d| <= M;
+      principal: the m = 0 term alone, (R gamma)(k) / U^2(k).
+    Returned is (G - (R gamma)(k)) / (h_x h_y h_z): added to the transform of the
+    sampled kernel it makes the mesh kernel the optimal one near the origin
+    while leaving its long-range part, and with it the open boundary, as the
+    exact sampled erf(a r)/r (the difference is finite at k = 0 and short-ranged).
+    The k = 0 entry is the limit along k_x."""
+    shp = [2 * int(grid[2]), 2 * int(grid[1]), int(grid[0]) + 1]
+    kz = 2 * math.pi * np.fft.fftfreq(shp[0], d=hp[2])
+    ky = 2 * math.pi * np.fft.fftfreq(shp[1], d=hp[1])
+    kx = 2 * math.pi * np.fft.rfftfreq(2 * int(grid[0]), d=hp[0])
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    KX = KX.copy()
+    KX[0, 0, 0] = 1e-3 * math.pi / (int(grid[0]) * hp[0])     # limit k -> 0 along k_x
+    ks = (KX, KY, KZ)
+
+    def rg(kx_, ky_, kz_):
+        k2 = kx_ * kx_ + ky_ * ky_ + kz_ * kz_
+        return 4 * math.pi * np.exp(-k2 / (4 * a * a)) / k2
+
+    if mode == "principal":
+        u2 = np.ones_like(KX)
+        for d in range(3):
+            u2 = u2 * bspline_ft(ks[d] * hp[d], order) ** 2
+        G = rg(KX, KY, KZ) / u2
+    else:
+        num = np.zeros_like(KX)
+        for mz in range(-M, M + 1):
+            for my in range(-M, M + 1):
+                for mx in range(-M, M + 1):
+                    q = [KX - 2 * math.pi * mx / hp[0], KY - 2 * math.pi * my / hp[1],
+                         KZ - 2 * math.pi * mz / hp[2]]
+                    u2 = np.ones_like(KX)
+                    for d in range(3):
+                        u2 = u2 * bspline_ft(q[d] * hp[d], order) ** 2
+                    num += u2 * rg(*q)
+        den = np.ones_like(KX)
+        for d in range(3):
+            den = den * alias_sum_u2(ks[d] * hp[d], order, M)
+        G = num / den ** 2
+    return (G - rg(KX, KY, KZ)) / (hp[0] * hp[1] * hp[2])
+
+
+def conv_fft(Q, grid, hp, a, influence=None):
     """phi = G (x) Q, aperiodic, by zero padding to 2N and numpy's FFT
-    (Sec. 3 eq. phi_L as a finite convolution; Hockney's doubling)."""
+    (Sec. 3 eq. phi_L as a finite convolution; Hockney's doubling). With
+    influence = (order, mode) the kernel carries the optimal-influence
+    correction (Sec. 3.1.2)."""
     nz, ny, nx = Q.shape
     Qp = np.zeros((2 * nz, 2 * ny, 2 * nx))
     Qp[:nz, :ny, :nx] = Q
     Gk = np.fft.rfftn(green_padded(grid, hp, a))
+    if influence is not None:
+        Gk = Gk + influence_correction(grid, hp, a, influence[0], influence[1])
     phi = np.fft.irfftn(np.fft.rfftn(Qp) * Gk, s=Qp.shape, axes=(0, 1, 2))
     return np.ascontiguousarray(phi[:nz, :ny, :nx])
 
@@ -282,6 +351,10 @@ def phi_image_point(Q, grid, x0, hp, a, zc, y):
 def mesh_potential(Q, prm, pl, direct=False):
     """The long-range potential on the mesh: free space, or with the grounded
     plane when prm.cathode_z is set."""
+    if prm.influence != "sampled":
+        if direct or prm.cathode_z is not None:
+            raise ValueError("the optimal influence function is applied in the FFT route, free space")
+        return conv_fft(Q, prm.grid, pl["hp"], pl["a"], influence=(prm.order, prm.influence))
     if prm.cathode_z is None:
         return (conv_direct if direct else conv_fft)(Q, prm.grid, pl["hp"], pl["a"])
     if direct:

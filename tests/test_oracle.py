@@ -440,6 +440,106 @@ def test_image_pm_force_is_minus_energy_gradient(order):
         assert fd == pytest.approx(parts["pm"][i, d], rel=1e-5, abs=1e-6 * np.abs(parts["pm"]).max())
 
 
+# ---- optimal influence function (Sec. 3.1.2, eq. Ghfinal) --------------------------
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_bspline_alias_sums_closed_form(order):
+    """sum_m sinc^4(x + pi m) = 1 - (2/3) sin^2 x and sum_m sinc^6(x + pi m) =
+    1 - sin^2 x + (2/15) sin^4 x (x = k h / 2): the aliasing sums of the CIC and
+    TSC assignment functions in closed form."""
+    kh = np.linspace(-math.pi, math.pi, 37)
+    s2 = np.sin(0.5 * kh) ** 2
+    closed = 1 - (2.0 / 3.0) * s2 if order == 1 else 1 - s2 + (2.0 / 15.0) * s2 ** 2
+    np.testing.assert_allclose(O.alias_sum_u2(kh, order, 400), closed, rtol=1e-9)
+    np.testing.assert_allclose(O.alias_sum_u2(kh, order, 2), closed, rtol=3e-3)
+
+
+def _lr_potential_error(order, mode):
+    """rms error of the mesh's long-range potential at the particles against
+    the exact sum of erf(a r)/r over all particles (self term 2a/sqrt(pi)),
+    the quantity the optimal influence function minimises."""
+    from scipy.special import erf
+    x = _rand_bunch(600, 35)
+    prm = O.Params((24, 24, 24), (0.35, 0.35, 0.35), 0.7, 3.0 / 0.7, order, 1.0, influence=mode)
+    pl = O.placement(x, prm)
+    Q = O.deposit(x, prm, pl)
+    phi = O.mesh_potential(Q, prm, pl).ravel()
+    est = np.array([(O.deposit(x[i:i + 1], prm, pl).ravel() * phi).sum() for i in range(len(x))])
+    a = pl["a"]
+    d = np.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        G = erf(a * d) / d
+    G[d == 0] = 2 * a / math.sqrt(math.pi)
+    ref = G.sum(1)
+    return math.sqrt(((est - ref) ** 2).mean() / (ref ** 2).mean())
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_optimal_influence_lowers_the_potential_error(order):
+    e_s = _lr_potential_error(order, "sampled")
+    e_o = _lr_potential_error(order, "optimal")
+    e_p = _lr_potential_error(order, "principal")
+    assert e_o < 0.5 * e_s and e_p < 0.7 * e_s
+
+
+def test_optimal_influence_lowers_tsc_force_error_vs_coulomb():
+    """Total P3M force against the unsplit O(N^2) Coulomb sum, TSC at r_c = 2h:
+    the optimal table lowers the rms error well below the sampled kernel's."""
+    x = _rand_bunch(2000, 36)
+    e = {}
+    for mode in ("sampled", "optimal"):
+        prm = O.Params((32, 32, 32), (8 / 30,) * 3, 16 / 30, 3.0 / (16 / 30), 2, 1.0, influence=mode)
+        f = O.forces(x, prm)
+        fc = O.coulomb_brute(x, 1.0)
+        e[mode] = math.sqrt(((f - fc) ** 2).sum() / (fc ** 2).sum())
+    assert e["optimal"] < 0.6 * e["sampled"]
+
+
+def test_optimal_influence_correction_is_short_ranged():
+    """The table correction, taken back to real space on the doubled mesh, is
+    concentrated near the origin: off the axes it is below 1e-6 of its peak at
+    half the mesh, along the axes (where the separable sinc^(p+1) of the
+    assignment leaves slower tails) below 1e-3. The mesh kernel keeps the
+    erf(a r)/r tail and the zero-padded open boundary."""
+    grid = (32, 32, 32)
+    hp = np.array([0.25, 0.25, 0.25])
+    a = 3.0 / 0.5
+    for order in (1, 2):
+        C = O.influence_correction(grid, hp, a, order, "optimal")
+        D = np.fft.irfftn(C, s=(64, 64, 64), axes=(0, 1, 2))
+        d0 = abs(D[0, 0, 0])
+        for off in [(16, 0, 0), (0, 16, 0), (0, 0, 31)]:
+            assert abs(D[off[2], off[1], off[0]]) < 1e-3 * d0
+        for off in [(12, 12, 12), (16, 16, 0), (31, 31, 31)]:
+            assert abs(D[off[2], off[1], off[0]]) < 1e-6 * d0
+
+
+def test_optimal_influence_force_is_minus_energy_gradient():
+    """The corrected table is still real and even: the mesh energy stays a
+    symmetric quadratic form and F_PM = -dU_PM/dxi."""
+    x = _rand_bunch(40, 37, scale=0.5)
+    prm = O.Params((12, 12, 12), (0.4, 0.4, 0.4), 0.8, 3.0 / 0.8, 2, 1.0, influence="optimal")
+    pl = O.placement(x, prm)
+    pl["x0"] = pl["x0"] - 0.013
+    F, parts = O.forces(x, prm, parts=True, pl=pl)
+
+    def upm(xx):
+        Q = O.deposit(xx, prm, pl)
+        return 0.5 * (Q * O.mesh_potential(Q, prm, pl)).sum()
+
+    eps = 1e-7
+    for i, d in [(0, 0), (3, 1), (17, 2), (39, 1)]:
+        u = (x[i, d] - pl["x0"][d]) / pl["hp"][d]
+        knot = u + 0.5 - math.floor(u + 0.5)
+        if min(knot, 1 - knot) < 1e-3:
+            continue
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += eps
+        xm[i, d] -= eps
+        fd = -(upm(xp) - upm(xm)) / (2 * eps)
+        assert fd == pytest.approx(parts["pm"][i, d], rel=1e-5, abs=1e-6 * np.abs(parts["pm"]).max())
+
+
 # ---- whole force ----------------------------------------------------------------
 
 def test_alpha_zero_large_cutoff_equals_coulomb():
