@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--gather", default="variational", choices=["variational", "momentum"],
                     help="mesh force at the particles: variational (default) or momentum-conserving")
+    ap.add_argument("--influence", default="sampled", choices=["sampled", "optimal", "principal"],
+                    help="Fourier table of the mesh kernel (built at create)")
     ap.add_argument("--cathode", action="store_true",
                     help="grounded plane 1 mm below the bunch (image charges on the mesh)")
     ap.add_argument("--cpu-steps", type=int, default=6)
@@ -117,11 +119,14 @@ def main():
     p = torch.tensor(p0, dtype=torch.float64, device=dev)
     gmode = p3m.GATHER_MOMENTUM if args.gather == "momentum" else p3m.GATHER_VARIATIONAL
     zc = float(x0[:, 2].min()) - 1e-3 if args.cathode else None
-    ctx = p3m.Context.from_workload(wl, precision=prec, gather=gmode, cathode_z=zc)
+    infl = {"sampled": p3m.INFLUENCE_SAMPLED, "optimal": p3m.INFLUENCE_OPTIMAL,
+            "principal": p3m.INFLUENCE_PRINCIPAL}[args.influence]
+    ctx = p3m.Context.from_workload(wl, precision=prec, gather=gmode, cathode_z=zc, influence=infl)
 
     # accuracy of this precision against the float64 path on the same GPU
     f_this = ctx.forces(x)
-    f64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode, cathode_z=zc).forces(x)
+    f64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode, cathode_z=zc,
+                                    influence=infl).forces(x)
     err = float(torch.sqrt(((f_this - f64) ** 2).sum() / (f64 ** 2).sum()))
     d0 = ctx.diagnostics(x, p)
 
@@ -217,6 +222,7 @@ def main():
             if prec == p3m.FP32C else "fp64",
             "gather": args.gather,
             "boundary": "grounded plane 1 mm below the bunch" if args.cathode else "open",
+            "influence": args.influence,
             "force_rms_err_vs_fp64": err,
             "pp_pairs_per_s": pairs * args.steps / wall,
             "pairs_per_eval": pairs,

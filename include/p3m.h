@@ -99,6 +99,20 @@ typedef int32_t p3m_status;
 #define P3M_BOUNDARY_OPEN    0
 #define P3M_BOUNDARY_CATHODE 1
 
+/* Fourier table of the mesh kernel (p3m_opts.influence), built at create.
+ * SAMPLED: erf(a r)/r sampled at the node offsets, no deconvolution.
+ * OPTIMAL: the optimal influence function of Sec. 3.1.2 (eq. Ghfinal) for
+ *   point particles, sum_m U^2(k_m) (R gamma)(k_m) / [sum_m U^2(k_m)]^2 with
+ *   U the B-spline's transform and |m_d| <= 2, which minimises the mean
+ *   square error of the mesh potential; PRINCIPAL: its m = 0 form
+ *   (R gamma)/U^2. Either enters as (G - R gamma)/V added to the sampled
+ *   kernel's table, which changes the kernel near the origin only and keeps
+ *   the open boundary. Lowers the potential error for CIC and TSC and the
+ *   force error for TSC. Free space only (P3M_EINVAL with the cathode). */
+#define P3M_INFLUENCE_SAMPLED   0
+#define P3M_INFLUENCE_OPTIMAL   1
+#define P3M_INFLUENCE_PRINCIPAL 2
+
 #define P3M_CIC 1             /* linear B-spline b1 (2 nodes per axis)          */
 #define P3M_TSC 2             /* quadratic B-spline b2 (3 nodes per axis)       */
 
@@ -117,7 +131,7 @@ typedef struct {
     double q;           /* macro-particle charge, C                        [1.0]  */
     double m;           /* macro-particle mass, kg                         [1.0]  */
     int32_t boundary;   /* P3M_BOUNDARY_OPEN or _CATHODE                   [OPEN] */
-    int32_t reserved2;  /* must be 0                                               */
+    int32_t influence;  /* P3M_INFLUENCE_SAMPLED, _OPTIMAL or _PRINCIPAL [SAMPLED] */
     double cathode_z;   /* plane position for P3M_BOUNDARY_CATHODE, m       [0.0]  */
 } p3m_opts;
 

@@ -340,7 +340,9 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   else p3m_default_opts(&o);
   if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
   if (o.gather != P3M_GATHER_VARIATIONAL && o.gather != P3M_GATHER_MOMENTUM) return P3M_EINVAL;
-  if (o.reserved != 0 || o.reserved2 != 0) return P3M_EINVAL;
+  if (o.reserved != 0) return P3M_EINVAL;
+  if (o.influence < P3M_INFLUENCE_SAMPLED || o.influence > P3M_INFLUENCE_PRINCIPAL) return P3M_EINVAL;
+  if (o.influence != P3M_INFLUENCE_SAMPLED && o.boundary == P3M_BOUNDARY_CATHODE) return P3M_EINVAL;
   if (o.boundary != P3M_BOUNDARY_OPEN && o.boundary != P3M_BOUNDARY_CATHODE) return P3M_EINVAL;
   if (o.boundary == P3M_BOUNDARY_CATHODE && !std::isfinite(o.cathode_z)) return P3M_EINVAL;
   if (o.precision != P3M_FP64 && o.precision != P3M_FP32C) return P3M_EINVAL;
@@ -370,6 +372,7 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   g.gather = o.gather == P3M_GATHER_MOMENTUM ? 1 : 0;
   g.cathode = o.boundary == P3M_BOUNDARY_CATHODE ? 1 : 0;
   g.zc = g.cathode ? o.cathode_z : 0.0;
+  g.influence = o.influence;
   g.ncells = 1;
   for (int d = 0; d < 3; ++d) {
     g.grid[d] = grid[d];

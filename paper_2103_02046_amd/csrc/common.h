@@ -45,6 +45,7 @@ struct Geo {
   int zoom;            // 1 zoom on
   int gather;          // 0 variational, 1 momentum-conserving (mesh E by central differences)
   int cathode;         // 1: grounded plane z = zc (image charges on the mesh)
+  int influence;       // mesh kernel table: 0 sampled, 1 optimal, 2 principal harmonic
   double zc;           // plane position (m)
 };
 

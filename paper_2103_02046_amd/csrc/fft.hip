@@ -450,6 +450,75 @@ __global__ void __launch_bounds__(kFftThreads) k_gimg_z(Geo geo, const double* _
   }
 }
 
+// ---- optimal influence function (Sec. 3.1.2, eq. Ghfinal) ---------------------
+// For point particles with the Gaussian screening in the reference kernel,
+// (R gamma)(k) = 4 pi exp(-k^2 / (4 kappa^2)) / k^2, and the assignment
+// U(k) = prod_d sinc(k_d h_d / 2)^(p+1):
+//   optimal (mode 1): G = sum_m U^2(k_m) (R gamma)(k_m) / [sum_m U^2(k_m)]^2,
+//                     k_m = k - 2 pi m / h, |m_d| <= 2;
+//   principal (mode 2): the m = 0 term, (R gamma)(k) / U^2(k).
+// The table gets (G - (R gamma)(k)) / (h_x h_y h_z) added to the transform of
+// the sampled kernel: the difference is finite at k = 0 and short-ranged, so
+// the mesh kernel becomes the optimum near the origin while its erf(kappa r)/r
+// tail, which the zero-padded open boundary relies on, is kept. Octant
+// entries (the table is even in each k_d); the k = 0 entry is the limit along
+// k_x. Internal units (lengths in r_c).
+__device__ __forceinline__ double sinc_pow(double kh, int p1) {
+  const double x = 0.5 * kh;
+  const double s = x == 0.0 ? 1.0 : sin(x) / x;
+  double r = s;
+  for (int i = 1; i < p1; ++i) r *= s;
+  return r;
+}
+
+__device__ __forceinline__ double rgamma(double kx, double ky, double kz, double kappa) {
+  const double k2 = kx * kx + ky * ky + kz * kz;
+  return 4.0 * M_PI * exp(-k2 / (4.0 * kappa * kappa)) / k2;
+}
+
+__global__ void k_green_influence(Geo geo, int mode, double* __restrict__ ghat, double scale) {
+  const int nx1 = geo.grid[0] + 1, ny1 = geo.grid[1] + 1, nz1 = geo.grid[2] + 1;
+  const long long total = (long long)nx1 * ny1 * nz1;
+  const long long e = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (e >= total) return;
+  const int i[3] = {(int)(e % nx1), (int)((e / nx1) % ny1), (int)(e / ((long long)nx1 * ny1))};
+  double k[3];
+  for (int d = 0; d < 3; ++d) k[d] = M_PI * i[d] / (geo.grid[d] * geo.hu[d]);
+  if (e == 0) k[0] = 1e-3 * M_PI / (geo.grid[0] * geo.hu[0]);
+  const int p1 = geo.order + 1;
+  const double h[3] = {geo.hu[0], geo.hu[1], geo.hu[2]};
+  double G;
+  if (mode == 2) {
+    double u2 = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      const double u = sinc_pow(k[d] * h[d], p1);
+      u2 *= u * u;
+    }
+    G = rgamma(k[0], k[1], k[2], geo.kappa) / u2;
+  } else {
+    constexpr int M = 2;
+    double num = 0.0, den[3] = {0.0, 0.0, 0.0};
+    double u2a[3][2 * M + 1];
+    for (int d = 0; d < 3; ++d)
+      for (int m = -M; m <= M; ++m) {
+        const double u = sinc_pow((k[d] - 2.0 * M_PI * m / h[d]) * h[d], p1);
+        u2a[d][m + M] = u * u;
+        den[d] += u * u;
+      }
+    for (int mz = -M; mz <= M; ++mz)
+      for (int my = -M; my <= M; ++my)
+        for (int mx = -M; mx <= M; ++mx) {
+          const double u2 = u2a[0][mx + M] * u2a[1][my + M] * u2a[2][mz + M];
+          num += u2 * rgamma(k[0] - 2.0 * M_PI * mx / h[0], k[1] - 2.0 * M_PI * my / h[1],
+                             k[2] - 2.0 * M_PI * mz / h[2], geo.kappa);
+        }
+    const double dd = den[0] * den[1] * den[2];
+    G = num / (dd * dd);
+  }
+  const double corr = (G - rgamma(k[0], k[1], k[2], geo.kappa)) / (h[0] * h[1] * h[2]);
+  ghat[e] += corr * scale;
+}
+
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 template <typename T, int L>
@@ -546,6 +615,8 @@ void build_green_table(const Geo& g, double* table, double* scratch, double* con
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(0, g, scratch, table, cosv[0], 1.0);
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(1, g, table, scratch, cosv[1], 1.0);
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(2, g, scratch, table, cosv[2], scale);
+  if (g.influence)
+    k_green_influence<<<blocks_for(total), kThreads, 0, st>>>(g, g.influence, table, scale);
 }
 
 size_t image_table_elems(const Geo& g) {

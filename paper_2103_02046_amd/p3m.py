@@ -38,13 +38,14 @@ class P3MError(RuntimeError):
 MESH_AUTO, MESH_F32, MESH_F64 = 0, 1, 2
 GATHER_VARIATIONAL, GATHER_MOMENTUM = 0, 1
 BOUNDARY_OPEN, BOUNDARY_CATHODE = 0, 1
+INFLUENCE_SAMPLED, INFLUENCE_OPTIMAL, INFLUENCE_PRINCIPAL = 0, 1, 2
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("zoom", ctypes.c_int32),
                 ("gather", ctypes.c_int32), ("mesh_precision", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("ke", ctypes.c_double), ("q", ctypes.c_double),
-                ("m", ctypes.c_double), ("boundary", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("m", ctypes.c_double), ("boundary", ctypes.c_int32), ("influence", ctypes.c_int32),
                 ("cathode_z", ctypes.c_double)]
 
 
@@ -108,7 +109,8 @@ class Context:
     cutoff r_cut (m), Ewald split parameter `split` (1/m)."""
 
     def __init__(self, grid, h, r_cut, split, order=TSC, precision=FP64, zoom=True, ke=8.9875517923e9,
-                 q=1.0, m=1.0, mesh_precision=MESH_AUTO, gather=GATHER_VARIATIONAL, cathode_z=None):
+                 q=1.0, m=1.0, mesh_precision=MESH_AUTO, gather=GATHER_VARIATIONAL, cathode_z=None,
+                 influence=INFLUENCE_SAMPLED):
         L = lib()
         o = Opts()
         L.p3m_default_opts(ctypes.byref(o))
@@ -118,6 +120,7 @@ class Context:
         o.gather = int(gather)
         if cathode_z is not None:
             o.boundary, o.cathode_z = BOUNDARY_CATHODE, float(cathode_z)
+        o.influence = int(influence)
         g = (ctypes.c_int32 * 3)(*[int(v) for v in grid])
         hh = (ctypes.c_double * 3)(*[float(v) for v in h])
         self._ctx = ctypes.c_void_p()

@@ -159,3 +159,56 @@ def test_cathode_step_and_hvp_parity():
     ref = O.hvp(x, v, prm, O.placement(x, prm))
     assert rms_err(out, ref) < 1e-10
     assert c.status_sync() == p3m.OK
+
+
+# ---- optimal influence function (table built at create) --------------------------
+
+def _tsc4k():
+    import dataclasses
+    return dataclasses.replace(W.get("gauss4k"), order=W.TSC)
+
+
+@pytest.mark.parametrize("mode,order", [("optimal", 1), ("optimal", 2), ("principal", 2)])
+def test_influence_parity_fp64(mode, order):
+    import dataclasses
+    wl = dataclasses.replace(W.get("gauss4k"), order=order)
+    x, _ = wl.draw()
+    code = p3m.INFLUENCE_OPTIMAL if mode == "optimal" else p3m.INFLUENCE_PRINCIPAL
+    c = p3m.Context.from_workload(wl, influence=code)
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    prm = O.Params.from_workload(wl, influence=mode)
+    _, parts = O.forces(x, prm, parts=True)
+    assert rms_err(host(fpp), parts["pp"]) < TOL64
+    assert rms_err(host(fpm), parts["pm"]) < TOL64
+
+
+def test_influence_parity_fp32c():
+    wl = W.aniso_tsc(n=1 << 15, grid=32, steps=5)
+    x, _ = wl.draw()
+    c = p3m.Context.from_workload(wl, precision=p3m.FP32C, influence=p3m.INFLUENCE_OPTIMAL)
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    ref, parts = O.forces(x, O.Params.from_workload(wl, influence="optimal"), parts=True)
+    e = rms_err(host(fpp) + host(fpm), ref)
+    print(f"optimal influence fp32c vs oracle: total {e:.2e}")
+    assert e < TOL32
+
+
+def test_influence_lowers_tsc_error_vs_coulomb():
+    """On the GPU, with the 4096-particle Gaussian at TSC: the P3M force against
+    the unsplit O(N^2) Coulomb sum, sampled kernel vs optimal table."""
+    wl = _tsc4k()
+    x, _ = wl.draw()
+    fc = O.coulomb_brute(x, wl.ke_q2)
+    e = {}
+    for name, code in (("sampled", p3m.INFLUENCE_SAMPLED), ("optimal", p3m.INFLUENCE_OPTIMAL)):
+        f = host(p3m.Context.from_workload(wl, influence=code).forces(dev(x)))
+        e[name] = rms_err(f, fc)
+    print(f"TSC 4096 vs Coulomb: sampled {e['sampled']:.3e} optimal {e['optimal']:.3e}")
+    assert e["optimal"] < 0.6 * e["sampled"]
+
+
+def test_influence_refused_with_cathode():
+    wl = W.get("gauss4k")
+    with pytest.raises(p3m.P3MError) as e:
+        p3m.Context.from_workload(wl, influence=p3m.INFLUENCE_OPTIMAL, cathode_z=-1.0)
+    assert e.value.code == p3m.EINVAL
