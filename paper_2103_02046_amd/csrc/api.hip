@@ -177,7 +177,7 @@ p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   HIPCHK(dalloc(&ctx->sb.vals_a, (size_t)n));
   HIPCHK(dalloc(&ctx->sb.keys_b, (size_t)n));
   HIPCHK(dalloc(&ctx->sb.vals_b, (size_t)n));
-  HIPCHK(dalloc(&ctx->sb.counts, (size_t)256 * sort_blocks(n)));
+  HIPCHK(dalloc(&ctx->sb.counts, (size_t)2048 * sort_blocks(n)));
   HIPCHK(dalloc(&ctx->groups, (size_t)pp_group_bound(n, ctx->geo)));
   HIPCHK(dalloc(&ctx->fcache, (size_t)3 * n));
   ctx->cap = n;
@@ -399,7 +399,7 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   hipStream_t st = 0;
   if (dalloc(&ctx->place, 1) != hipSuccess || dalloc(&ctx->status, 1) != hipSuccess ||
       dalloc(&ctx->bbox_part, 6 * 1024) != hipSuccess || dalloc(&ctx->acc, 64) != hipSuccess ||
-      dalloc(&ctx->sb.ghist, 4 * 256) != hipSuccess || dalloc(&ctx->sb.counter, 2) != hipSuccess ||
+      dalloc(&ctx->sb.ghist, 3 * 2048) != hipSuccess || dalloc(&ctx->sb.counter, 2) != hipSuccess ||
       dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess ||
       dalloc(&ctx->group_scratch, (size_t)pp_scratch_ints(g)) != hipSuccess)
     return bail(P3M_ENOMEM);

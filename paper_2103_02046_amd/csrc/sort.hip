@@ -1,5 +1,5 @@
 // Linked cells on the device: PP-cell key per particle, a stable LSD radix
-// sort of (key, index) with 8-bit digits, the start of every cell in the
+// sort of (key, index) with digits of up to 11 bits, the start of every cell in the
 // sorted order, and the reorder of the particles into sorted records.
 //
 // The paper sums the short-range force over particles "close to" each
@@ -37,21 +37,29 @@ __global__ void __launch_bounds__(kThreads) k_keys(int64_t n, const double* __re
   vals[i] = (uint32_t)i;
 }
 
+// Digits of db <= 11 bits (nbins = 2^db <= kMaxBins): keys of at most 22
+// bits, the usual case, take two passes.
+constexpr int kMaxBins = 2048;
+constexpr int kBinsPerThread = kMaxBins / kThreads;
+
 __global__ void __launch_bounds__(kThreads) k_radix_count(int64_t n, const uint32_t* __restrict__ keys,
-                                                          int shift, int* __restrict__ counts,
+                                                          int shift, int nbins, int* __restrict__ counts,
                                                           int* __restrict__ ghist, int nb) {
-  __shared__ int h[256];
-  h[threadIdx.x] = 0;
+  __shared__ int h[kMaxBins];
+  for (int d = threadIdx.x; d < nbins; d += kThreads) h[d] = 0;
   __syncthreads();
+  const uint32_t mask = (uint32_t)nbins - 1u;
   int64_t base = (int64_t)blockIdx.x * kTile;
   for (int k = 0; k < kItems; ++k) {
     int64_t i = base + k * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1);
   }
   __syncthreads();
-  int c = h[threadIdx.x];
-  counts[threadIdx.x * nb + blockIdx.x] = c;
-  if (c) atomicAdd(&ghist[threadIdx.x], c);
+  for (int d = threadIdx.x; d < nbins; d += kThreads) {
+    const int c = h[d];
+    counts[(int64_t)d * nb + blockIdx.x] = c;
+    if (c) atomicAdd(&ghist[d], c);
+  }
 }
 
 // Exclusive scan of 256 values held one per thread; returns the thread's
@@ -73,17 +81,33 @@ __device__ inline int block_exclusive_scan(int v, int* total) {
   return incl - v;
 }
 
+// One block: ghist becomes the exclusive prefix over digits (in place).
+__global__ void __launch_bounds__(kThreads) k_radix_digit_base(int* __restrict__ ghist, int nbins) {
+  const int t = threadIdx.x;
+  const int per = (nbins + kThreads - 1) / kThreads;
+  int v[kBinsPerThread];
+  int sum = 0;
+  for (int k = 0; k < per; ++k) {
+    const int d = t * per + k;
+    v[k] = d < nbins ? ghist[d] : 0;
+    sum += v[k];
+  }
+  int total;
+  int run = block_exclusive_scan(sum, &total);
+  for (int k = 0; k < per; ++k) {
+    const int d = t * per + k;
+    if (d < nbins) ghist[d] = run;
+    run += v[k];
+  }
+}
+
 // One block per digit: offsets[d][b] = (keys with a smaller digit) + (keys of
 // digit d in blocks before b). counts is overwritten with the offsets.
 __global__ void __launch_bounds__(kThreads) k_radix_scan(int* __restrict__ counts,
-                                                         const int* __restrict__ ghist, int nb) {
+                                                         const int* __restrict__ gbase, int nb) {
   const int d = blockIdx.x, t = threadIdx.x;
   int total;
-  int pre = block_exclusive_scan(ghist[t], &total);
-  __shared__ int base_s;
-  if (t == d) base_s = pre;
-  __syncthreads();
-  int carry = base_s;
+  int carry = gbase[d];
   int* row = counts + (int64_t)d * nb;
   for (int b0 = 0; b0 < nb; b0 += kThreads) {
     int v = (b0 + t < nb) ? row[b0 + t] : 0;
@@ -93,35 +117,44 @@ __global__ void __launch_bounds__(kThreads) k_radix_scan(int* __restrict__ count
   }
 }
 
-// Stable scatter of one tile: keys keep their order within a digit.
+// Stable scatter of one tile: keys keep their order within a digit. Per
+// round of 256 keys, each wave ranks its lanes by matching the digit bit by
+// bit (ballots); the first lane of each digit run in a wave records the
+// run's length for the waves after it, adds it to the digit's running count
+// and clears its entry, so the per-wave counts never need a full clear.
 __global__ void __launch_bounds__(kThreads) k_radix_scatter(
     int64_t n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift, int db,
     const int* __restrict__ offsets, int nb) {
-  __shared__ int run[256];
-  __shared__ int base[256];
-  __shared__ int wcnt[kWaves][256];
+  __shared__ int run[kMaxBins];
+  __shared__ int base[kMaxBins];
+  __shared__ int wcnt[kWaves][kMaxBins];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  run[t] = 0;
-  base[t] = offsets[t * nb + blockIdx.x];
+  const int nbins = 1 << db;
+  for (int d = t; d < nbins; d += kThreads) {
+    run[d] = 0;
+    base[d] = offsets[(int64_t)d * nb + blockIdx.x];
+    for (int q = 0; q < kWaves; ++q) wcnt[q][d] = 0;
+  }
+  __syncthreads();
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t mask = (uint32_t)nbins - 1u;
   int64_t tile = (int64_t)blockIdx.x * kTile;
   for (int k = 0; k < kItems; ++k) {
     int64_t i = tile + k * kThreads + t;
     const bool valid = i < n;
     uint32_t key = valid ? kin[i] : 0u;
     uint32_t val = valid ? vin[i] : 0u;
-    const int d = (int)((key >> shift) & 255u);
-    for (int q = 0; q < kWaves; ++q) wcnt[q][t] = 0;
-    __syncthreads();
+    const int d = (int)((key >> shift) & mask);
     unsigned long long peers = __ballot(valid);
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < db; ++bit) {
       const bool b = (d >> bit) & 1;
       unsigned long long m = __ballot(b);
       peers &= b ? m : ~m;
     }
     const int rank = __popcll(peers & lt);
-    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    const int cnt = __popcll(peers);
+    if (valid && rank == 0) wcnt[w][d] = cnt;
     __syncthreads();
     if (valid) {
       int pos = base[d] + run[d] + rank;
@@ -130,9 +163,10 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter(
       vout[pos] = val;
     }
     __syncthreads();
-    int add = 0;
-    for (int q = 0; q < kWaves; ++q) add += wcnt[q][t];
-    run[t] += add;
+    if (valid && rank == 0) {
+      atomicAdd(&run[d], cnt);
+      wcnt[w][d] = 0;
+    }
     __syncthreads();
   }
 }
@@ -242,10 +276,17 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 }  // namespace
 
-int sort_passes(long long ncells) {
+static int key_bits(long long ncells) {
   int bits = 1;
   while ((1ll << bits) < ncells) ++bits;
-  return (bits + 7) / 8;
+  return bits;
+}
+
+int sort_passes(long long ncells) { return (key_bits(ncells) + 10) / 11; }
+
+static int digit_bits(long long ncells) {
+  const int bits = key_bits(ncells), passes = sort_passes(ncells);
+  return (bits + passes - 1) / passes;
 }
 
 int sort_blocks(int64_t n) { return (int)((n + kTile - 1) / kTile); }
@@ -253,15 +294,17 @@ int sort_blocks(int64_t n) { return (int)((n + kTile - 1) / kTile); }
 void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b,
                       uint32_t** keys, uint32_t** perm, hipStream_t st) {
   const int passes = sort_passes(geo.ncells);
+  const int db = digit_bits(geo.ncells), nbins = 1 << db;
   const int nb = sort_blocks(n);
-  k_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_a, b.vals_a, b.ghist, passes * 256,
+  k_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_a, b.vals_a, b.ghist, passes * nbins,
                                              b.counter);
   uint32_t *ka = b.keys_a, *va = b.vals_a, *kb = b.keys_b, *vb = b.vals_b;
   for (int p = 0; p < passes; ++p) {
-    int* gh = b.ghist + p * 256;
-    k_radix_count<<<nb, kThreads, 0, st>>>(n, ka, 8 * p, b.counts, gh, nb);
-    k_radix_scan<<<256, kThreads, 0, st>>>(b.counts, gh, nb);
-    k_radix_scatter<<<nb, kThreads, 0, st>>>(n, ka, va, kb, vb, 8 * p, b.counts, nb);
+    int* gh = b.ghist + p * nbins;
+    k_radix_count<<<nb, kThreads, 0, st>>>(n, ka, db * p, nbins, b.counts, gh, nb);
+    k_radix_digit_base<<<1, kThreads, 0, st>>>(gh, nbins);
+    k_radix_scan<<<nbins, kThreads, 0, st>>>(b.counts, gh, nb);
+    k_radix_scatter<<<nb, kThreads, 0, st>>>(n, ka, va, kb, vb, db * p, db, b.counts, nb);
     uint32_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;
   }
