@@ -61,6 +61,11 @@ struct p3m_ctx {
   C2<double>* tw64[3] = {nullptr, nullptr, nullptr};
   // step
   double* fcache = nullptr;     // [cap][3]
+  // state stepped in cell order (double-buffered), its caller indices, and
+  // the force in that order
+  double *xs[2] = {nullptr, nullptr}, *ps[2] = {nullptr, nullptr}, *qs[2] = {nullptr, nullptr};
+  uint32_t* ids[2] = {nullptr, nullptr};
+  double* fs = nullptr;
   bool force_cached = false;
   const double* cached_x = nullptr;
   int64_t cached_n = -1;
@@ -156,6 +161,33 @@ void engine_free(Engine<R>& E) {
   E.mesh_ready = false;
 }
 
+void free_state(p3m_ctx* ctx) {
+  for (int b = 0; b < 2; ++b) {
+    dfree(ctx->xs[b]);
+    dfree(ctx->ps[b]);
+    dfree(ctx->qs[b]);
+    dfree(ctx->ids[b]);
+  }
+  dfree(ctx->fs);
+}
+
+// Buffers of the cell-ordered step state, at the current capacity.
+p3m_status ensure_state(p3m_ctx* ctx, bool weights) {
+  if (!ctx->fs) {
+    for (int b = 0; b < 2; ++b) {
+      HIPCHK(dalloc(&ctx->xs[b], (size_t)3 * ctx->cap));
+      HIPCHK(dalloc(&ctx->ps[b], (size_t)3 * ctx->cap));
+      HIPCHK(dalloc(&ctx->ids[b], (size_t)ctx->cap));
+    }
+    HIPCHK(dalloc(&ctx->fs, (size_t)3 * ctx->cap));
+  }
+  if (weights && !ctx->qs[0]) {
+    HIPCHK(dalloc(&ctx->qs[0], (size_t)ctx->cap));
+    HIPCHK(dalloc(&ctx->qs[1], (size_t)ctx->cap));
+  }
+  return P3M_OK;
+}
+
 p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   if (n > 0xffffffffll / 2) return fail(ctx, P3M_EINVAL, "n exceeds the 32-bit particle index range");
   if (n <= ctx->cap) return P3M_OK;
@@ -166,6 +198,7 @@ p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   dfree(ctx->sb.counts);
   dfree(ctx->groups);
   dfree(ctx->fcache);
+  free_state(ctx);
   dfree(ctx->v_sorted);
   dfree(ctx->hpp);
   dfree(ctx->hv);
@@ -239,7 +272,8 @@ const C2<double>* image_table(p3m_ctx* ctx, hipStream_t st) {
 // records in R, the mesh (charge, transform, potential) of engine EM in M.
 template <typename R, typename M>
 p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const double* x,
-                    const double* qw, GatherOut out, double* e_pp, double* e_pm, hipStream_t st) {
+                    const double* qw, GatherOut out, double* e_pp, double* e_pm, const Carry& carry,
+                    hipStream_t st) {
   p3m_status s;
   if ((s = engine_mesh_alloc(ctx, EM)) != P3M_OK) return s;
   if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
@@ -251,7 +285,7 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   }
   {
     StageTimer t(ctx, 2, st);
-    launch_reorder<R>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, st);
+    launch_reorder<R>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, carry, st);
   }
   {
     StageTimer t(ctx, 3, st);
@@ -275,12 +309,13 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
 }
 
 p3m_status evaluate_any(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, GatherOut out,
-                        double* e_pp, double* e_pm, hipStream_t st) {
+                        double* e_pp, double* e_pm, hipStream_t st, const Carry& carry = Carry{}) {
   if (ctx->opts.precision == P3M_FP32C) {
-    if (ctx->mesh64) return evaluate<float, double>(ctx, ctx->e32, ctx->e64, n, x, qw, out, e_pp, e_pm, st);
-    return evaluate<float, float>(ctx, ctx->e32, ctx->e32, n, x, qw, out, e_pp, e_pm, st);
+    if (ctx->mesh64)
+      return evaluate<float, double>(ctx, ctx->e32, ctx->e64, n, x, qw, out, e_pp, e_pm, carry, st);
+    return evaluate<float, float>(ctx, ctx->e32, ctx->e32, n, x, qw, out, e_pp, e_pm, carry, st);
   }
-  return evaluate<double, double>(ctx, ctx->e64, ctx->e64, n, x, qw, out, e_pp, e_pm, st);
+  return evaluate<double, double>(ctx, ctx->e64, ctx->e64, n, x, qw, out, e_pp, e_pm, carry, st);
 }
 
 p3m_status check_last(p3m_ctx* ctx) {
@@ -299,7 +334,7 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   if ((s = ensure_adjoint(ctx, n)) != P3M_OK) return s;
   const Geo& g = ctx->geo;
   launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
-  launch_reorder<double>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, st);
+  launch_reorder<double>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, Carry{}, st);
   launch_sort_vector<double>(n, v, ctx->perm, ctx->v_sorted, st);
   launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
@@ -490,23 +525,59 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
       return fail(ctx, P3M_ESTATE, "no cached force for these positions");
     if (place_record || place_replay)
       return fail(ctx, P3M_EINVAL, "placement record/replay needs a fresh start force");
-  } else {
+  }
+  // The state is stepped in the cell order of the latest force evaluation:
+  // each reorder moves x, p, the caller indices and the weights into the new
+  // order, so that the push, the gather's writes and the next sort stream
+  // through memory instead of scattering to caller order every step. One
+  // scatter at the end restores caller order. Placement (min/max) and the
+  // fixed-point deposit do not depend on the order; the PP sums do only
+  // through rounding.
+  if ((s = ensure_state(ctx, qw != nullptr)) != P3M_OK) return s;
+  int cur = 0;
+  bool sorted = false;
+  if (!reuse_force) {
     place(ctx, n, x, place_replay, place_record, st);
-    GatherOut out{ctx->fcache, nullptr, nullptr, nullptr, 0.0};
-    if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
+    Carry c;
+    c.x_out = ctx->xs[0];
+    c.p_in = p;
+    c.p_out = ctx->ps[0];
+    c.id_out = ctx->ids[0];
+    c.qw_out = ctx->qs[0];
+    GatherOut out{ctx->fs, nullptr, nullptr, nullptr, 0.0, true};
+    if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st, c)) != P3M_OK) return s;
+    sorted = true;
   }
   const double inv_m = 1.0 / ctx->opts.m;
   const int nb = bbox_blocks(n);
   for (int k = 0; k < nsteps; ++k) {
     const size_t off = (size_t)P3M_PLACEMENT_DOUBLES * (k + 1);
+    double* xk = sorted ? ctx->xs[cur] : x;
+    double* pk = sorted ? ctx->ps[cur] : p;
+    const double* qk = sorted ? (qw ? ctx->qs[cur] : nullptr) : qw;
     {
       StageTimer t(ctx, 0, st);
-      launch_kick_drift_bbox(n, x, p, ctx->fcache, dt, inv_m, ctx->bbox_part, nb, ctx->status, st);
+      launch_kick_drift_bbox(n, xk, pk, sorted ? ctx->fs : ctx->fcache, dt, inv_m, ctx->bbox_part, nb,
+                             ctx->status, st);
       launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_replay ? place_replay + off : nullptr,
                             ctx->place, place_record ? place_record + off : nullptr, ctx->status, st);
     }
-    GatherOut out{ctx->fcache, nullptr, nullptr, p, 0.5 * dt};
-    if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
+    const int nxt = sorted ? 1 - cur : 0;
+    Carry c;
+    c.x_out = ctx->xs[nxt];
+    c.p_in = pk;
+    c.p_out = ctx->ps[nxt];
+    c.id_in = sorted ? ctx->ids[cur] : nullptr;
+    c.id_out = ctx->ids[nxt];
+    c.qw_out = ctx->qs[nxt];
+    GatherOut out{ctx->fs, nullptr, nullptr, ctx->ps[nxt], 0.5 * dt, true};
+    if ((s = evaluate_any(ctx, n, xk, qk, out, nullptr, nullptr, st, c)) != P3M_OK) return s;
+    cur = nxt;
+    sorted = true;
+  }
+  if (sorted) {
+    StageTimer t(ctx, 2, st);
+    launch_unpermute(n, ctx->xs[cur], ctx->ps[cur], ctx->fs, ctx->ids[cur], x, p, ctx->fcache, st);
   }
   ctx->force_cached = true;
   ctx->cached_x = x;
@@ -697,6 +768,7 @@ void p3m_destroy(p3m_ctx* ctx) {
   dfree(ctx->gimg_t2);
   for (int d = 0; d < 3; ++d) dfree(ctx->tw64[d]);
   dfree(ctx->fcache);
+  free_state(ctx);
   dfree(ctx->v_sorted);
   dfree(ctx->hpp);
   dfree(ctx->hv);

@@ -27,10 +27,23 @@ int sort_blocks(int64_t n);
 // Sorts particles by PP cell; on return *keys/*perm point at the sorted arrays.
 void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b,
                       uint32_t** keys, uint32_t** perm, hipStream_t st);
+// Stepping in cell order: the reorder also moves the particle state into the
+// new order (x_out NULL: nothing is moved).
+struct Carry {
+  double* x_out = nullptr;           // x[perm[j]]
+  const double* p_in = nullptr;      // momenta, in the order of x
+  double* p_out = nullptr;           // p_in[perm[j]]
+  const uint32_t* id_in = nullptr;   // caller index of each particle of x (NULL: the identity)
+  uint32_t* id_out = nullptr;        // id_in[perm[j]]
+  double* qw_out = nullptr;          // qw[perm[j]] (when qw is given)
+};
 template <typename R>
 void launch_reorder(int64_t n, const double* x, const double* qw, const uint32_t* perm,
                     const uint32_t* keys, const Place* pl, const Geo& geo, PPPos<R>* pp,
-                    MeshRec<R>* mesh, int* status, hipStream_t st);
+                    MeshRec<R>* mesh, int* status, const Carry& carry, hipStream_t st);
+// Back to caller order: x[id[j]] = xs[j], p[id[j]] = ps[j], f[id[j]] = fs[j].
+void launch_unpermute(int64_t n, const double* xs, const double* ps, const double* fs, const uint32_t* id,
+                      double* x, double* p, double* f, hipStream_t st);
 template <typename R>
 void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out, hipStream_t st);
 
@@ -64,6 +77,7 @@ struct GatherOut {
   double* f_pm;     // PM part, caller order (may be NULL)
   double* p;        // momenta to kick by half_dt * f (may be NULL)
   double half_dt;
+  bool sorted = false;   // all of the above in cell order instead of caller order
 };
 template <typename R, typename M>
 void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,

@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
         }
     }
     const double fs = pl->fscale;
-    const uint32_t i = perm[j];
+    const uint32_t i = out.sorted ? (uint32_t)j : perm[j];
     double fpm[3], fp[3] = {0, 0, 0}, ft[3];
     const PPRec<R> a = fpp[j];
     fp[0] = (double)a.x;

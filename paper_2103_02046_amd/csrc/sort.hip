@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
     int64_t n, const double* __restrict__ x, const double* __restrict__ qw,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ keys,
     const Place* __restrict__ pl, Geo geo, PPPos<R>* __restrict__ pp, MeshRec<R>* __restrict__ mesh,
-    int* __restrict__ status) {
+    int* __restrict__ status, Carry carry) {
   int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (j >= n) return;
   const Place P = *pl;
@@ -225,6 +225,12 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
                     (int)(key / ((uint32_t)geo.ncell[0] * (uint32_t)geo.ncell[1]))};
   double xi[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
   const double w = qw ? qw[i] : 1.0;
+  if (carry.x_out) {
+    for (int d = 0; d < 3; ++d) carry.x_out[3 * j + d] = xi[d];
+    for (int d = 0; d < 3; ++d) carry.p_out[3 * j + d] = carry.p_in[3 * i + d];
+    carry.id_out[j] = carry.id_in ? carry.id_in[i] : i;
+    if (qw) carry.qw_out[j] = w;
+  }
   // PP record: offset from the own cell corner, formed in float64 before
   // rounding (units of Lu, or fixed point of the cell edge).
   double loc[3];
@@ -259,6 +265,21 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
   m.fz = (R)f[2];
   m.base = ((b[2] * geo.grid[1]) + b[1]) * geo.grid[0] + b[0];
   mesh[j] = m;
+}
+
+__global__ void __launch_bounds__(kThreads) k_unpermute(int64_t n, const double* __restrict__ xs,
+                                                        const double* __restrict__ ps,
+                                                        const double* __restrict__ fs,
+                                                        const uint32_t* __restrict__ id, double* __restrict__ x,
+                                                        double* __restrict__ p, double* __restrict__ f) {
+  int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t i = id[j];
+  for (int d = 0; d < 3; ++d) {
+    x[3 * i + d] = xs[3 * j + d];
+    p[3 * i + d] = ps[3 * j + d];
+    f[3 * i + d] = fs[3 * j + d];
+  }
 }
 
 template <typename R>
@@ -316,8 +337,13 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
 template <typename R>
 void launch_reorder(int64_t n, const double* x, const double* qw, const uint32_t* perm,
                     const uint32_t* keys, const Place* pl, const Geo& geo, PPPos<R>* pp,
-                    MeshRec<R>* mesh, int* status, hipStream_t st) {
-  k_reorder<R><<<blocks_for(n), kThreads, 0, st>>>(n, x, qw, perm, keys, pl, geo, pp, mesh, status);
+                    MeshRec<R>* mesh, int* status, const Carry& carry, hipStream_t st) {
+  k_reorder<R><<<blocks_for(n), kThreads, 0, st>>>(n, x, qw, perm, keys, pl, geo, pp, mesh, status, carry);
+}
+
+void launch_unpermute(int64_t n, const double* xs, const double* ps, const double* fs, const uint32_t* id,
+                      double* x, double* p, double* f, hipStream_t st) {
+  if (n > 0) k_unpermute<<<blocks_for(n), kThreads, 0, st>>>(n, xs, ps, fs, id, x, p, f);
 }
 
 template <typename R>
@@ -327,10 +353,10 @@ void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out
 
 template void launch_reorder<float>(int64_t, const double*, const double*, const uint32_t*,
                                     const uint32_t*, const Place*, const Geo&, PPPos<float>*,
-                                    MeshRec<float>*, int*, hipStream_t);
+                                    MeshRec<float>*, int*, const Carry&, hipStream_t);
 template void launch_reorder<double>(int64_t, const double*, const double*, const uint32_t*,
                                      const uint32_t*, const Place*, const Geo&, PPPos<double>*,
-                                     MeshRec<double>*, int*, hipStream_t);
+                                     MeshRec<double>*, int*, const Carry&, hipStream_t);
 template void launch_sort_vector<float>(int64_t, const double*, const uint32_t*, float*, hipStream_t);
 template void launch_sort_vector<double>(int64_t, const double*, const uint32_t*, double*, hipStream_t);
 
