@@ -30,7 +30,7 @@ import os
 import subprocess
 
 import numpy as np
-from scipy.special import erf
+from scipy.special import erf, erfc, ive
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "p3m_oracle.c")
@@ -125,7 +125,7 @@ class Params:
             raise ValueError(gather)
         self.gather = gather
         self.cathode_z = None if cathode_z is None else float(cathode_z)
-        if influence not in ("sampled", "optimal", "principal"):
+        if influence not in ("sampled", "optimal", "principal", "lattice"):
             raise ValueError(influence)
         self.influence = influence
 
@@ -216,6 +216,88 @@ def green_padded(grid, hp, a):
     return g
 
 
+def lattice_cell_weights(h, a, tol=1e-18):
+    """Charge of the Gaussian screening cloud (density (a/sqrt(pi)) exp(-a^2 x^2)
+    along one axis, the gamma of Sec. 2.2) inside each mesh cell of edge h
+    centred on a node: g(m) = [erf(a (m + 1/2) h) - erf(a (m - 1/2) h)] / 2,
+    m = 0, 1, ... until below tol (g is even in m), the tail through erfc.
+    a = None: no screening, g = delta."""
+    if a is None:
+        return np.array([1.0])
+    out = []
+    m = 0
+    while True:
+        if m == 0:
+            g = erf(0.5 * a * h)
+        else:
+            g = 0.5 * (erfc(a * (m - 0.5) * h) - erfc(a * (m + 0.5) * h))
+        out.append(g)
+        if m > 0 and g < tol:
+            return np.array(out)
+        m += 1
+
+
+def _gauss_legendre_panels(lo, hi, width=1.0, q=16):
+    x, w = np.polynomial.legendre.leggauss(q)
+    n = int(math.ceil((hi - lo) / width))
+    edges = np.linspace(lo, hi, n + 1)
+    u = np.concatenate([0.5 * (b - a) * x + 0.5 * (a + b) for a, b in zip(edges[:-1], edges[1:])])
+    wu = np.concatenate([0.5 * (b - a) * w for a, b in zip(edges[:-1], edges[1:])])
+    return u, wu
+
+
+def lattice_kernel(nmax, hp, a):
+    """Mesh kernel of the lattice form on the octant 0 <= n_d <= nmax_d:
+    K = 4 pi G_L (x) g, where G_L solves the 7-point discrete Poisson equation
+    of the free (unbounded) lattice, -sum_d D_d G_L / h_d^2 = delta / (h_x h_y h_z)
+    (D_d the second difference of Sec. 2.4.3 eq. 1d_ddiff, summed as in eq.
+    3dim_second_order_fin_diff_tensor; the Green's function of Sec. 3 eq.
+    def_G_L), and g = prod_d g_d the Gaussian screening integrated over cells
+    (lattice_cell_weights). K -> 1/r far away, like the sampled erf(a r)/r.
+
+    Evaluated through 1/L = int_0^inf exp(-t L) dt for the operator L: the
+    heat kernel of the second difference along one axis is
+    exp(-2 s) I_k(2 s) = ive(k, 2 s), s = t / h_d^2, so
+      K(n) = (4 pi / V) int_0^inf prod_d F_d(n_d, t) dt,
+      F_d(n, t) = sum_m g_d(m) ive(n - m, 2 t / h_d^2).
+    The t integral is Gauss-Legendre over panels of ln t from 1e-14 h_min^2
+    to T = 5e7 h_min^2 (scipy's ive is accurate there); beyond T the heat
+    kernel is Gaussian to O(h^2 / T) and the rest is erf(r / (2 sqrt(T))) / r.
+    Returned as K[z, y, x]."""
+    hp = np.asarray(hp, dtype=np.float64)
+    V = float(np.prod(hp))
+    T = 5e7 * hp.min() ** 2
+    u, wu = _gauss_legendre_panels(math.log(1e-14 * hp.min() ** 2), math.log(T))
+    t = np.exp(u)
+    F = []
+    for d in range(3):
+        g = lattice_cell_weights(hp[d], a)
+        n = np.arange(int(nmax[d]) + 1)
+        z = 2.0 * t / hp[d] ** 2
+        Fd = np.zeros((len(n), len(t)))
+        for m in range(-(len(g) - 1), len(g)):
+            Fd += g[abs(m)] * ive(np.abs(n - m)[:, None], z[None, :])
+        F.append(Fd)
+    K = np.einsum("t,it,jt,kt->kji", wu * t, F[0], F[1], F[2]) * (4.0 * math.pi / V)
+    ax = [np.arange(int(nmax[d]) + 1) * hp[d] for d in range(3)]
+    rz, ry, rx = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    r = np.sqrt(rx * rx + ry * ry + rz * rz)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        tail = np.where(r > 0, erf(r / (2.0 * math.sqrt(T))) / r, 1.0 / math.sqrt(math.pi * T))
+    return K + tail
+
+
+def green_padded_lattice(grid, hp, a):
+    """The lattice kernel on the doubled mesh, laid out like green_padded."""
+    K = lattice_kernel(grid, hp, a)
+    idx = []
+    for d in range(3):
+        n = int(grid[d])
+        k = np.arange(2 * n)
+        idx.append(np.abs(np.where(k < n, k, k - 2 * n)))
+    return K[np.ix_(idx[2], idx[1], idx[0])]
+
+
 def bspline_ft(kh, order):
     """Fourier transform of the cardinal B-spline of the assignment along one
     axis at k h: sinc(k h / 2)^(p+1), sinc(x) = sin(x)/x (b1 CIC p = 1, b2 TSC p = 2)."""
@@ -282,11 +364,15 @@ def conv_fft(Q, grid, hp, a, influence=None):
     """phi = G (x) Q, aperiodic, by zero padding to 2N and numpy's FFT
     (Sec. 3 eq. phi_L as a finite convolution; Hockney's doubling). With
     influence = (order, mode) the kernel carries the optimal-influence
-    correction (Sec. 3.1.2)."""
+    correction (Sec. 3.1.2), or, for mode "lattice", is the lattice kernel."""
     nz, ny, nx = Q.shape
     Qp = np.zeros((2 * nz, 2 * ny, 2 * nx))
     Qp[:nz, :ny, :nx] = Q
-    Gk = np.fft.rfftn(green_padded(grid, hp, a))
+    if influence is not None and influence[1] == "lattice":
+        Gk = np.fft.rfftn(green_padded_lattice(grid, hp, a))
+        influence = None
+    else:
+        Gk = np.fft.rfftn(green_padded(grid, hp, a))
     if influence is not None:
         Gk = Gk + influence_correction(grid, hp, a, influence[0], influence[1])
     phi = np.fft.irfftn(np.fft.rfftn(Qp) * Gk, s=Qp.shape, axes=(0, 1, 2))
@@ -353,7 +439,7 @@ def mesh_potential(Q, prm, pl, direct=False):
     plane when prm.cathode_z is set."""
     if prm.influence != "sampled":
         if direct or prm.cathode_z is not None:
-            raise ValueError("the optimal influence function is applied in the FFT route, free space")
+            raise ValueError("the alternative mesh kernels are applied in the FFT route, free space")
         return conv_fft(Q, prm.grid, pl["hp"], pl["a"], influence=(prm.order, prm.influence))
     if prm.cathode_z is None:
         return (conv_direct if direct else conv_fft)(Q, prm.grid, pl["hp"], pl["a"])

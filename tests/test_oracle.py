@@ -540,6 +540,145 @@ def test_optimal_influence_force_is_minus_energy_gradient():
         assert fd == pytest.approx(parts["pm"][i, d], rel=1e-5, abs=1e-6 * np.abs(parts["pm"]).max())
 
 
+# ---- lattice Green's function of the discrete Laplacian (Sec. 2.4.3, Sec. 3) -----------
+
+def _watson_sc():
+    """Watson's simple-cubic integral (1/pi^3) int_[0,pi]^3 dx dy dz / (1 - (cos x +
+    cos y + cos z)/3) in the closed form of Glasser and Zucker (1977):
+    sqrt(6)/(32 pi^3) Gamma(1/24) Gamma(5/24) Gamma(7/24) Gamma(11/24)."""
+    from scipy.special import gamma
+    return (math.sqrt(6) / (32 * math.pi ** 3) * gamma(1 / 24) * gamma(5 / 24) * gamma(7 / 24)
+            * gamma(11 / 24))
+
+
+def test_lattice_green_origin_is_watsons_integral():
+    """Unscreened, cubic spacing h: the 7-point Green's function at the origin is
+    (1/h) int d^3theta/(2 pi)^3 / (6 - 2 sum cos) = W / (6 h), so K(0) = 4 pi W / (6 h);
+    its neighbour follows from the lattice equation at the origin, K(e) = K(0) - 4 pi / (6 h)."""
+    W = _watson_sc()
+    assert W == pytest.approx(1.516386059151978, rel=1e-14)
+    for h in (1.0, 0.37):
+        K = O.lattice_kernel((3, 3, 3), (h, h, h), None)
+        assert K[0, 0, 0] == pytest.approx(4 * math.pi * W / (6 * h), rel=1e-12)
+        assert K[0, 0, 1] == pytest.approx(K[0, 0, 0] - 4 * math.pi / (6 * h), rel=1e-12)
+        assert K[1, 0, 0] == pytest.approx(K[0, 0, 1], rel=1e-13)
+        assert K[0, 1, 0] == pytest.approx(K[0, 0, 1], rel=1e-13)
+
+
+def test_lattice_cell_weights_are_the_screening_charge_per_cell():
+    """The Gaussian cloud's charge per cell: positive, decreasing, summing to 1
+    over the whole axis; a -> infinity leaves the unit charge on its node."""
+    for h, a in [(0.5, 1.9), (1.3, 1.9), (0.25, 6.0), (1.0, 0.3)]:
+        g = O.lattice_cell_weights(h, a)
+        assert g[0] + 2 * g[1:].sum() == pytest.approx(1.0, abs=1e-15)
+        assert np.all(g > 0) and np.all(np.diff(g) < 0)
+    g = O.lattice_cell_weights(1.0, 40.0)
+    assert g[0] == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("h,a", [((0.5, 0.7, 1.3), 1.9), ((0.4, 0.4, 0.4), None), ((0.25, 0.25, 0.75), 6.0)])
+def test_lattice_kernel_solves_the_discrete_poisson_equation(h, a):
+    """Minus the 7-point Laplacian with spacings h_d (second differences D_d / h_d^2
+    of Sec. 2.4.3, eq. 1d_ddiff) of K is the screening charge per cell over the
+    cell volume times 4 pi: prod_d g_d(n_d), g_d(m) = [erf(a (m+1/2) h_d) -
+    erf(a (m-1/2) h_d)]/2, or the unit charge at the origin unscreened."""
+    from scipy.special import erf
+    nm = (10, 9, 8)
+    K = O.lattice_kernel(nm, h, a)
+    V = float(np.prod(h))
+
+    def k(i, j, l):
+        return K[abs(l), abs(j), abs(i)]
+
+    def gd(m, hd):
+        if a is None:
+            return 1.0 if m == 0 else 0.0
+        return 0.5 * (erf(a * (m + 0.5) * hd) - erf(a * (m - 0.5) * hd))
+
+    scale = 4 * math.pi / V
+    for n in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 3, 1), (1, 1, 1), (5, 5, 5),
+              (9, 1, 3), (0, 8, 0), (3, 0, 7)]:
+        lap = 0.0
+        for d in range(3):
+            e = [0, 0, 0]
+            e[d] = 1
+            lap -= (k(n[0] + e[0], n[1] + e[1], n[2] + e[2]) + k(n[0] - e[0], n[1] - e[1], n[2] - e[2])
+                    - 2 * k(*n)) / h[d] ** 2
+        rhs = scale * gd(n[0], h[0]) * gd(n[1], h[1]) * gd(n[2], h[2])
+        assert lap == pytest.approx(rhs, abs=1e-11 * scale)
+
+
+def test_lattice_green_far_field_asymptote():
+    """Unscreened cubic lattice: r K(n) = 1 + (h^2 / (8 r^2)) (5 sum_d x_d^4 / r^4 - 3)
+    + O(h^4 / r^4), the leading anisotropic correction of the simple-cubic
+    lattice Green's function to the Coulomb potential."""
+    K = O.lattice_kernel((12, 12, 12), (1.0, 1.0, 1.0), None)
+    for n in [(12, 0, 0), (12, 12, 12), (6, 9, 12), (3, 0, 12), (8, 8, 0), (10, 4, 2)]:
+        r2 = float(sum(v * v for v in n))
+        r = math.sqrt(r2)
+        pred = (5 * sum(v ** 4 for v in n) / r2 ** 2 - 3) / (8 * r2)
+        assert K[n[2], n[1], n[0]] * r - 1 == pytest.approx(pred, abs=2.0 / r2 ** 2)
+
+
+def test_lattice_kernel_tends_to_the_sampled_kernel():
+    """When the screening spans many cells (a h -> 0) the lattice kernel tends
+    to erf(a r)/r at second order in a h."""
+    from scipy.special import erf
+    err = []
+    for ah in (0.4, 0.2, 0.1):
+        K = O.lattice_kernel((12, 12, 12), (1.0, 1.0, 1.0), ah)
+        ax = np.arange(13.0)
+        rz, ry, rx = np.meshgrid(ax, ax, ax, indexing="ij")
+        r = np.sqrt(rx * rx + ry * ry + rz * rz)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ref = np.where(r > 0, erf(ah * r) / r, 2 * ah / math.sqrt(math.pi))
+        err.append(np.abs(K - ref).max() / ref.max())
+    assert err[0] < 3e-3
+    assert 3.5 < err[0] / err[1] < 4.5 and 3.5 < err[1] / err[2] < 4.5
+
+
+def test_lattice_fft_route_equals_direct_sum():
+    """The zero-padded FFT convolution with the lattice kernel equals the plain
+    aperiodic sum over node pairs."""
+    grid, hp, a = (4, 5, 3), (0.3, 0.25, 0.4), 2.0
+    Q = np.random.default_rng(3).standard_normal((3, 5, 4))
+    prm = O.Params(grid, hp, 0.5, a, 2, 1.0, influence="lattice")
+    pl = {"hp": np.array(hp), "a": a, "x0": np.zeros(3)}
+    phi = O.mesh_potential(Q, prm, pl)
+    K = O.lattice_kernel(grid, hp, a)
+    ref = np.zeros_like(Q)
+    for iz, iy, ix in np.ndindex(*Q.shape):
+        for jz, jy, jx in np.ndindex(*Q.shape):
+            ref[iz, iy, ix] += Q[jz, jy, jx] * K[abs(iz - jz), abs(iy - jy), abs(ix - jx)]
+    assert np.abs(phi - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_lattice_force_is_minus_energy_gradient():
+    """The lattice kernel is real and even, so the variational mesh force stays
+    the exact gradient of the mesh energy."""
+    x = _rand_bunch(40, 38, scale=0.5)
+    prm = O.Params((12, 12, 12), (0.4, 0.4, 0.4), 0.8, 3.0 / 0.8, 2, 1.0, influence="lattice")
+    pl = O.placement(x, prm)
+    pl["x0"] = pl["x0"] - 0.013
+    F, parts = O.forces(x, prm, parts=True, pl=pl)
+
+    def upm(xx):
+        Q = O.deposit(xx, prm, pl)
+        return 0.5 * (Q * O.mesh_potential(Q, prm, pl)).sum()
+
+    eps = 1e-7
+    for i, d in [(0, 0), (3, 1), (17, 2), (39, 1)]:
+        u = (x[i, d] - pl["x0"][d]) / pl["hp"][d]
+        knot = u + 0.5 - math.floor(u + 0.5)
+        if min(knot, 1 - knot) < 1e-3:
+            continue
+        xp, xm = x.copy(), x.copy()
+        xp[i, d] += eps
+        xm[i, d] -= eps
+        fd = -(upm(xp) - upm(xm)) / (2 * eps)
+        assert fd == pytest.approx(parts["pm"][i, d], rel=1e-5, abs=1e-6 * np.abs(parts["pm"]).max())
+
+
 # ---- whole force ----------------------------------------------------------------
 
 def test_alpha_zero_large_cutoff_equals_coulomb():
