@@ -40,7 +40,6 @@ __global__ void __launch_bounds__(kThreads) k_keys(int64_t n, const double* __re
 // Digits of db <= 11 bits (nbins = 2^db <= kMaxBins): keys of at most 22
 // bits, the usual case, take two passes.
 constexpr int kMaxBins = 2048;
-constexpr int kBinsPerThread = kMaxBins / kThreads;
 
 __global__ void __launch_bounds__(kThreads) k_radix_count(int64_t n, const uint32_t* __restrict__ keys,
                                                           int shift, int nbins, int* __restrict__ counts,
@@ -49,10 +48,24 @@ __global__ void __launch_bounds__(kThreads) k_radix_count(int64_t n, const uint3
   for (int d = threadIdx.x; d < nbins; d += kThreads) h[d] = 0;
   __syncthreads();
   const uint32_t mask = (uint32_t)nbins - 1u;
+  const int lane = threadIdx.x & 63;
   int64_t base = (int64_t)blockIdx.x * kTile;
+  // Keys stepped in cell order arrive in runs of equal digits: the first lane
+  // of each run within the wave adds the run's length (valid lanes form a
+  // prefix of the wave; equal digits in separate runs simply add separately).
   for (int k = 0; k < kItems; ++k) {
-    int64_t i = base + k * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & mask], 1);
+    const int64_t i = base + k * kThreads + threadIdx.x;
+    const bool valid = i < n;
+    const int d = valid ? (int)((keys[i] >> shift) & mask) : -1;
+    const int prev = __shfl_up(d, 1);
+    const bool head = valid && (lane == 0 || prev != d);
+    const unsigned long long heads = __ballot(head);
+    const int nvalid = __popcll(__ballot(valid));
+    if (head) {
+      const unsigned long long after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+      const int next = after ? (int)__builtin_ctzll(after) : nvalid;
+      atomicAdd(&h[d], next - lane);
+    }
   }
   __syncthreads();
   for (int d = threadIdx.x; d < nbins; d += kThreads) {
@@ -81,33 +94,17 @@ __device__ inline int block_exclusive_scan(int v, int* total) {
   return incl - v;
 }
 
-// One block: ghist becomes the exclusive prefix over digits (in place).
-__global__ void __launch_bounds__(kThreads) k_radix_digit_base(int* __restrict__ ghist, int nbins) {
-  const int t = threadIdx.x;
-  const int per = (nbins + kThreads - 1) / kThreads;
-  int v[kBinsPerThread];
-  int sum = 0;
-  for (int k = 0; k < per; ++k) {
-    const int d = t * per + k;
-    v[k] = d < nbins ? ghist[d] : 0;
-    sum += v[k];
-  }
-  int total;
-  int run = block_exclusive_scan(sum, &total);
-  for (int k = 0; k < per; ++k) {
-    const int d = t * per + k;
-    if (d < nbins) ghist[d] = run;
-    run += v[k];
-  }
-}
-
 // One block per digit: offsets[d][b] = (keys with a smaller digit) + (keys of
-// digit d in blocks before b). counts is overwritten with the offsets.
+// digit d in blocks before b). counts is overwritten with the offsets. The
+// first term is the sum of the digit histogram below d, formed by each block.
 __global__ void __launch_bounds__(kThreads) k_radix_scan(int* __restrict__ counts,
-                                                         const int* __restrict__ gbase, int nb) {
+                                                         const int* __restrict__ ghist, int nb) {
   const int d = blockIdx.x, t = threadIdx.x;
+  int below = 0;
+  for (int q = t; q < d; q += kThreads) below += ghist[q];
   int total;
-  int carry = gbase[d];
+  (void)block_exclusive_scan(below, &total);
+  int carry = total;
   int* row = counts + (int64_t)d * nb;
   for (int b0 = 0; b0 < nb; b0 += kThreads) {
     int v = (b0 + t < nb) ? row[b0 + t] : 0;
@@ -323,7 +320,6 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
   for (int p = 0; p < passes; ++p) {
     int* gh = b.ghist + p * nbins;
     k_radix_count<<<nb, kThreads, 0, st>>>(n, ka, db * p, nbins, b.counts, gh, nb);
-    k_radix_digit_base<<<1, kThreads, 0, st>>>(gh, nbins);
     k_radix_scan<<<nbins, kThreads, 0, st>>>(b.counts, gh, nb);
     k_radix_scatter<<<nb, kThreads, 0, st>>>(n, ka, va, kb, vb, db * p, db, b.counts, nb);
     uint32_t* tk = ka; ka = kb; kb = tk;
