@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--gather", default="variational", choices=["variational", "momentum"],
                     help="mesh force at the particles: variational (default) or momentum-conserving")
-    ap.add_argument("--influence", default="sampled", choices=["sampled", "optimal", "principal"],
+    ap.add_argument("--influence", default="sampled", choices=["sampled", "optimal", "principal", "lattice"],
                     help="Fourier table of the mesh kernel (built at create)")
     ap.add_argument("--cathode", action="store_true",
                     help="grounded plane 1 mm below the bunch (image charges on the mesh)")
@@ -120,7 +120,7 @@ def main():
     gmode = p3m.GATHER_MOMENTUM if args.gather == "momentum" else p3m.GATHER_VARIATIONAL
     zc = float(x0[:, 2].min()) - 1e-3 if args.cathode else None
     infl = {"sampled": p3m.INFLUENCE_SAMPLED, "optimal": p3m.INFLUENCE_OPTIMAL,
-            "principal": p3m.INFLUENCE_PRINCIPAL}[args.influence]
+            "principal": p3m.INFLUENCE_PRINCIPAL, "lattice": p3m.INFLUENCE_LATTICE}[args.influence]
     ctx = p3m.Context.from_workload(wl, precision=prec, gather=gmode, cathode_z=zc, influence=infl)
 
     # accuracy of this precision against the float64 path on the same GPU

@@ -112,6 +112,18 @@ typedef int32_t p3m_status;
 #define P3M_INFLUENCE_SAMPLED   0
 #define P3M_INFLUENCE_OPTIMAL   1
 #define P3M_INFLUENCE_PRINCIPAL 2
+/* LATTICE: the paper's literal discrete field equation. The mesh potential
+ * solves the 7-point discrete Poisson equation of the free lattice: the
+ * second differences D_d of Sec. 2.4.3 (eq. 1d_ddiff), divided by h_d^2 and
+ * summed as in eq. 3dim_second_order_fin_diff_tensor, with the Green's
+ * function of Sec. 3 (eq. def_G_L). The source is the deposited charge
+ * convolved with the Gaussian screening's charge per cell,
+ * [erf(a (m+1/2) h) - erf(a (m-1/2) h)]/2 per axis. The kernel tends to
+ * erf(a r)/r at second order in a h, and to 1/r far away. Built at create
+ * from a one-dimensional integral representation of the lattice Green's
+ * function, to about 1e-13. Free space only. P3M_EINVAL when the screening
+ * cloud spans more than 256 cells. */
+#define P3M_INFLUENCE_LATTICE   3
 
 #define P3M_CIC 1             /* linear B-spline b1 (2 nodes per axis)          */
 #define P3M_TSC 2             /* quadratic B-spline b2 (3 nodes per axis)       */
@@ -131,7 +143,7 @@ typedef struct {
     double q;           /* macro-particle charge, C                        [1.0]  */
     double m;           /* macro-particle mass, kg                         [1.0]  */
     int32_t boundary;   /* P3M_BOUNDARY_OPEN or _CATHODE                   [OPEN] */
-    int32_t influence;  /* P3M_INFLUENCE_SAMPLED, _OPTIMAL or _PRINCIPAL [SAMPLED] */
+    int32_t influence;  /* P3M_INFLUENCE_SAMPLED, _OPTIMAL, _PRINCIPAL or _LATTICE [SAMPLED] */
     double cathode_z;   /* plane position for P3M_BOUNDARY_CATHODE, m       [0.0]  */
 } p3m_opts;
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libp3m.so")
-SOURCES = ["api.hip", "placement.hip", "sort.hip", "pp.hip", "mesh.hip", "fft.hip", "diag.hip"]
+SOURCES = ["api.hip", "placement.hip", "sort.hip", "pp.hip", "mesh.hip", "fft.hip", "lattice.hip", "diag.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -32,6 +32,7 @@ struct Engine {
   R* Q = nullptr;
   R* phi = nullptr;
   C2<R>* spec = nullptr;
+  R* gz = nullptr;              // kernel table in this precision, padded rows (z pass)
   C2<R>* tw[3] = {nullptr, nullptr, nullptr};
   int64_t cap = 0;
   bool mesh_ready = false;
@@ -122,6 +123,9 @@ p3m_status engine_mesh_alloc(p3m_ctx* ctx, Engine<R>& E) {
   HIPCHK(dalloc(&E.Q, mesh_nodes(g)));
   HIPCHK(dalloc(&E.phi, mesh_nodes(g)));
   HIPCHK(dalloc(&E.spec, spectrum_elems(g)));
+  HIPCHK(dalloc(&E.gz, green_pack_elems(g)));
+  launch_green_pack<R>(g, ctx->ghat, E.gz, nullptr);
+  HIPCHK(hipStreamSynchronize(nullptr));
   HIPCHK(hipMemset(E.Q, 0, mesh_nodes(g) * sizeof(R)));
   for (int d = 0; d < 3; ++d) {
     const int L = 2 * g.grid[d];
@@ -156,6 +160,7 @@ void engine_free(Engine<R>& E) {
   dfree(E.Q);
   dfree(E.phi);
   dfree(E.spec);
+  dfree(E.gz);
   for (int d = 0; d < 3; ++d) dfree(E.tw[d]);
   E.cap = 0;
   E.mesh_ready = false;
@@ -298,7 +303,7 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   {
     StageTimer t(ctx, 5, st);
     const C2<M>* tw[3] = {EM.tw[0], EM.tw[1], EM.tw[2]};
-    launch_convolve<M>(g, EM.Q, EM.spec, ctx->ghat, image_table(ctx, st), tw, EM.phi, st);
+    launch_convolve<M>(g, EM.Q, EM.spec, EM.gz, image_table(ctx, st), tw, EM.phi, st);
   }
   {
     StageTimer t(ctx, 6, st);
@@ -340,10 +345,10 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
   launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, st);
   const C2<double>* gimg = image_table(ctx, st);
-  launch_convolve<double>(g, E.Q, E.spec, ctx->ghat, gimg, tw, E.phi, st);
+  launch_convolve<double>(g, E.Q, E.spec, E.gz, gimg, tw, E.phi, st);
   launch_fill(ctx->Rm, mesh_nodes(g) * sizeof(double), st);
   launch_deposit_grad(n, E.pp, E.mesh, ctx->v_sorted, g, ctx->Rm, st);
-  launch_convolve<double>(g, ctx->Rm, E.spec, ctx->ghat, gimg, tw, ctx->psi, st);
+  launch_convolve<double>(g, ctx->Rm, E.spec, E.gz, gimg, tw, ctx->psi, st);
   launch_gather_hvp(n, E.pp, E.mesh, ctx->hpp, ctx->v_sorted, ctx->perm, g, ctx->place, E.phi, ctx->psi,
                     out, st);
   ctx->last_precision = -1;
@@ -376,7 +381,7 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
   if (o.gather != P3M_GATHER_VARIATIONAL && o.gather != P3M_GATHER_MOMENTUM) return P3M_EINVAL;
   if (o.reserved != 0) return P3M_EINVAL;
-  if (o.influence < P3M_INFLUENCE_SAMPLED || o.influence > P3M_INFLUENCE_PRINCIPAL) return P3M_EINVAL;
+  if (o.influence < P3M_INFLUENCE_SAMPLED || o.influence > P3M_INFLUENCE_LATTICE) return P3M_EINVAL;
   if (o.influence != P3M_INFLUENCE_SAMPLED && o.boundary == P3M_BOUNDARY_CATHODE) return P3M_EINVAL;
   if (o.boundary != P3M_BOUNDARY_OPEN && o.boundary != P3M_BOUNDARY_CATHODE) return P3M_EINVAL;
   if (o.boundary == P3M_BOUNDARY_CATHODE && !std::isfinite(o.cathode_z)) return P3M_EINVAL;
@@ -458,10 +463,13 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
       return bail(P3M_ENOMEM);
     }
   }
-  build_green_table(g, ctx->ghat, scratch, cosv, st);
-  hipError_t e = hipStreamSynchronize(st);
+  hipError_t e = build_green_table(g, ctx->ghat, scratch, cosv, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  else (void)hipStreamSynchronize(st);
   for (int d = 0; d < 3; ++d) dfree(cosv[d]);
   dfree(scratch);
+  // the lattice table refuses a screening cloud wider than its cell-weight table
+  if (e == hipErrorInvalidValue) return bail(P3M_EINVAL);
   if (e != hipSuccess) return bail(P3M_EHIP);
   if (g.cathode) {
     const size_t ne = image_table_elems(g);

@@ -30,6 +30,17 @@ struct Place {
 };
 static_assert(sizeof(Place) == 16 * sizeof(double), "Place layout");
 
+// Mesh kernel tables (the values of p3m_opts.influence).
+constexpr int kInfluenceSampled = 0;
+constexpr int kInfluenceOptimal = 1;
+constexpr int kInfluencePrincipal = 2;
+constexpr int kInfluenceLattice = 3;
+
+// Row stride (in k_x) of the half spectrum and of the z pass's copy of the
+// kernel table: N_x + 1 values padded to a multiple of 16, so that the
+// 16-wide rows of the strided y and z passes are whole cache lines.
+__host__ __device__ inline int spec_stride(int nx) { return (nx + 1 + 15) & ~15; }
+
 // Zoom-invariant geometry, passed by value.
 struct Geo {
   int grid[3];         // mesh nodes per axis
@@ -45,7 +56,7 @@ struct Geo {
   int zoom;            // 1 zoom on
   int gather;          // 0 variational, 1 momentum-conserving (mesh E by central differences)
   int cathode;         // 1: grounded plane z = zc (image charges on the mesh)
-  int influence;       // mesh kernel table: 0 sampled, 1 optimal, 2 principal harmonic
+  int influence;       // mesh kernel table: kInfluence*
   double zc;           // plane position (m)
 };
 

@@ -18,7 +18,9 @@
 //   y inverse: keep y < N_y;  x inverse: two half spectra -> two real lines.
 // Each line is transformed in LDS by a Stockham radix-8 (then 4 or 2) FFT;
 // a block holds B lines side by side (point-major), so the strided y and z
-// passes read and write rows of B consecutive k_x values.
+// passes read and write rows of B consecutive k_x values. Spectrum rows are
+// spec_stride(N_x) long (N_x + 1 padded to a multiple of 16), so those rows
+// start on cache-line boundaries; the padding is never read.
 // The inverse is conj(FFT(conj(.))); 1/(L_x L_y L_z) is folded into Ghat.
 #include <cmath>
 #include <vector>
@@ -138,7 +140,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, const T* __r
                                                            C2<T>* __restrict__ S,
                                                            const C2<T>* __restrict__ tw) {
   constexpr int B = Cfg<T, L>::B;
-  constexpr int N = L / 2, K = N + 1;
+  constexpr int N = L / 2, K = N + 1, KS = (K + 15) & ~15;
   __shared__ C2<T> s[L * B];
   const int ny = geo.grid[1];
   const long long rows = (long long)ny * geo.grid[2];
@@ -166,7 +168,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, const T* __r
     if (r & 1) o = C2<T>{(T)0.5 * (z.y + zm.y), (T)-0.5 * (z.x - zm.x)};   // (Z - conj Zm) / 2i
     else o = C2<T>{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};          // (Z + conj Zm) / 2
     const long long z_ = gr / ny, y = gr % ny;
-    S[(z_ * 2 * ny + y) * K + k] = o;
+    S[(z_ * 2 * ny + y) * KS + k] = o;
   }
 }
 
@@ -177,15 +179,15 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restric
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2;
   __shared__ C2<T> s[L * B];
-  const int K = geo.grid[0] + 1;
+  const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
   const int nch = (K + B - 1) / B;
   const int z = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
-  C2<T>* base = S + (long long)z * L * K;
+  C2<T>* base = S + (long long)z * L * KS;
   const int nin = INV ? L : N;
   for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
     const int p = e / B, b = e % B;
     C2<T> v{(T)0, (T)0};
-    if (p < nin && kx0 + b < K) v = base[(long long)p * K + kx0 + b];
+    if (p < nin && kx0 + b < K) v = base[(long long)p * KS + kx0 + b];
     if (INV) v.y = -v.y;
     s[e] = v;
   }
@@ -197,7 +199,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restric
     if (kx0 + b < K) {
       C2<T> v = s[e];
       if (INV) v.y = -v.y;
-      base[(long long)p * K + kx0 + b] = v;
+      base[(long long)p * KS + kx0 + b] = v;
     }
   }
 }
@@ -205,18 +207,18 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restric
 // ---- z pass: forward, times Ghat, inverse, keep z < N_z
 template <typename T, int L, bool IMG>
 __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restrict__ S,
-                                                       const double* __restrict__ ghat,
+                                                       const T* __restrict__ gz,
                                                        const C2<double>* __restrict__ gimg,
                                                        const C2<T>* __restrict__ tw) {
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2;
   __shared__ C2<T> s[L * B];
-  const int K = geo.grid[0] + 1;
+  const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
   const int ly = 2 * geo.grid[1];
   const int nch = (K + B - 1) / B;
   const int ky = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
-  const long long zstride = (long long)ly * K;
-  C2<T>* base = S + (long long)ky * K;
+  const long long zstride = (long long)ly * KS;
+  C2<T>* base = S + (long long)ky * KS;
   for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
     const int p = e / B, b = e % B;
     C2<T> v{(T)0, (T)0};
@@ -226,13 +228,14 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restric
   __syncthreads();
   fft_lines<T, L, B>(s, tw);
   const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
-  const long long gplane = (long long)(geo.grid[1] + 1) * K;
+  const long long gplane = (long long)(geo.grid[1] + 1) * K;    // image table
+  const long long gplane_s = (long long)(geo.grid[1] + 1) * KS;
   if constexpr (!IMG) {
     for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
       const int kz = e / B, b = e % B;
       const int kzp = kz <= N ? kz : L - kz;
-      const int kx = kx0 + b < K ? kx0 + b : K - 1;
-      const T g = (T)ghat[kzp * gplane + (long long)kyp * K + kx];
+      const int kx = kx0 + b < K ? kx0 + b : K - 1;   // a block may span more than a row
+      const T g = gz[kzp * gplane_s + (long long)kyp * KS + kx];
       C2<T> v = s[e];
       s[e] = C2<T>{g * v.x, -(g * v.y)};   // conj(g Z): input of the inverse
     }
@@ -249,7 +252,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restric
         const int kzp = kz <= N ? kz : L - kz;
         const int kzm = kz == 0 ? 0 : L - kz;
         const int kx = kx0 + b < K ? kx0 + b : K - 1;
-        const T g = (T)ghat[kzp * gplane + (long long)kyp * K + kx];
+        const T g = gz[kzp * gplane_s + (long long)kyp * KS + kx];
         const C2<double> gd = gimg[(long long)kz * gplane + (long long)kyp * K + kx];
         const C2<T> gs{(T)gd.x, (T)gd.y};
         const C2<T> v = s[e], vm = s[kzm * B + b];
@@ -282,7 +285,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(Geo geo, const C2<T>*
                                                            T* __restrict__ phi,
                                                            const C2<T>* __restrict__ tw) {
   constexpr int B = Cfg<T, L>::B;
-  constexpr int N = L / 2, K = N + 1;
+  constexpr int N = L / 2, K = N + 1, KS = (K + 15) & ~15;
   __shared__ C2<T> s[L * B];
   const int ny = geo.grid[1];
   const long long rows = (long long)ny * geo.grid[2];
@@ -291,8 +294,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(Geo geo, const C2<T>*
     const int l = e / K, k = e % K;
     const long long ga = row0 + 2 * l, gc = ga + 1;
     C2<T> A{(T)0, (T)0}, C{(T)0, (T)0};
-    if (ga < rows) A = S[((ga / ny) * 2 * ny + ga % ny) * K + k];
-    if (gc < rows) C = S[((gc / ny) * 2 * ny + gc % ny) * K + k];
+    if (ga < rows) A = S[((ga / ny) * 2 * ny + ga % ny) * KS + k];
+    if (gc < rows) C = S[((gc / ny) * 2 * ny + gc % ny) * KS + k];
     // Z_k = A_k + i C_k ; stored conjugated (input of the inverse)
     s[k * B + l] = C2<T>{A.x - C.y, -(A.y + C.x)};
     if (k > 0 && k < N) s[(L - k) * B + l] = C2<T>{A.x + C.y, -(C.x - A.y)};
@@ -543,15 +546,28 @@ void run_y(const Geo& g, C2<T>* S, const C2<T>* tw, hipStream_t st) {
   k_fft_y<T, L, INV><<<blocks, kFftThreads, 0, st>>>(g, S, tw);
 }
 template <typename T, int L>
-void run_z(const Geo& g, C2<T>* S, const double* ghat, const C2<double>* gimg, const C2<T>* tw,
+void run_z(const Geo& g, C2<T>* S, const T* gz, const C2<double>* gimg, const C2<T>* tw,
            hipStream_t st) {
   constexpr int B = Cfg<T, L>::B;
   int K = g.grid[0] + 1;
   unsigned blocks = (unsigned)(2 * g.grid[1] * ((K + B - 1) / B));
   if (gimg)
-    k_fft_z<T, L, true><<<blocks, kFftThreads, 0, st>>>(g, S, ghat, gimg, tw);
+    k_fft_z<T, L, true><<<blocks, kFftThreads, 0, st>>>(g, S, gz, gimg, tw);
   else
-    k_fft_z<T, L, false><<<blocks, kFftThreads, 0, st>>>(g, S, ghat, nullptr, tw);
+    k_fft_z<T, L, false><<<blocks, kFftThreads, 0, st>>>(g, S, gz, nullptr, tw);
+}
+
+// The z pass's copy of the kernel table: float64 octant [N_z+1][N_y+1][N_x+1]
+// -> mesh precision with rows of spec_stride(N_x), zero in the padding.
+template <typename R>
+__global__ void k_green_pack(Geo geo, const double* __restrict__ ghat, R* __restrict__ gz) {
+  const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
+  const long long rows = (long long)(geo.grid[1] + 1) * (geo.grid[2] + 1);
+  const long long e = blockIdx.x * (long long)kThreads + threadIdx.x;
+  if (e >= rows * KS) return;
+  const long long row = e / KS;
+  const int kx = (int)(e % KS);
+  gz[e] = kx < K ? (R)ghat[row * K + kx] : (R)0;
 }
 
 #define P3M_FFT_SWITCH(L_, CALL) \
@@ -575,16 +591,25 @@ bool fft_supported(int nodes) {
 }
 
 size_t spectrum_elems(const Geo& g) {
-  return (size_t)g.grid[2] * 2 * g.grid[1] * (g.grid[0] + 1);
+  return (size_t)g.grid[2] * 2 * g.grid[1] * spec_stride(g.grid[0]);
+}
+
+size_t green_pack_elems(const Geo& g) {
+  return (size_t)(g.grid[2] + 1) * (g.grid[1] + 1) * spec_stride(g.grid[0]);
 }
 
 template <typename R>
-void launch_convolve(const Geo& g, const R* Q, C2<R>* S, const double* ghat, const C2<double>* gimg,
+void launch_green_pack(const Geo& g, const double* ghat, R* gz, hipStream_t st) {
+  k_green_pack<R><<<blocks_for((long long)green_pack_elems(g)), kThreads, 0, st>>>(g, ghat, gz);
+}
+
+template <typename R>
+void launch_convolve(const Geo& g, const R* Q, C2<R>* S, const R* gz, const C2<double>* gimg,
                      const C2<R>* tw[3], R* phi, hipStream_t st) {
   const int Lx = 2 * g.grid[0], Ly = 2 * g.grid[1], Lz = 2 * g.grid[2];
 #define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], st)
 #define YF(L) run_y<R, L, false>(g, S, tw[1], st)
-#define ZZ(L) run_z<R, L>(g, S, ghat, gimg, tw[2], st)
+#define ZZ(L) run_z<R, L>(g, S, gz, gimg, tw[2], st)
 #define YI(L) run_y<R, L, true>(g, S, tw[1], st)
 #define XI(L) run_x_inv<R, L>(g, S, phi, tw[0], st)
   P3M_FFT_SWITCH(Lx, XF)
@@ -607,16 +632,22 @@ void make_twiddles(int L, C2<R>* out) {
   }
 }
 
-void build_green_table(const Geo& g, double* table, double* scratch, double* const cosv[3],
-                       hipStream_t st) {
+hipError_t build_green_table(const Geo& g, double* table, double* scratch, double* const cosv[3],
+                             hipStream_t st) {
   const long long total = (long long)(g.grid[0] + 1) * (g.grid[1] + 1) * (g.grid[2] + 1);
   const double scale = 1.0 / (8.0 * g.grid[0] * g.grid[1] * g.grid[2]);
-  k_green_sample<<<blocks_for(total), kThreads, 0, st>>>(g, scratch);
+  if (g.influence == kInfluenceLattice) {
+    const hipError_t e = build_lattice_kernel(g, scratch, st);
+    if (e != hipSuccess) return e;
+  } else {
+    k_green_sample<<<blocks_for(total), kThreads, 0, st>>>(g, scratch);
+  }
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(0, g, scratch, table, cosv[0], 1.0);
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(1, g, table, scratch, cosv[1], 1.0);
   k_green_dct<<<blocks_for(total), kThreads, 0, st>>>(2, g, scratch, table, cosv[2], scale);
-  if (g.influence)
+  if (g.influence == kInfluenceOptimal || g.influence == kInfluencePrincipal)
     k_green_influence<<<blocks_for(total), kThreads, 0, st>>>(g, g.influence, table, scale);
+  return hipGetLastError();
 }
 
 size_t image_table_elems(const Geo& g) {
@@ -644,10 +675,12 @@ void build_image_table(const Geo& g, const Place* pl, double* t1, double* t2, C2
 #undef GZ
 }
 
-template void launch_convolve<float>(const Geo&, const float*, C2<float>*, const double*, const C2<double>*,
+template void launch_convolve<float>(const Geo&, const float*, C2<float>*, const float*, const C2<double>*,
                                      const C2<float>*[3], float*, hipStream_t);
 template void launch_convolve<double>(const Geo&, const double*, C2<double>*, const double*, const C2<double>*,
                                       const C2<double>*[3], double*, hipStream_t);
+template void launch_green_pack<float>(const Geo&, const double*, float*, hipStream_t);
+template void launch_green_pack<double>(const Geo&, const double*, double*, hipStream_t);
 template void make_twiddles<float>(int, C2<float>*);
 template void make_twiddles<double>(int, C2<double>*);
 

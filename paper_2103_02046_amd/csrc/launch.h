@@ -97,10 +97,14 @@ void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale
 bool fft_supported(int nodes);
 // Spectrum buffer: complex, grid[2] x 2 grid[1] x (grid[0] + 1).
 size_t spectrum_elems(const Geo& geo);
+// Elements of the z pass's padded copy of the kernel table, and its build.
+size_t green_pack_elems(const Geo& geo);
+template <typename R>
+void launch_green_pack(const Geo& geo, const double* ghat, R* gz, hipStream_t st);
 // phi = G (x) Q on the mesh (internal units); with gimg (the image table of a
 // grounded plane) minus the image term.
 template <typename R>
-void launch_convolve(const Geo& geo, const R* Q, C2<R>* spec, const double* ghat, const C2<double>* gimg,
+void launch_convolve(const Geo& geo, const R* Q, C2<R>* spec, const R* gz, const C2<double>* gimg,
                      const C2<R>* tw[3], R* phi, hipStream_t st);
 // Image table of the grounded plane z = geo.zc for the placement *pl:
 // complex, [2 grid[2]][grid[1] + 1][grid[0] + 1]; t1, t2 float64 scratch of
@@ -113,7 +117,9 @@ void make_twiddles(int L, C2<R>* host_out);
 // Fourier transform of the sampled kernel erf(kappa rho)/rho on the doubled
 // mesh, divided by the number of doubled-mesh nodes: (grid+1)^3 float64
 // octant [kz][ky][kx]. scratch holds 2 (grid+1)^3 doubles.
-void build_green_table(const Geo& geo, double* table, double* scratch, double* const cosv[3],
+// Lattice-form kernel on the octant of offsets into out (float64, internal units).
+hipError_t build_lattice_kernel(const Geo& geo, double* out, hipStream_t st);
+hipError_t build_green_table(const Geo& geo, double* table, double* scratch, double* const cosv[3],
                        hipStream_t st);
 
 // ---- reductions (diag.hip) ------------------------------------------------

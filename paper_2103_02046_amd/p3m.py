@@ -38,7 +38,7 @@ class P3MError(RuntimeError):
 MESH_AUTO, MESH_F32, MESH_F64 = 0, 1, 2
 GATHER_VARIATIONAL, GATHER_MOMENTUM = 0, 1
 BOUNDARY_OPEN, BOUNDARY_CATHODE = 0, 1
-INFLUENCE_SAMPLED, INFLUENCE_OPTIMAL, INFLUENCE_PRINCIPAL = 0, 1, 2
+INFLUENCE_SAMPLED, INFLUENCE_OPTIMAL, INFLUENCE_PRINCIPAL, INFLUENCE_LATTICE = 0, 1, 2, 3
 
 
 class Opts(ctypes.Structure):

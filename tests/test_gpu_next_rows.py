@@ -212,3 +212,87 @@ def test_influence_refused_with_cathode():
     with pytest.raises(p3m.P3MError) as e:
         p3m.Context.from_workload(wl, influence=p3m.INFLUENCE_OPTIMAL, cathode_z=-1.0)
     assert e.value.code == p3m.EINVAL
+
+
+# ---- lattice Green's function of the discrete Laplacian (table built at create) ----
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_lattice_parity_fp64(order):
+    """Forces with the lattice-form kernel (built on the GPU from its
+    one-dimensional integral representation) against the oracle (built from
+    modified Bessel functions), element by element."""
+    import dataclasses
+    wl = dataclasses.replace(W.get("gauss4k"), order=order)
+    x, _ = wl.draw()
+    c = p3m.Context.from_workload(wl, influence=p3m.INFLUENCE_LATTICE)
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    _, parts = O.forces(x, O.Params.from_workload(wl, influence="lattice"), parts=True)
+    assert rms_err(host(fpp), parts["pp"]) < TOL64
+    assert rms_err(host(fpm), parts["pm"]) < TOL64
+    assert c.status_sync() == p3m.OK
+
+
+def test_lattice_parity_fp32c():
+    wl = W.aniso_tsc(n=1 << 15, grid=32, steps=5)
+    x, _ = wl.draw()
+    c = p3m.Context.from_workload(wl, precision=p3m.FP32C, influence=p3m.INFLUENCE_LATTICE)
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    ref, _ = O.forces(x, O.Params.from_workload(wl, influence="lattice"), parts=True)
+    e = rms_err(host(fpp) + host(fpm), ref)
+    print(f"lattice kernel fp32c vs oracle: total {e:.2e}")
+    assert e < TOL32
+
+
+def test_lattice_potential_solves_discrete_poisson_full_size():
+    """2^20-particle anisotropic bunch on the 128^3 mesh: at every node one cell
+    inside the mesh, minus the 7-point Laplacian (spacings h'_d) of the exported
+    potential equals 4 pi / (h'_x h'_y h'_z) times the deposited charge convolved
+    with the screening charge per cell, g_d(m) = [erf(a' (m+1/2) h'_d) -
+    erf(a' (m-1/2) h'_d)]/2 (a property of the lattice kernel that holds at any
+    size, checked on the GPU's own mesh)."""
+    from scipy.special import erf
+    wl = W.get("aniso1m")
+    x, _ = wl.draw()
+    c = p3m.Context.from_workload(wl, influence=p3m.INFLUENCE_LATTICE)
+    _, _, pl = c.forces_parts(dev(x))
+    pl = host(pl)
+    Q, phi = host(c.mesh(0)), host(c.mesh(1))
+    assert c.status_sync() == p3m.OK
+    s = pl[3]
+    hp = np.asarray(wl.h, float) * s
+    a = wl.split / s
+    conv = Q.copy()
+    for d in range(3):                       # array axes are z, y, x
+        m = np.arange(-12, 13)
+        g = 0.5 * (erf(a * (m + 0.5) * hp[d]) - erf(a * (m - 0.5) * hp[d]))
+        assert g[0] < 1e-17 and g[-1] < 1e-17
+        axis = 2 - d
+        out = np.zeros_like(conv)
+        n = conv.shape[axis]
+        for k, gk in zip(m, g):
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            src[axis] = slice(max(0, -k), n - max(0, k))
+            dst[axis] = slice(max(0, k), n - max(0, -k))
+            out[tuple(dst)] += gk * conv[tuple(src)]
+        conv = out
+    lap = np.zeros_like(phi[1:-1, 1:-1, 1:-1])
+    core = phi[1:-1, 1:-1, 1:-1]
+    for d in range(3):
+        axis = 2 - d
+        up = [slice(1, -1)] * 3
+        dn = [slice(1, -1)] * 3
+        up[axis] = slice(2, None)
+        dn[axis] = slice(None, -2)
+        lap -= (phi[tuple(up)] + phi[tuple(dn)] - 2 * core) / hp[d] ** 2
+    rhs = 4 * math.pi / np.prod(hp) * conv[1:-1, 1:-1, 1:-1]
+    err = np.abs(lap - rhs).max() / np.abs(rhs).max()
+    print(f"lattice Poisson residual, 2^20 particles on 128^3: {err:.2e}")
+    assert err < 1e-9
+
+
+def test_lattice_refused_with_cathode():
+    wl = W.get("gauss4k")
+    with pytest.raises(p3m.P3MError) as e:
+        p3m.Context.from_workload(wl, influence=p3m.INFLUENCE_LATTICE, cathode_z=-1.0)
+    assert e.value.code == p3m.EINVAL
