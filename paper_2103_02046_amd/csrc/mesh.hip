@@ -75,6 +75,13 @@ __device__ __forceinline__ double wave_maxd(double v) {
   return v;
 }
 
+// Nearest integer (ties to even) of |v| < 2^51: adding 1.5 * 2^52 leaves the
+// rounded value in the low bits of the sum. A product passed in may fuse
+// with the addition into one fma, which rounds the exact product once.
+__device__ __forceinline__ long long fix_round(double v) {
+  return __double_as_longlong(v + 6755399441055744.0) - 0x4338000000000000ll;
+}
+
 // Stencil origin of a sorted particle from its mesh record.
 template <typename R>
 __device__ __forceinline__ void unpack_base(const MeshRec<R>& m, int nx, unsigned nxy, int b[3]) {
@@ -142,7 +149,8 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
   }
   const long long pieces = (long long)((e2 + hz - 1) / hz) * ((e1 + hy - 1) / hy);
   if (pieces <= kMaxPieces) {
-    // unit 2^-s with qmax < 2^(ex+1): 1024 * 2^(ex+1) * 2^s <= 2^61
+    // unit 2^-s with qmax < 2^(ex+1): 1024 * 2^(ex+1) * 2^s <= 2^61, and every
+    // contribution (weights <= 1) is below 2^51 units, as fix_round needs
     const int ex = ilogb(qmax);
     const double toFix = ldexp(1.0, 50 - ex), fromFix = ldexp(1.0, ex - 50);
     for (int pz = 0; pz < e2; pz += hz) {
@@ -163,6 +171,9 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
           const int rx = b[0] - o0, ry = b[1] - o1 - py, rz = b[2] - o2 - pz;
           if (rz >= pe2 || rz + NS <= 0 || ry >= pe1 || ry + NS <= 0) continue;
           const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
+          double wx[NS];
+#pragma unroll
+          for (int a = 0; a < NS; ++a) wx[a] = (double)S.w[0][a];
 #pragma unroll
           for (int c = 0; c < NS; ++c) {
             const int z = rz + c;
@@ -174,8 +185,7 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
               const double wyz = (double)(q * S.w[1][bb] * S.w[2][c]) * toFix;
               unsigned long long* row = reinterpret_cast<unsigned long long*>(tile) + (z * pe1 + y) * e0 + rx;
 #pragma unroll
-              for (int a = 0; a < NS; ++a)
-                atomicAdd(row + a, (unsigned long long)__double2ll_rn(wyz * (double)S.w[0][a]));
+              for (int a = 0; a < NS; ++a) atomicAdd(row + a, (unsigned long long)fix_round(wyz * wx[a]));
             }
           }
         }
