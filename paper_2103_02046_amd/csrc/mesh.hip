@@ -46,7 +46,7 @@ struct Stencil {
   }
 };
 
-// Deposit. A block takes 1024 consecutive sorted particles; sorted by PP
+// Deposit. A block takes 2048 consecutive sorted particles; sorted by PP
 // cell they usually cover a small box of nodes. The block accumulates their
 // weights in an LDS tile of that box in 64-bit fixed point (integer LDS
 // atomics: exact, order-independent, and far cheaper than float LDS
@@ -55,10 +55,11 @@ struct Stencil {
 // is covered in pieces (z-slabs, or y-bands of one plane), each a pass over
 // the block's particles; past kMaxPieces (very sparse bunches) each particle
 // adds its weights to the mesh directly. The fixed-point unit is 2^-s of the
-// block's largest |charge weight| with s chosen so that 1024 contributions
+// block's largest |charge weight| with s chosen so that 2048 contributions
 // cannot overflow: a node value keeps 50 bits below that weight.
 constexpr int kDepItems = 4;
-constexpr int kDepChunk = kThreads * kDepItems;
+constexpr int kDepThreads = 512;   // 8 waves beside a 64 KB tile
+constexpr int kDepChunk = kDepThreads * kDepItems;
 constexpr int kTileNodes = 8192;     // 64 KB of int64
 constexpr int kMaxPieces = 16;
 
@@ -94,13 +95,13 @@ __device__ __forceinline__ void unpack_base(const MeshRec<R>& m, int nx, unsigne
 }
 
 template <typename R, typename M, int ORDER>
-__global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>* __restrict__ pp,
+__global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<R>* __restrict__ pp,
                                                       const MeshRec<R>* __restrict__ mesh, Geo geo,
                                                       M* __restrict__ Q) {
   constexpr int NS = ORDER + 1;
   __shared__ long long tile[kTileNodes];
   __shared__ int red[6];
-  __shared__ double qred[kThreads / 64];
+  __shared__ double qred[kDepThreads / 64];
   const int t = threadIdx.x;
   const int nx = geo.grid[0], ny = geo.grid[1];
   const unsigned nxy = (unsigned)nx * (unsigned)ny;
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
   double qmax = 0.0;
 #pragma unroll
   for (int it = 0; it < kDepItems; ++it) {
-    const int64_t j = j0 + it * kThreads + t;
+    const int64_t j = j0 + it * kDepThreads + t;
     if (j < n) {
       int b[3];
       unpack_base(mesh[j], nx, nxy, b);
@@ -134,7 +135,7 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
   if ((t & 63) == 0) qred[t >> 6] = qmax;
   __syncthreads();
   qmax = qred[0];
-  for (int k = 1; k < kThreads / 64; ++k) qmax = fmax(qmax, qred[k]);
+  for (int k = 1; k < kDepThreads / 64; ++k) qmax = fmax(qmax, qred[k]);
   if (red[0] == INT_MAX || qmax == 0.0) return;   // nothing to add (uniform across the block)
   const int o0 = red[0], o1 = red[1], o2 = red[2];
   const int e0 = red[3] - o0 + NS, e1 = red[4] - o1 + NS, e2 = red[5] - o2 + NS;
@@ -149,8 +150,9 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
   }
   const long long pieces = (long long)((e2 + hz - 1) / hz) * ((e1 + hy - 1) / hy);
   if (pieces <= kMaxPieces) {
-    // unit 2^-s with qmax < 2^(ex+1): 1024 * 2^(ex+1) * 2^s <= 2^61, and every
-    // contribution (weights <= 1) is below 2^51 units, as fix_round needs
+    // unit 2^-s, s = 50 - ex with qmax < 2^(ex+1): every contribution
+    // (weights <= 1) is below 2^51 units, as fix_round needs, and the 2048
+    // particles of a block sum to below 2^62 at any node
     const int ex = ilogb(qmax);
     const double toFix = ldexp(1.0, 50 - ex), fromFix = ldexp(1.0, ex - 50);
     for (int pz = 0; pz < e2; pz += hz) {
@@ -158,11 +160,11 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
       for (int py = 0; py < e1; py += hy) {
         const int pe1 = min(hy, e1 - py);
         const int pvol = e0 * pe1 * pe2;
-        for (int e = t; e < pvol; e += kThreads) tile[e] = 0;
+        for (int e = t; e < pvol; e += kDepThreads) tile[e] = 0;
         __syncthreads();
 #pragma unroll 1
         for (int it = 0; it < kDepItems; ++it) {
-          const int64_t j = j0 + it * kThreads + t;
+          const int64_t j = j0 + it * kDepThreads + t;
           if (j >= n) continue;
           const MeshRec<R> m = mesh[j];
           const R q = pp[j].w;
@@ -190,7 +192,7 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
           }
         }
         __syncthreads();
-        for (int e = t; e < pvol; e += kThreads) {
+        for (int e = t; e < pvol; e += kDepThreads) {
           const long long v = tile[e];
           if (v != 0) {
             const int ex0 = e % e0, ey = (e / e0) % pe1, ez = e / (e0 * pe1);
@@ -204,7 +206,7 @@ __global__ void __launch_bounds__(kThreads) k_deposit(int64_t n, const PPPos<R>*
   } else {
 #pragma unroll 1
     for (int it = 0; it < kDepItems; ++it) {
-      const int64_t j = j0 + it * kThreads + t;
+      const int64_t j = j0 + it * kDepThreads + t;
       if (j >= n) continue;
       const MeshRec<R> m = mesh[j];
       const R q = pp[j].w;
@@ -427,9 +429,9 @@ void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const
   const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
   if (blocks == 0) return;
   if (geo.order == 1)
-    k_deposit<R, M, 1><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, M, 1><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, Q);
   else
-    k_deposit<R, M, 2><<<blocks, kThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, M, 2><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, Q);
 }
 
 template <typename R, typename M>
