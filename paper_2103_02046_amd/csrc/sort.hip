@@ -13,8 +13,8 @@ namespace p3m {
 
 namespace {
 
-constexpr int kItems = 16;                 // keys per thread in a radix tile
-constexpr int kTile = kThreads * kItems;   // 4096 keys per block
+constexpr int kItems = 8;                  // keys per thread in a radix tile
+constexpr int kTile = kThreads * kItems;   // 2048 keys per block
 constexpr int kWaves = kThreads / 64;
 
 __global__ void __launch_bounds__(kThreads) k_keys(int64_t n, const double* __restrict__ x,
