@@ -258,13 +258,17 @@ p3m_status p3m_diagnostics(p3m_ctx *ctx, int64_t n, const double *x, const doubl
 p3m_status p3m_mesh(p3m_ctx *ctx, int32_t which, double *out, void *stream);
 
 /* Stage timing with HIP events recorded on the calling stream around every
- * stage of every evaluation, for at most max_records stage launches:
+ * selected stage of every evaluation, for at most max_records stage launches:
  *   0 push + placement, 1 linked-cell sort and PP work groups, 2 reorder,
  *   3 PP pair forces (the pair kernel alone), 4 deposit, 5 FFT convolution
  *   (five passes), 6 gather.
+ * stage_mask selects the stages (bit s for stage s; 0x7f all, nonzero). An
+ * event pair costs about 2 us of idle GPU between the kernels it separates,
+ * so a throughput measurement times only the stages it needs.
  * p3m_profile_end synchronises `stream`, writes the summed milliseconds and
- * the number of timed launches per stage (arrays of 8, host) and stops. */
-p3m_status p3m_profile_begin(p3m_ctx *ctx, int32_t max_records);
+ * the number of timed launches per stage (arrays of 8, host) and stops.
+ * P3M_EINVAL for max_records < 1 or a mask outside 0x01..0x7f. */
+p3m_status p3m_profile_begin(p3m_ctx *ctx, int32_t max_records, int32_t stage_mask);
 p3m_status p3m_profile_end(p3m_ctx *ctx, double ms[8], int64_t launches[8], void *stream);
 
 /* Synchronise `stream`, return and clear the device status word

@@ -81,6 +81,7 @@ struct p3m_ctx {
   bool mesh64 = false;          // float32 particle path with a float64 mesh
   // stage timing
   bool prof_on = false;
+  int prof_mask = 0;            // stages timed (bit s: stage s)
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_stage;
   int prof_next = 0;
@@ -244,7 +245,7 @@ struct StageTimer {
   hipStream_t st;
   int slot = -1;
   StageTimer(p3m_ctx* ctx, int stage, hipStream_t s) : c(ctx), st(s) {
-    if (c->prof_on && c->prof_next < (int)c->prof_stage.size()) {
+    if (c->prof_on && ((c->prof_mask >> stage) & 1) && c->prof_next < (int)c->prof_stage.size()) {
       slot = c->prof_next++;
       c->prof_stage[slot] = stage;
       (void)hipEventRecord(c->prof_ev[2 * slot], st);
@@ -692,8 +693,9 @@ p3m_status p3m_mesh(p3m_ctx* ctx, int32_t which, double* out, void* stream) {
   return check_last(ctx);
 }
 
-p3m_status p3m_profile_begin(p3m_ctx* ctx, int32_t max_records) {
-  if (!ctx || max_records < 1) return P3M_EINVAL;
+p3m_status p3m_profile_begin(p3m_ctx* ctx, int32_t max_records, int32_t stage_mask) {
+  if (!ctx || max_records < 1 || (stage_mask & ~0x7f) || !stage_mask) return P3M_EINVAL;
+  ctx->prof_mask = stage_mask;
   for (auto& e : ctx->prof_ev) (void)hipEventDestroy(e);
   ctx->prof_ev.assign(2 * (size_t)max_records, nullptr);
   for (auto& e : ctx->prof_ev) HIPCHK(hipEventCreate(&e));

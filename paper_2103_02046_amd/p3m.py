@@ -81,7 +81,7 @@ def lib():
             "p3m_info": (i32, [P, P]),
             "p3m_last_error": (ctypes.c_char_p, [P]),
             "p3m_destroy": (None, [P]),
-            "p3m_profile_begin": (i32, [P, i32]),
+            "p3m_profile_begin": (i32, [P, i32, i32]),
             "p3m_profile_end": (i32, [P, P, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -197,8 +197,10 @@ class Context:
                 "mean": list(d.mean), "rms": list(d.rms), "emit_n": list(d.emit_n), "zoom": d.zoom,
                 "charge": d.charge, "pairs": d.pairs}
 
-    def profile_begin(self, max_records=1 << 16):
-        self._check(lib().p3m_profile_begin(self._ctx, int(max_records)))
+    def profile_begin(self, max_records=1 << 16, stages=None):
+        """Time the named stages (all when None) from now on."""
+        mask = 0x7f if stages is None else sum(1 << STAGES.index(s) for s in stages)
+        self._check(lib().p3m_profile_begin(self._ctx, int(max_records), int(mask)))
 
     def profile_end(self):
         """Per-stage (milliseconds summed, launches) since profile_begin; synchronises."""
