@@ -216,7 +216,7 @@ p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   HIPCHK(dalloc(&ctx->sb.vals_a, (size_t)n));
   HIPCHK(dalloc(&ctx->sb.keys_b, (size_t)n));
   HIPCHK(dalloc(&ctx->sb.vals_b, (size_t)n));
-  HIPCHK(dalloc(&ctx->sb.counts, (size_t)2048 * sort_blocks(n)));
+  HIPCHK(dalloc(&ctx->sb.counts, (size_t)3 * 2048 * sort_blocks(n)));   // per pass (at most 3)
   HIPCHK(dalloc(&ctx->groups, (size_t)pp_group_bound(n, ctx->geo)));
   HIPCHK(dalloc(&ctx->fcache, (size_t)3 * n));
   ctx->cap = n;

@@ -17,7 +17,7 @@ void launch_place_finalize(int nblk, const double* part, const Geo& geo, const d
 // ---- linked cells (sort.hip) ----------------------------------------------
 struct SortBufs {
   uint32_t *keys_a, *vals_a, *keys_b, *vals_b;
-  int* counts;      // [2048][nblocks]
+  int* counts;      // [passes][2048][nblocks]
   int* ghist;       // [passes][2048]
   int* cell_start;  // [ncells + 1]
   int* counter;     // [0] PP groups built, [1] PP groups taken; cleared by the key kernel

@@ -22,12 +22,16 @@ __global__ void __launch_bounds__(kThreads) k_keys(int64_t n, const double* __re
                                                    uint32_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals,
                                                    int* __restrict__ ghist, int nhist,
-                                                   int* __restrict__ counter) {
+                                                   int* __restrict__ counter, int* __restrict__ counts,
+                                                   int64_t ncounts) {
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < nhist; k += kThreads) ghist[k] = 0;
     if (threadIdx.x < 2) counter[threadIdx.x] = 0;
   }
   int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  // the per-block digit counts of every pass start at zero (the count
+  // kernels write only the digits present in their tile)
+  for (int64_t e = i; e < ncounts; e += (int64_t)gridDim.x * kThreads) counts[e] = 0;
   if (i >= n) return;
   const Place P = *pl;
   int c[3];
@@ -70,8 +74,10 @@ __global__ void __launch_bounds__(kThreads) k_radix_count(int64_t n, const uint3
   __syncthreads();
   for (int d = threadIdx.x; d < nbins; d += kThreads) {
     const int c = h[d];
-    counts[(int64_t)d * nb + blockIdx.x] = c;
-    if (c) atomicAdd(&ghist[d], c);
+    if (c) {
+      counts[(int64_t)d * nb + blockIdx.x] = c;
+      atomicAdd(&ghist[d], c);
+    }
   }
 }
 
@@ -128,9 +134,11 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter(
   __shared__ int wcnt[kWaves][kMaxBins];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int nbins = 1 << db;
+  // a digit's offset is fetched when the digit first occurs in the tile (a
+  // tile of sorted keys holds few digits; two waves may fetch the same one)
   for (int d = t; d < nbins; d += kThreads) {
     run[d] = 0;
-    base[d] = offsets[(int64_t)d * nb + blockIdx.x];
+    base[d] = -1;
     for (int q = 0; q < kWaves; ++q) wcnt[q][d] = 0;
   }
   __syncthreads();
@@ -151,7 +159,10 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter(
     }
     const int rank = __popcll(peers & lt);
     const int cnt = __popcll(peers);
-    if (valid && rank == 0) wcnt[w][d] = cnt;
+    if (valid && rank == 0) {
+      wcnt[w][d] = cnt;
+      if (base[d] < 0) base[d] = offsets[(int64_t)d * nb + blockIdx.x];
+    }
     __syncthreads();
     if (valid) {
       int pos = base[d] + run[d] + rank;
@@ -314,14 +325,16 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
   const int passes = sort_passes(geo.ncells);
   const int db = digit_bits(geo.ncells), nbins = 1 << db;
   const int nb = sort_blocks(n);
+  const int64_t per_pass = (int64_t)nbins * nb;
   k_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_a, b.vals_a, b.ghist, passes * nbins,
-                                             b.counter);
+                                             b.counter, b.counts, passes * per_pass);
   uint32_t *ka = b.keys_a, *va = b.vals_a, *kb = b.keys_b, *vb = b.vals_b;
   for (int p = 0; p < passes; ++p) {
     int* gh = b.ghist + p * nbins;
-    k_radix_count<<<nb, kThreads, 0, st>>>(n, ka, db * p, nbins, b.counts, gh, nb);
-    k_radix_scan<<<nbins, kThreads, 0, st>>>(b.counts, gh, nb);
-    k_radix_scatter<<<nb, kThreads, 0, st>>>(n, ka, va, kb, vb, db * p, db, b.counts, nb);
+    int* cnt = b.counts + p * per_pass;
+    k_radix_count<<<nb, kThreads, 0, st>>>(n, ka, db * p, nbins, cnt, gh, nb);
+    k_radix_scan<<<nbins, kThreads, 0, st>>>(cnt, gh, nb);
+    k_radix_scatter<<<nb, kThreads, 0, st>>>(n, ka, va, kb, vb, db * p, db, cnt, nb);
     uint32_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;
   }
