@@ -16,7 +16,7 @@
 //   z: for every (k_y, k_x): N_z inputs -> L_z -> times the real, even Ghat
 //      -> inverse -> keep z < N_z  (the full spectrum never reaches memory);
 //   y inverse: keep y < N_y;  x inverse: two half spectra -> two real lines.
-// Each line is transformed in LDS by a Stockham radix-8 (then 4 or 2) FFT;
+// Each line is transformed in LDS by a Stockham radix-16 (then 8, 4 or 2) FFT;
 // a block holds B lines side by side (point-major), so the strided y and z
 // passes read and write rows of B consecutive k_x values. Spectrum rows are
 // spec_stride(N_x) long (N_x + 1 padded to a multiple of 16), so those rows
@@ -78,9 +78,43 @@ __device__ __forceinline__ void dft8(C2<T>* v) {
   v[7] = csub(e[3], o3);
 }
 
+// 16 points as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2; DFTs over n1, twiddles
+// w16^(n2 k1), DFTs over n2.
+template <typename T>
+__device__ __forceinline__ void dft16(C2<T>* v) {
+  C2<T> y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    C2<T> a[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+    dft4(a);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = a[k1];
+  }
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+  const T h = (T)0.70710678118654752440;
+  // w16^j = (cos(2 pi j / 16), -sin(2 pi j / 16)) for j = n2 k1
+  y[1][1] = cmul(y[1][1], C2<T>{c1, -s1});
+  y[1][2] = cmul(y[1][2], C2<T>{h, -h});
+  y[1][3] = cmul(y[1][3], C2<T>{s1, -c1});
+  y[2][1] = cmul(y[2][1], C2<T>{h, -h});
+  y[2][2] = cmul_mi(y[2][2]);
+  y[2][3] = cmul(y[2][3], C2<T>{-h, -h});
+  y[3][1] = cmul(y[3][1], C2<T>{s1, -c1});
+  y[3][2] = cmul(y[3][2], C2<T>{-h, -h});
+  y[3][3] = cmul(y[3][3], C2<T>{-c1, s1});
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C2<T> b[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    dft4(b);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+  }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dftR(C2<T>* v) {
-  if constexpr (R == 8) dft8(v);
+  if constexpr (R == 16) dft16(v);
+  else if constexpr (R == 8) dft8(v);
   else if constexpr (R == 4) dft4(v);
   else if constexpr (R == 2) dft2(v);
 }
@@ -128,7 +162,7 @@ template <typename T, int L, int B, int Ns = 1>
 __device__ __forceinline__ void fft_lines(C2<T>* s, const C2<T>* __restrict__ tw) {
   if constexpr (Ns < L) {
     constexpr int rem = L / Ns;
-    constexpr int R = rem >= 8 ? 8 : rem;
+    constexpr int R = rem >= 16 ? 16 : rem >= 8 ? 8 : rem;
     fft_stage<T, L, B, Ns, R>(s, tw);
     fft_lines<T, L, B, Ns * R>(s, tw);
   }
