@@ -23,6 +23,7 @@
 // start on cache-line boundaries; the padding is never read.
 // The inverse is conj(FFT(conj(.))); 1/(L_x L_y L_z) is folded into Ghat.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "launch.h"
@@ -313,6 +314,119 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restric
   }
 }
 
+// ---- float lines of 256 points held in registers (y and z passes) ------------
+// 256 = 16 x 16: with n = r + 16 m and k = k1 + 16 k2,
+//   X[k] = sum_r w16^(r k2) w256^(r k1) sum_m x[r + 16 m] w16^(m k1).
+// Thread t of a block takes line b = t % 16 (16 consecutive k_x) and index
+// r = t / 16: it loads x[r + 16 m] straight from memory, transforms over m,
+// twiddles, and passes the values through LDS (one transpose) to the thread
+// that transforms over r, which then holds X[q + 16 k2] for its q = t / 16.
+// That is again the input layout of a transform, so the z pass multiplies
+// by the kernel table and starts the inverse in registers. Two LDS passes per
+// line instead of one per radix stage plus the staging in and out.
+constexpr int kRegL = 256;
+
+__device__ __forceinline__ void reg_first_half(C2<float>* v, int r, const C2<float>* __restrict__ tw,
+                                               C2<float>* s, int b) {
+  dft16(v);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[r * k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) s[(k1 * 16 + r) * 16 + b] = v[k1];
+}
+
+__device__ __forceinline__ void reg_second_half(C2<float>* v, int q, const C2<float>* s, int b) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = s[(q * 16 + r) * 16 + b];
+  dft16(v);
+}
+
+// y pass on 256-point float lines: forward (N inputs, all outputs) or inverse
+// (all inputs, N outputs kept), conjugating around the forward transform.
+template <bool INV>
+__global__ void __launch_bounds__(kFftThreads) k_fft_y_reg(Geo geo, C2<float>* __restrict__ S,
+                                                           const C2<float>* __restrict__ tw) {
+  constexpr int L = kRegL, N = L / 2;
+  __shared__ C2<float> s[L * 16];
+  const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
+  const int nch = (K + 15) / 16;
+  const int z = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * 16;
+  const int b = threadIdx.x & 15, r = threadIdx.x >> 4;
+  const bool valid = kx0 + b < K;
+  C2<float>* base = S + (long long)z * L * KS + kx0 + b;
+  C2<float> v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int p = r + 16 * m;
+    C2<float> x{0.f, 0.f};
+    if (valid && (INV || p < N)) x = base[(long long)p * KS];
+    if (INV) x.y = -x.y;
+    v[m] = x;
+  }
+  reg_first_half(v, r, tw, s, b);
+  __syncthreads();
+  reg_second_half(v, r, s, b);
+  if (valid) {
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) {
+      const int p = r + 16 * k2;
+      if (INV && p >= N) continue;
+      C2<float> x = v[k2];
+      if (INV) x.y = -x.y;
+      base[(long long)p * KS] = x;
+    }
+  }
+}
+
+// z pass on 256-point float lines, free space: forward, times the kernel
+// table, inverse, keep z < N.
+__global__ void __launch_bounds__(kFftThreads) k_fft_z_reg(Geo geo, C2<float>* __restrict__ S,
+                                                           const float* __restrict__ gz,
+                                                           const C2<float>* __restrict__ tw) {
+  constexpr int L = kRegL, N = L / 2;
+  __shared__ C2<float> s[L * 16];
+  const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
+  const int ly = 2 * geo.grid[1];
+  const int nch = (K + 15) / 16;
+  const int ky = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * 16;
+  const int b = threadIdx.x & 15, q = threadIdx.x >> 4;
+  const int kx = kx0 + b;
+  const bool valid = kx < K;
+  const long long zstride = (long long)ly * KS;
+  C2<float>* base = S + (long long)ky * KS + kx;
+  C2<float> v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int p = q + 16 * m;
+    v[m] = (valid && p < N) ? base[p * zstride] : C2<float>{0.f, 0.f};
+  }
+  reg_first_half(v, q, tw, s, b);
+  __syncthreads();
+  reg_second_half(v, q, s, b);
+  // v[k2] = Z(kz), kz = q + 16 k2: conj(Ghat Z) is the inverse's input
+  const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
+  const float* grow = gz + (long long)kyp * KS + (valid ? kx : K - 1);
+  const long long gplane_s = (long long)(geo.grid[1] + 1) * KS;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    const int kz = q + 16 * k2;
+    const int kzp = kz <= N ? kz : L - kz;
+    const float g = grow[kzp * gplane_s];
+    v[k2] = C2<float>{g * v[k2].x, -(g * v[k2].y)};
+  }
+  __syncthreads();   // every thread has read its column of s
+  reg_first_half(v, q, tw, s, b);
+  __syncthreads();
+  reg_second_half(v, q, s, b);
+  if (valid) {
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {   // z = q + 16 k2 < N
+      const C2<float> x = v[k2];
+      base[(long long)(q + 16 * k2) * zstride] = C2<float>{x.x, -x.y};
+    }
+  }
+}
+
 // ---- x pass, inverse: two half spectra -> one complex line -> two real rows
 template <typename T, int L>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(Geo geo, const C2<T>* __restrict__ S,
@@ -576,6 +690,11 @@ template <typename T, int L, bool INV>
 void run_y(const Geo& g, C2<T>* S, const C2<T>* tw, hipStream_t st) {
   constexpr int B = Cfg<T, L>::B;
   int K = g.grid[0] + 1;
+  if constexpr (std::is_same<T, float>::value && L == kRegL) {
+    static_assert(B == 16, "register lines take 16 k_x per block");
+    k_fft_y_reg<INV><<<(unsigned)(g.grid[2] * ((K + 15) / 16)), kFftThreads, 0, st>>>(g, S, tw);
+    return;
+  }
   unsigned blocks = (unsigned)(g.grid[2] * ((K + B - 1) / B));
   k_fft_y<T, L, INV><<<blocks, kFftThreads, 0, st>>>(g, S, tw);
 }
@@ -585,6 +704,12 @@ void run_z(const Geo& g, C2<T>* S, const T* gz, const C2<double>* gimg, const C2
   constexpr int B = Cfg<T, L>::B;
   int K = g.grid[0] + 1;
   unsigned blocks = (unsigned)(2 * g.grid[1] * ((K + B - 1) / B));
+  if constexpr (std::is_same<T, float>::value && L == kRegL) {
+    if (!gimg) {
+      k_fft_z_reg<<<(unsigned)(2 * g.grid[1] * ((K + 15) / 16)), kFftThreads, 0, st>>>(g, S, gz, tw);
+      return;
+    }
+  }
   if (gimg)
     k_fft_z<T, L, true><<<blocks, kFftThreads, 0, st>>>(g, S, gz, gimg, tw);
   else
