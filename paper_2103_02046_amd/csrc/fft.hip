@@ -428,6 +428,106 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z_reg(Geo geo, C2<float>* _
   }
 }
 
+// x passes on 256-point float lines (two real rows of N = 128 per complex
+// line): the same 16 x 16 transform, with the lanes of a line along the
+// row (index fastest) so that loads and stores run along rows. The LDS rows
+// are 17 long so that the transposed reads do not share banks.
+constexpr int kXPad = 17;
+
+__global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd_reg(Geo geo, const float* __restrict__ Q,
+                                                               C2<float>* __restrict__ S,
+                                                               const C2<float>* __restrict__ tw,
+                                                               float* __restrict__ Qz) {
+  constexpr int L = kRegL, N = L / 2, K = N + 1, KS = (K + 15) & ~15;
+  __shared__ C2<float> s[16 * 16 * kXPad];
+  const int ny = geo.grid[1];
+  const long long rows = (long long)ny * geo.grid[2];
+  const int r = threadIdx.x & 15, b = threadIdx.x >> 4;
+  const long long ra = (long long)blockIdx.x * 32 + 2 * b, rc = ra + 1;
+  C2<float> v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    v[m] = C2<float>{0.f, 0.f};
+    if (m < 8) {
+      const int p = r + 16 * m;
+      if (ra < rows) {
+        v[m].x = Q[ra * N + p];
+        if (Qz) Qz[ra * N + p] = 0.f;
+      }
+      if (rc < rows) {
+        v[m].y = Q[rc * N + p];
+        if (Qz) Qz[rc * N + p] = 0.f;
+      }
+    }
+  }
+  dft16(v);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[r * k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) s[(b * 16 + k1) * kXPad + r] = v[k1];
+  __syncthreads();
+  const int q = r;   // this thread now transforms over r for k1 = q
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = s[(b * 16 + q) * kXPad + j];
+  dft16(v);          // v[k2] = Z(q + 16 k2)
+  __syncthreads();
+  C2<float>* zs = s + b * L;   // natural order, for Z(L - k)
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) zs[q + 16 * k2] = v[k2];
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < 9; ++k2) {
+    const int k = q + 16 * k2;
+    if (k > N) continue;
+    const C2<float> z = v[k2], zm = zs[(L - k) & (L - 1)];
+    if (ra < rows)   // (Z + conj Zm) / 2
+      S[((ra / ny) * 2 * ny + ra % ny) * KS + k] = C2<float>{0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)};
+    if (rc < rows)   // (Z - conj Zm) / 2i
+      S[((rc / ny) * 2 * ny + rc % ny) * KS + k] = C2<float>{0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x)};
+  }
+}
+
+__global__ void __launch_bounds__(kFftThreads) k_fft_x_inv_reg(Geo geo, const C2<float>* __restrict__ S,
+                                                               float* __restrict__ phi,
+                                                               const C2<float>* __restrict__ tw) {
+  constexpr int L = kRegL, N = L / 2, K = N + 1, KS = (K + 15) & ~15;
+  __shared__ C2<float> s[16 * 16 * kXPad];
+  const int ny = geo.grid[1];
+  const long long rows = (long long)ny * geo.grid[2];
+  const int r = threadIdx.x & 15, b = threadIdx.x >> 4;
+  const long long ra = (long long)blockIdx.x * 32 + 2 * b, rc = ra + 1;
+  const C2<float>* A = S + ((ra / ny) * 2 * ny + ra % ny) * KS;
+  const C2<float>* C = S + ((rc / ny) * 2 * ny + rc % ny) * KS;
+  // conj(Z_n), Z = A + i C the packed line: Z_n from (A_n, C_n) for n <= N,
+  // from conj(A_{L-n}) + i conj(C_{L-n}) above
+  C2<float> v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int n = r + 16 * m;
+    const int k = n <= N ? n : L - n;
+    C2<float> a{0.f, 0.f}, c{0.f, 0.f};
+    if (ra < rows) a = A[k];
+    if (rc < rows) c = C[k];
+    v[m] = n <= N ? C2<float>{a.x - c.y, -(a.y + c.x)} : C2<float>{a.x + c.y, a.y - c.x};
+  }
+  dft16(v);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[r * k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) s[(b * 16 + k1) * kXPad + r] = v[k1];
+  __syncthreads();
+  const int q = r;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = s[(b * 16 + q) * kXPad + j];
+  dft16(v);          // v[k2] = conj of the inverse at n = q + 16 k2
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) {   // n < N
+    const int n = q + 16 * k2;
+    if (ra < rows) phi[ra * N + n] = v[k2].x;
+    if (rc < rows) phi[rc * N + n] = -v[k2].y;
+  }
+}
+
 // ---- x pass, inverse: two half spectra -> one complex line -> two real rows
 template <typename T, int L>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(Geo geo, const C2<T>* __restrict__ S,
@@ -677,6 +777,10 @@ template <typename T, int L>
 void run_x_fwd(const Geo& g, const T* Q, C2<T>* S, const C2<T>* tw, T* Qz, hipStream_t st) {
   constexpr int B = Cfg<T, L>::B;
   long long rows = (long long)g.grid[1] * g.grid[2];
+  if constexpr (std::is_same<T, float>::value && L == kRegL) {
+    k_fft_x_fwd_reg<<<(unsigned)((rows + 31) / 32), kFftThreads, 0, st>>>(g, Q, S, tw, Qz);
+    return;
+  }
   unsigned blocks = (unsigned)((rows + 2 * B - 1) / (2 * B));
   k_fft_x_fwd<T, L><<<blocks, kFftThreads, 0, st>>>(g, Q, S, tw, Qz);
 }
@@ -684,6 +788,10 @@ template <typename T, int L>
 void run_x_inv(const Geo& g, const C2<T>* S, T* phi, const C2<T>* tw, hipStream_t st) {
   constexpr int B = Cfg<T, L>::B;
   long long rows = (long long)g.grid[1] * g.grid[2];
+  if constexpr (std::is_same<T, float>::value && L == kRegL) {
+    k_fft_x_inv_reg<<<(unsigned)((rows + 31) / 32), kFftThreads, 0, st>>>(g, S, phi, tw);
+    return;
+  }
   unsigned blocks = (unsigned)((rows + 2 * B - 1) / (2 * B));
   k_fft_x_inv<T, L><<<blocks, kFftThreads, 0, st>>>(g, S, phi, tw);
 }
