@@ -96,7 +96,6 @@ struct Acc3<double> {
 // contiguous in the sorted order). Groups are listed in cell order (count
 // per cell, prefix sum, emit), so consecutive groups are spatial neighbours.
 constexpr int kGroupMax = 16;
-constexpr int kScanItems = 256;   // block totals per thread in the middle scan
 
 __global__ void __launch_bounds__(kThreads) k_pp_groups_count(const int* __restrict__ cs, long long ncells,
                                                               int* __restrict__ celloff, int* __restrict__ btot) {
@@ -116,40 +115,27 @@ __global__ void __launch_bounds__(kThreads) k_pp_groups_count(const int* __restr
   if (t == kThreads - 1) btot[blockIdx.x] = s[t];
 }
 
-// One block: exclusive scan of the block totals in place; counter[0] = total.
-__global__ void __launch_bounds__(kThreads) k_pp_groups_scan(int* __restrict__ btot, int nblk,
-                                                             int* __restrict__ counter) {
-  const int t = threadIdx.x;
-  const int per = (nblk + kThreads - 1) / kThreads;
-  const int b0 = t * per, b1 = min(nblk, b0 + per);
-  int sum = 0;
-  for (int b = b0; b < b1; ++b) sum += btot[b];
-  __shared__ int s[kThreads];
-  s[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
-    const int add = t >= off ? s[t - off] : 0;
-    __syncthreads();
-    s[t] += add;
-    __syncthreads();
-  }
-  int run = s[t] - sum;
-  for (int b = b0; b < b1; ++b) {
-    const int v = btot[b];
-    btot[b] = run;
-    run += v;
-  }
-  if (t == kThreads - 1) counter[0] = s[t];
-}
 
+// Each block sums the group totals of the blocks before it (a few thousand
+// cached ints) instead of a separate scan; the last block stores the total.
 __global__ void __launch_bounds__(kThreads) k_pp_groups_emit(const int* __restrict__ cs, long long ncells,
                                                              const int* __restrict__ celloff,
-                                                             const int* __restrict__ boff,
-                                                             int2* __restrict__ desc) {
-  const long long c = blockIdx.x * (long long)kThreads + threadIdx.x;
+                                                             const int* __restrict__ btot,
+                                                             int2* __restrict__ desc, int* __restrict__ counter) {
+  __shared__ int red[kThreads / 64];
+  const int t = threadIdx.x;
+  int before = 0;
+  for (int q = t; q < (int)blockIdx.x; q += kThreads) before += btot[q];
+  for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off);
+  if ((t & 63) == 0) red[t >> 6] = before;
+  __syncthreads();
+  int boff = 0;
+  for (int w = 0; w < kThreads / 64; ++w) boff += red[w];
+  if (blockIdx.x == gridDim.x - 1 && t == 0) counter[0] = boff + btot[blockIdx.x];
+  const long long c = blockIdx.x * (long long)kThreads + t;
   if (c >= ncells) return;
   const int b = cs[c], cnt = cs[c + 1] - b;
-  int g = boff[blockIdx.x] + celloff[c];
+  int g = boff + celloff[c];
   for (int k = 0; k < cnt; k += kGroupMax) desc[g++] = make_int2(b + k, min(kGroupMax, cnt - k));
 }
 
@@ -526,8 +512,7 @@ void launch_pp_groups(const int* cell_start, const Geo& geo, int2* desc, int* co
   int* celloff = scratch;
   int* btot = scratch + nc;
   k_pp_groups_count<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot);
-  k_pp_groups_scan<<<1, kThreads, 0, st>>>(btot, cb, counter);
-  k_pp_groups_emit<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot, desc);
+  k_pp_groups_emit<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot, desc, counter);
 }
 
 template <typename R>

@@ -106,6 +106,7 @@ __device__ inline int block_exclusive_scan(int v, int* total) {
 __global__ void __launch_bounds__(kThreads) k_radix_scan(int* __restrict__ counts,
                                                          const int* __restrict__ ghist, int nb) {
   const int d = blockIdx.x, t = threadIdx.x;
+  if (ghist[d] == 0) return;   // no key has this digit: its offsets are never read
   int below = 0;
   for (int q = t; q < d; q += kThreads) below += ghist[q];
   int total;
