@@ -29,10 +29,7 @@ struct Engine {
   MeshRec<R>* mesh = nullptr;
   PPRec<R>* fpp = nullptr;
   // mesh
-  R* Q = nullptr;               // charge of the latest evaluation (one of Qb)
-  R* Qb[2] = {nullptr, nullptr}; // charge buffers: the next evaluation deposits into Qb[qnext],
-  int qnext = 0;                 // which the x pass of the previous one zeroed
-  bool qzero[2] = {true, true};
+  R* Q = nullptr;
   R* phi = nullptr;
   C2<R>* spec = nullptr;
   R* gz = nullptr;              // kernel table in this precision, padded rows (z pass)
@@ -124,18 +121,13 @@ template <typename R>
 p3m_status engine_mesh_alloc(p3m_ctx* ctx, Engine<R>& E) {
   if (E.mesh_ready) return P3M_OK;
   const Geo& g = ctx->geo;
-  HIPCHK(dalloc(&E.Qb[0], mesh_nodes(g)));
-  HIPCHK(dalloc(&E.Qb[1], mesh_nodes(g)));
-  E.Q = E.Qb[1];   // always Qb[1 - qnext]: paths that deposit into Q never touch the next one
+  HIPCHK(dalloc(&E.Q, mesh_nodes(g)));
   HIPCHK(dalloc(&E.phi, mesh_nodes(g)));
   HIPCHK(dalloc(&E.spec, spectrum_elems(g)));
   HIPCHK(dalloc(&E.gz, green_pack_elems(g)));
   launch_green_pack<R>(g, ctx->ghat, E.gz, nullptr);
   HIPCHK(hipStreamSynchronize(nullptr));
-  HIPCHK(hipMemset(E.Qb[0], 0, mesh_nodes(g) * sizeof(R)));
-  HIPCHK(hipMemset(E.Qb[1], 0, mesh_nodes(g) * sizeof(R)));
-  E.qnext = 0;
-  E.qzero[0] = E.qzero[1] = true;
+  HIPCHK(hipMemset(E.Q, 0, mesh_nodes(g) * sizeof(R)));
   for (int d = 0; d < 3; ++d) {
     const int L = 2 * g.grid[d];
     std::vector<C2<R>> h(L);
@@ -166,9 +158,7 @@ void engine_free(Engine<R>& E) {
   dfree(E.pp);
   dfree(E.mesh);
   dfree(E.fpp);
-  dfree(E.Qb[0]);
-  dfree(E.Qb[1]);
-  E.Q = nullptr;
+  dfree(E.Q);
   dfree(E.phi);
   dfree(E.spec);
   dfree(E.gz);
@@ -309,19 +299,12 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   }
   {
     StageTimer t(ctx, 4, st);
-    M* Qd = EM.Qb[EM.qnext];
-    launch_deposit<R, M>(n, E.pp, E.mesh, g, Qd, !EM.qzero[EM.qnext], st);
-    EM.qzero[EM.qnext] = false;
-    EM.Q = Qd;
+    launch_deposit<R, M>(n, E.pp, E.mesh, g, EM.Q, st);
   }
   {
     StageTimer t(ctx, 5, st);
     const C2<M>* tw[3] = {EM.tw[0], EM.tw[1], EM.tw[2]};
-    // the x pass also zeroes the other buffer for the next evaluation
-    M* Qo = EM.Qb[1 - EM.qnext];
-    launch_convolve<M>(g, EM.Q, EM.spec, EM.gz, image_table(ctx, st), tw, EM.phi, Qo, st);
-    EM.qzero[1 - EM.qnext] = true;
-    EM.qnext = 1 - EM.qnext;
+    launch_convolve<M>(g, EM.Q, EM.spec, EM.gz, image_table(ctx, st), tw, EM.phi, st);
   }
   {
     StageTimer t(ctx, 6, st);
@@ -361,13 +344,12 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   launch_sort_vector<double>(n, v, ctx->perm, ctx->v_sorted, st);
   launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
-  launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, true, st);
-  E.qzero[1 - E.qnext] = false;
+  launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, st);
   const C2<double>* gimg = image_table(ctx, st);
-  launch_convolve<double>(g, E.Q, E.spec, E.gz, gimg, tw, E.phi, nullptr, st);
+  launch_convolve<double>(g, E.Q, E.spec, E.gz, gimg, tw, E.phi, st);
   launch_fill(ctx->Rm, mesh_nodes(g) * sizeof(double), st);
   launch_deposit_grad(n, E.pp, E.mesh, ctx->v_sorted, g, ctx->Rm, st);
-  launch_convolve<double>(g, ctx->Rm, E.spec, E.gz, gimg, tw, ctx->psi, nullptr, st);
+  launch_convolve<double>(g, ctx->Rm, E.spec, E.gz, gimg, tw, ctx->psi, st);
   launch_gather_hvp(n, E.pp, E.mesh, ctx->hpp, ctx->v_sorted, ctx->perm, g, ctx->place, E.phi, ctx->psi,
                     out, st);
   ctx->last_precision = -1;

@@ -173,7 +173,7 @@ __device__ __forceinline__ void fft_lines(C2<T>* s, const C2<T>* __restrict__ tw
 template <typename T, int L>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, const T* __restrict__ Q,
                                                            C2<T>* __restrict__ S,
-                                                           const C2<T>* __restrict__ tw, T* __restrict__ Qz) {
+                                                           const C2<T>* __restrict__ tw) {
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2, K = N + 1, KS = (K + 15) & ~15;
   __shared__ C2<T> s[L * B];
@@ -187,7 +187,6 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, const T* __r
     const long long gr = row0 + r;
     if (gr < rows) {
       T v = Q[gr * N + p];
-      if (Qz) Qz[gr * N + p] = (T)0;   // the other charge buffer, for the next deposit
       if (r & 1) s[p * B + (r >> 1)].y = v;
       else s[p * B + (r >> 1)].x = v;
     }
@@ -436,8 +435,7 @@ constexpr int kXPad = 17;
 
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd_reg(Geo geo, const float* __restrict__ Q,
                                                                C2<float>* __restrict__ S,
-                                                               const C2<float>* __restrict__ tw,
-                                                               float* __restrict__ Qz) {
+                                                               const C2<float>* __restrict__ tw) {
   constexpr int L = kRegL, N = L / 2, K = N + 1, KS = (K + 15) & ~15;
   __shared__ C2<float> s[16 * 16 * kXPad];
   const int ny = geo.grid[1];
@@ -450,14 +448,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd_reg(Geo geo, const fl
     v[m] = C2<float>{0.f, 0.f};
     if (m < 8) {
       const int p = r + 16 * m;
-      if (ra < rows) {
-        v[m].x = Q[ra * N + p];
-        if (Qz) Qz[ra * N + p] = 0.f;
-      }
-      if (rc < rows) {
-        v[m].y = Q[rc * N + p];
-        if (Qz) Qz[rc * N + p] = 0.f;
-      }
+      if (ra < rows) v[m].x = Q[ra * N + p];
+      if (rc < rows) v[m].y = Q[rc * N + p];
     }
   }
   dft16(v);
@@ -774,15 +766,15 @@ __global__ void k_green_influence(Geo geo, int mode, double* __restrict__ ghat, 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 template <typename T, int L>
-void run_x_fwd(const Geo& g, const T* Q, C2<T>* S, const C2<T>* tw, T* Qz, hipStream_t st) {
+void run_x_fwd(const Geo& g, const T* Q, C2<T>* S, const C2<T>* tw, hipStream_t st) {
   constexpr int B = Cfg<T, L>::B;
   long long rows = (long long)g.grid[1] * g.grid[2];
   if constexpr (std::is_same<T, float>::value && L == kRegL) {
-    k_fft_x_fwd_reg<<<(unsigned)((rows + 31) / 32), kFftThreads, 0, st>>>(g, Q, S, tw, Qz);
+    k_fft_x_fwd_reg<<<(unsigned)((rows + 31) / 32), kFftThreads, 0, st>>>(g, Q, S, tw);
     return;
   }
   unsigned blocks = (unsigned)((rows + 2 * B - 1) / (2 * B));
-  k_fft_x_fwd<T, L><<<blocks, kFftThreads, 0, st>>>(g, Q, S, tw, Qz);
+  k_fft_x_fwd<T, L><<<blocks, kFftThreads, 0, st>>>(g, Q, S, tw);
 }
 template <typename T, int L>
 void run_x_inv(const Geo& g, const C2<T>* S, T* phi, const C2<T>* tw, hipStream_t st) {
@@ -873,9 +865,9 @@ void launch_green_pack(const Geo& g, const double* ghat, R* gz, hipStream_t st) 
 
 template <typename R>
 void launch_convolve(const Geo& g, const R* Q, C2<R>* S, const R* gz, const C2<double>* gimg,
-                     const C2<R>* tw[3], R* phi, R* qzero, hipStream_t st) {
+                     const C2<R>* tw[3], R* phi, hipStream_t st) {
   const int Lx = 2 * g.grid[0], Ly = 2 * g.grid[1], Lz = 2 * g.grid[2];
-#define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], qzero, st)
+#define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], st)
 #define YF(L) run_y<R, L, false>(g, S, tw[1], st)
 #define ZZ(L) run_z<R, L>(g, S, gz, gimg, tw[2], st)
 #define YI(L) run_y<R, L, true>(g, S, tw[1], st)
@@ -944,9 +936,9 @@ void build_image_table(const Geo& g, const Place* pl, double* t1, double* t2, C2
 }
 
 template void launch_convolve<float>(const Geo&, const float*, C2<float>*, const float*, const C2<double>*,
-                                     const C2<float>*[3], float*, float*, hipStream_t);
+                                     const C2<float>*[3], float*, hipStream_t);
 template void launch_convolve<double>(const Geo&, const double*, C2<double>*, const double*, const C2<double>*,
-                                      const C2<double>*[3], double*, double*, hipStream_t);
+                                      const C2<double>*[3], double*, hipStream_t);
 template void launch_green_pack<float>(const Geo&, const double*, float*, hipStream_t);
 template void launch_green_pack<double>(const Geo&, const double*, double*, hipStream_t);
 template void make_twiddles<float>(int, C2<float>*);

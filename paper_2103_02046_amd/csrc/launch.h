@@ -68,8 +68,7 @@ void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
 // Deposit into a mesh of type M (float or double) from records of type R in
 // PP-cell order; clears Q first.
 template <typename R, typename M>
-// clear: zero Q first (false when Q is known to be zero already)
-void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q, bool clear,
+void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st);
 // Gather modes: write the total force, the two parts, or (step) total + half kick.
 struct GatherOut {
@@ -105,9 +104,8 @@ void launch_green_pack(const Geo& geo, const double* ghat, R* gz, hipStream_t st
 // phi = G (x) Q on the mesh (internal units); with gimg (the image table of a
 // grounded plane) minus the image term.
 template <typename R>
-// qzero (may be NULL): a mesh-sized buffer the x pass sets to zero
 void launch_convolve(const Geo& geo, const R* Q, C2<R>* spec, const R* gz, const C2<double>* gimg,
-                     const C2<R>* tw[3], R* phi, R* qzero, hipStream_t st);
+                     const C2<R>* tw[3], R* phi, hipStream_t st);
 // Image table of the grounded plane z = geo.zc for the placement *pl:
 // complex, [2 grid[2]][grid[1] + 1][grid[0] + 1]; t1, t2 float64 scratch of
 // image_table_elems each; tw float64 twiddles of the three doubled lengths.

@@ -423,9 +423,9 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kThreads - 1) /
 }  // namespace
 
 template <typename R, typename M>
-void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q, bool clear,
+void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const Geo& geo, M* Q,
                     hipStream_t st) {
-  if (clear) launch_fill(Q, (size_t)geo.grid[0] * geo.grid[1] * geo.grid[2] * sizeof(M), st);
+  launch_fill(Q, (size_t)geo.grid[0] * geo.grid[1] * geo.grid[2] * sizeof(M), st);
   const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
   if (blocks == 0) return;
   if (geo.order == 1)
@@ -478,7 +478,7 @@ void launch_mesh_export(const Geo& geo, const R* src, const Place* pl, int scale
 }
 
 #define P3M_MESH_INST(R, M)                                                                        \
-  template void launch_deposit<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const Geo&, M*, bool,  \
+  template void launch_deposit<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const Geo&, M*,        \
                                      hipStream_t);                                                        \
   template void launch_gather<R, M>(int64_t, const PPPos<R>*, const MeshRec<R>*, const PPRec<R>*,          \
                                     const uint32_t*, const Geo&, const Place*, const M*, GatherOut,       \
