@@ -400,20 +400,23 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z_reg(Geo geo, C2<float>* _
     const int p = q + 16 * m;
     v[m] = (valid && p < N) ? base[p * zstride] : C2<float>{0.f, 0.f};
   }
-  reg_first_half(v, q, tw, s, b);
-  __syncthreads();
-  reg_second_half(v, q, s, b);
-  // v[k2] = Z(kz), kz = q + 16 k2: conj(Ghat Z) is the inverse's input
+  // the kernel table at this thread's frequencies kz = q + 16 k2 (after the
+  // forward transform), loaded now so that its latency overlaps the transform
   const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
   const float* grow = gz + (long long)kyp * KS + (valid ? kx : K - 1);
   const long long gplane_s = (long long)(geo.grid[1] + 1) * KS;
+  float g[16];
 #pragma unroll
   for (int k2 = 0; k2 < 16; ++k2) {
     const int kz = q + 16 * k2;
-    const int kzp = kz <= N ? kz : L - kz;
-    const float g = grow[kzp * gplane_s];
-    v[k2] = C2<float>{g * v[k2].x, -(g * v[k2].y)};
+    g[k2] = grow[(kz <= N ? kz : L - kz) * gplane_s];
   }
+  reg_first_half(v, q, tw, s, b);
+  __syncthreads();
+  reg_second_half(v, q, s, b);
+  // v[k2] = Z(kz): conj(Ghat Z) is the inverse's input
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) v[k2] = C2<float>{g[k2] * v[k2].x, -(g[k2] * v[k2].y)};
   __syncthreads();   // every thread has read its column of s
   reg_first_half(v, q, tw, s, b);
   __syncthreads();
