@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "p3m.h"
@@ -283,7 +284,9 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   p3m_status s;
   if ((s = engine_mesh_alloc(ctx, EM)) != P3M_OK) return s;
   if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
-  const Geo& g = ctx->geo;
+  // float records of a call without weights carry the position residuals
+  Geo g = ctx->geo;
+  g.wpacked = (std::is_same<R, float>::value && !qw) ? 1 : 0;
   {
     StageTimer t(ctx, 1, st);
     launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);

@@ -57,6 +57,7 @@ struct Geo {
   int gather;          // 0 variational, 1 momentum-conserving (mesh E by central differences)
   int cathode;         // 1: grounded plane z = zc (image charges on the mesh)
   int influence;       // mesh kernel table: kInfluence*
+  int wpacked;         // per call: float records carry position residuals, weights all 1
   double zc;           // plane position (m)
 };
 
@@ -102,6 +103,23 @@ struct alignas(16) PPFix { int x, y, z; float w; };
 template <typename R> struct PPPosOf { using type = PPRec<R>; };
 template <> struct PPPosOf<float> { using type = PPFix; };
 template <typename R> using PPPos = typename PPPosOf<R>::type;
+
+// Sub-unit residuals of a float record. A fixed-point position rounds the
+// position to the unit, so a separation of d units is good to about 1/d:
+// for the closest pairs (a few thousand units) that is 1e-4. When every
+// weight is 1 (Geo::wpacked), the weight slot holds the residual u - rint(u)
+// of each axis instead, in units of 2^-kResBits, as three signed 10-bit fields;
+// pairs closer than kCloseUnits add them back.
+constexpr int kResBits = 10;
+constexpr float kCloseUnits2 = 70368744177664.0f;   // (2^23 units)^2: beyond, rounding is below float's
+__host__ __device__ inline float rec_w(const PPFix& r, const Geo& g) { return g.wpacked ? 1.0f : r.w; }
+template <typename R>
+__host__ __device__ inline R rec_w(const PPRec<R>& r, const Geo&) { return r.w; }
+// Residual field f (0..2) of a packed weight slot, sign-extended. The bit
+// field builtin is typed unsigned; the cast keeps the field difference signed.
+__device__ __forceinline__ int res_field(int v, int f) {
+  return (int)__builtin_amdgcn_sbfe(v, 10 * f, 10);
+}
 
 __host__ __device__ inline double fix_unit(const double cu[3]) {
   const double m = cu[0] > cu[1] ? (cu[0] > cu[2] ? cu[0] : cu[2]) : (cu[1] > cu[2] ? cu[1] : cu[2]);

@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
     if (j < n) {
       int b[3];
       unpack_base(mesh[j], nx, nxy, b);
-      qmax = fmax(qmax, fabs((double)pp[j].w));
+      qmax = fmax(qmax, fabs((double)rec_w(pp[j], geo)));
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         lo[d] = min(lo[d], b[d]);
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
           const int64_t j = j0 + it * kDepThreads + t;
           if (j >= n) continue;
           const MeshRec<R> m = mesh[j];
-          const R q = pp[j].w;
+          const R q = rec_w(pp[j], geo);
           int b[3];
           unpack_base(m, nx, nxy, b);
           const int rx = b[0] - o0, ry = b[1] - o1 - py, rz = b[2] - o2 - pz;
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
       const int64_t j = j0 + it * kDepThreads + t;
       if (j >= n) continue;
       const MeshRec<R> m = mesh[j];
-      const R q = pp[j].w;
+      const R q = rec_w(pp[j], geo);
       int b[3];
       unpack_base(m, nx, nxy, b);
       const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
   double e_acc = 0.0;
   if (j < n) {
     const MeshRec<R> m = mesh[j];
-    const R q = pp[j].w;
+    const R q = rec_w(pp[j], geo);
     Stencil<M, ORDER> S((M)m.fx, (M)m.fy, (M)m.fz);
     const int nx = geo.grid[0];
     const long long nxy = (long long)nx * geo.grid[1];

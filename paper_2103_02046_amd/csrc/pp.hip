@@ -178,7 +178,7 @@ constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
 //      cell-local positions plus cell-corner offsets (exact multiples of the
 //      cell edge). The tile sum is added to the per-particle total with
 //      Kahan compensation (float form).
-template <typename R, bool ENERGY>
+template <typename R, bool ENERGY, bool PACKED>
 __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter,
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
                                            const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
@@ -189,6 +189,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   constexpr int TS = kTileK + 1;
   constexpr int NT = kWaveGroups * TS;
   constexpr bool kFix = std::is_same<R, float>::value;
+  // PACKED: float records whose weight slot holds position residuals (all weights 1)
+  static_assert(kFix || !PACKED, "residual packing is a float-form layout");
   __shared__ V4 tile[NT];                   // group-relative x, y, z (cutoff test)
   __shared__ int4 tfix[kFix ? NT : 1];      // float: fixed-point x, y, z from the group's corner; weight bits
   __shared__ V4 tloc[kFix ? 1 : NT];        // double: cell-local x, y, z and the charge weight
@@ -243,6 +245,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   const bool active = gvalid && ql < gd.y;
   R lx = 0, ly = 0, lz = 0, tw = 0;
   int ix = 0, iy = 0, iz = 0;
+  int tres = 0;   // float form, packed records: the target's position residuals
   int tdc = 0;
   if (active) {
     const int j = gd.x + ql;
@@ -252,12 +255,13 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       ix = me.x + tdc * kex;
       iy = me.y;
       iz = me.z;
+      tres = __float_as_int(me.w);
     } else {
       lx = me.x;
       ly = me.y;
       lz = me.z;
     }
-    tw = me.w;
+    tw = PACKED ? (R)1 : rec_w(me, geo);
   }
   const R tox = (R)tdc * cux;
   // cutoff test: r^2 - lim = (|t|^2 + (|c|^2 - lim)) - 2 t.c with lim =
@@ -388,8 +392,21 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         dx = (R)(ix - cf.x);
         dy = (R)(iy - cf.y);
         dz = (R)(iz - cf.z);
-        wj = __int_as_float(cf.w);
-        r2 = (dx * dx + dy * dy + dz * dz) * fu2;
+        R d2 = dx * dx + dy * dy + dz * dz;
+        if constexpr (PACKED) {
+          wj = (R)1;
+          if (d2 < kCloseUnits2) {
+            // a close pair: add the difference of the sub-unit residuals
+            const R s = (R)1 / (R)(1 << kResBits);
+            dx += (R)(res_field(tres, 0) - res_field(cf.w, 0)) * s;
+            dy += (R)(res_field(tres, 1) - res_field(cf.w, 1)) * s;
+            dz += (R)(res_field(tres, 2) - res_field(cf.w, 2)) * s;
+            d2 = dx * dx + dy * dy + dz * dz;
+          }
+        } else {
+          wj = __int_as_float(cf.w);
+        }
+        r2 = d2 * fu2;
       } else {
         const V4 cl = tloc[TS * q + k];
         const V4 co = toff[TS * q + k];
@@ -516,15 +533,23 @@ void launch_pp_groups(const int* cell_start, const Geo& geo, int2* desc, int* co
 }
 
 template <typename R>
+constexpr bool kPackable = std::is_same<R, float>::value;
+
+template <typename R>
 void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
                hipStream_t st) {
   // one wave per quad of groups; waves beyond the groups built leave at once
   const unsigned blocks = (unsigned)((pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups);
-  if (energy)
-    k_pp<R, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
+  const bool packed = std::is_same<R, float>::value && geo.wpacked;
+  if (energy && packed)
+    k_pp<R, true, kPackable<R>><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
+  else if (energy)
+    k_pp<R, true, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
+  else if (packed)
+    k_pp<R, false, kPackable<R>><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr);
   else
-    k_pp<R, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr);
+    k_pp<R, false, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr);
 }
 
 void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys, const int* cell_start,

@@ -196,26 +196,32 @@ __global__ void k_cell_start(int64_t n, const uint32_t* __restrict__ keys, int* 
 }
 
 template <typename R>
-__device__ __forceinline__ PPPos<R> make_pos(const double* loc, const double* cu, double w);
+__device__ __forceinline__ PPPos<R> make_pos(const double* loc, const double* cu, double w, bool packed);
 template <>
-__device__ __forceinline__ PPPos<double> make_pos<double>(const double* loc, const double*, double w) {
+__device__ __forceinline__ PPPos<double> make_pos<double>(const double* loc, const double*, double w, bool) {
   return PPPos<double>{loc[0], loc[1], loc[2], w};
 }
 // Nearest fixed-point value. Inside the mesh a particle lies in [0, 1] cell
 // edges of its cell's corner; one outside it (reported as a domain error)
 // is clamped to [-1/2, 3/2) edges, which keeps every PP separation, cell
 // offsets included, below 2^31 units (an edge is at most 2^29 units).
+// packed (every weight 1): the weight slot holds the residuals u - rint(u),
+// rounded to 2^-kResBits units, as three 10-bit fields (x lowest).
 template <>
-__device__ __forceinline__ PPPos<float> make_pos<float>(const double* loc, const double* cu, double w) {
+__device__ __forceinline__ PPPos<float> make_pos<float>(const double* loc, const double* cu, double w,
+                                                        bool packed) {
   const double unit = fix_unit(cu);
   int v[3];
+  unsigned res = 0;
   for (int d = 0; d < 3; ++d) {
     const double e = (double)fix_edge(cu, d);
     double u = loc[d] / unit;
     u = fmin(fmax(u, -0.5 * e), 1.4999999 * e);
     v[d] = (int)rint(u);
+    const int r = min(max((int)rint((u - v[d]) * (1 << kResBits)), -511), 511);
+    res |= ((unsigned)r & 1023u) << (10 * d);
   }
-  return PPFix{v[0], v[1], v[2], (float)w};
+  return PPFix{v[0], v[1], v[2], packed ? __uint_as_float(res) : (float)w};
 }
 
 template <typename R>
@@ -244,7 +250,7 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
   // rounding (units of Lu, or fixed point of the cell edge).
   double loc[3];
   for (int d = 0; d < 3; ++d) loc[d] = (xi[d] - P.x0[d]) * P.inv_lu - c[d] * geo.cu[d];
-  pp[j] = make_pos<R>(loc, geo.cu, w);
+  pp[j] = make_pos<R>(loc, geo.cu, w, geo.wpacked != 0);
   // Mesh record: stencil origin and fractional offset (Sec. 2.4.2 B-splines).
   // CIC: base floor(u), offset u - base in [0, 1).
   // TSC: centre floor(u + 1/2), offset u - centre in [-1/2, 1/2), base centre - 1.

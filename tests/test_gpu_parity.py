@@ -208,6 +208,45 @@ def test_charge_weights():
     assert rms_err(f, O.forces(x, prm)) < TOL64
 
 
+def test_charge_weights_fp32c():
+    """Float-compensated path with per-particle weights (records keep the
+    weight; without weights they carry the position residuals instead)."""
+    rng = np.random.default_rng(4)
+    wl = small_aniso(n=8192, grid=32)
+    x, _ = wl.draw()
+    qw = rng.random(wl.n) + 0.5
+    c = ctx_for(wl, p3m.FP32C)
+    f = host(c.forces(dev(x), qw=dev(qw)))
+    prm = O.Params.from_workload(wl, qw=qw)
+    assert rms_err(f, O.forces(x, prm)) < TOL32
+
+
+def test_fp32c_close_pairs():
+    """Pairs 1e-5 .. 1e-3 cutoffs apart: a fixed-point position alone is good
+    to 1 part in the separation in units (1e-4 at the closest), the records'
+    residual fields bring the float pair force back to float precision."""
+    rng = np.random.default_rng(6)
+    wl = small_aniso(n=8192, grid=32)
+    x, _ = wl.draw()
+    prm = O.Params.from_workload(wl)
+    rc = O.placement(x, prm)["rc"]
+    m = 24
+    first = rng.choice(wl.n // 2, m, replace=False)
+    second = wl.n // 2 + first
+    u = rng.standard_normal((m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    x[second] = x[first] + u * (rc * 10.0 ** rng.uniform(-5, -3, m))[:, None]
+    pl = O.placement(x, prm)
+    idx = np.concatenate([first, second])
+    ref = O.pp_sample(x, prm, pl["rc"], pl["a"], idx)
+    c = ctx_for(wl, p3m.FP32C)
+    fpp, _, _ = c.forces_parts(dev(x))
+    got = host(fpp)[idx]
+    rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    print(f"close pairs: max rel pp error {rel.max():.2e}")
+    assert rel.max() < 3e-6
+
+
 def test_error_status_words():
     rng = np.random.default_rng(5)
     x = rng.standard_normal((300, 3))
