@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
 PEAK_FP32_VALU = 157.3         # TFLOP/s, vector FP32 (256 CU x 2.4 GHz)
 PEAK_FP64_VALU = 78.6          # TFLOP/s, vector FP64
-PP_FLOP_PER_PAIR = 40          # canonical count per in-cutoff ordered pair
+PP_FLOP_PER_PAIR = 40          # per in-cutoff ordered pair: FMA 2, rsqrt/exp/rcp 1 each, the 7-term
+                               # polynomial 14, plus the separation, products and Kahan adds
 
 
 def parse():
@@ -106,8 +107,7 @@ def cpu_baseline(wl, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(the sharded design is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     from paper_2103_02046_amd import p3m
@@ -198,7 +198,8 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak}
     else:
-        # compulsory bytes per launch of the stage (the design doc lists each)
+        # compulsory bytes per launch of the stage: the records each kernel must
+        # read and write once per particle, mesh node and kernel-table entry
         per_stage = {
             "fft": 2 * fbytes * mesh_nodes + 8 * (wl.grid[0] + 1) * (wl.grid[1] + 1) * (wl.grid[2] + 1),
             "sort": 3 * 16 * wl.n,
@@ -213,6 +214,8 @@ def main():
                 "frac": achieved / PEAK_HBM_GBS}
     roof["kernel"] = stage
     roof["avg_launch_ms"] = avg_s * 1e3
+    if stage == "pp":
+        roof["pairs_per_s"] = pairs / avg_s
     roof["traffic"] = traffic_from_profiles(stage, args.workload, args.precision, 1)
 
     out = {
@@ -239,7 +242,7 @@ def main():
             "boundary": "grounded plane 1 mm below the bunch" if args.cathode else "open",
             "influence": args.influence,
             "force_rms_err_vs_fp64": err,
-            "pp_pairs_per_s": pairs * args.steps / wall,
+            "pairs_per_s_of_step": pairs * args.steps / wall,
             "pairs_per_eval": pairs,
             "pairs_first_last_eval": [d0["pairs"], d1["pairs"]],
             "status": status,
