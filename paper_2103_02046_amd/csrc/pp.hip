@@ -11,8 +11,9 @@
 //
 // float form: erfc(x) = exp(-x^2) t P(t), t = 1/(1 + x/2), with the degree-6
 // polynomial fitted in this repository on 0 <= x <= 6 (fit_erfcx.py; relative
-// error < 5e-7 in float; beyond x = 6 both terms of the pair force are below
-// 2e-16 of their value at 0), the exp(-x^2) shared with the second term;
+// error < 5e-7 in float), the exp(-x^2) shared with the second term. Beyond
+// x = 6 (kappa > 6 only) t < 1/4, where |t P(t)| < 0.1, and exp(-x^2) <
+// 2.4e-16 leaves both terms of the pair force negligible, so t is not clamped;
 // per-particle sums are Kahan compensated. double form: the device
 // library's erfc and exp.
 #include <type_traits>
@@ -58,7 +59,7 @@ struct PairK {
 __device__ __forceinline__ float pair_scalar(float r2, float wj, const PairK<float>& K, float* epair) {
   const float rinv = __builtin_amdgcn_rsqf(r2);
   const float r = r2 * rinv;
-  const float t = fmaxf(__builtin_amdgcn_rcpf(fmaf(K.half_kappa, r, 1.0f)), P3M_ERFCX_TMIN);
+  const float t = __builtin_amdgcn_rcpf(fmaf(K.half_kappa, r, 1.0f));
   const float e = __builtin_amdgcn_exp2f(K.ek * r2);
   const float tp = t * erfcx_poly(t);
   if (epair) *epair = e * tp * rinv * wj;
@@ -377,15 +378,16 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     }
     if (!active) m0 = m1 = 0u;
     // 3. own hits (the particle itself and coincident ones give r2 = 0).
-    //    As one 64-bit word (m0 high), bit b is candidate 63 - b; the lowest
-    //    set bit is taken and cleared each round. Float form: separations
+    //    As one 64-bit word (m0 high), bit b is candidate 63 - b, so the
+    //    count of leading zeros is the candidate index; the highest set bit
+    //    is taken and cleared each round. Float form: separations
     //    in fixed-point units, the unit applied to r2 here and to the sums
     //    at the end.
     R sx = 0, sy = 0, sz = 0;
     uint64_t hm = ((uint64_t)m0 << 32) | m1;
     while (hm) {
-      const int k = 63 - (int)__builtin_ctzll(hm);
-      hm &= hm - 1;
+      const int k = (int)__builtin_clzll(hm);   // the highest set bit, 63 - k
+      hm ^= 0x8000000000000000ull >> k;
       R dx, dy, dz, wj, r2;
       if constexpr (kFix) {
         const int4 cf = tfix[TS * q + k];
