@@ -275,7 +275,8 @@ p3m_status p3m_profile_end(p3m_ctx *ctx, double ms[8], int64_t launches[8], void
  * (P3M_OK, P3M_EDOMAIN or P3M_ENONFINITE). */
 p3m_status p3m_status_sync(p3m_ctx *ctx, void *stream);
 
-/* Number of radix-sort passes, PP cells and padded FFT extents (host info). */
+/* Host info: passes of the cell sort over the keys (1, a counting sort),
+ * PP cells (total, x, y, z) and the padded FFT extents (x, y, z). */
 p3m_status p3m_info(const p3m_ctx *ctx, int64_t out[8]);
 
 /* Message of the last failing call on ctx (never NULL). */

@@ -49,7 +49,6 @@ struct p3m_ctx {
   // sort
   SortBufs sb{};
   int2* groups = nullptr;       // PP work groups
-  int* group_scratch = nullptr; // per-row group offsets
   int sort_nb_cap = 0;
   // placement, status, small scratch
   Place* place = nullptr;
@@ -198,11 +197,9 @@ p3m_status ensure_state(p3m_ctx* ctx, bool weights) {
 p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   if (n > 0xffffffffll / 2) return fail(ctx, P3M_EINVAL, "n exceeds the 32-bit particle index range");
   if (n <= ctx->cap) return P3M_OK;
-  dfree(ctx->sb.keys_a);
-  dfree(ctx->sb.vals_a);
-  dfree(ctx->sb.keys_b);
-  dfree(ctx->sb.vals_b);
-  dfree(ctx->sb.counts);
+  dfree(ctx->sb.keys_in);
+  dfree(ctx->sb.keys);
+  dfree(ctx->sb.perm);
   dfree(ctx->groups);
   dfree(ctx->fcache);
   free_state(ctx);
@@ -213,11 +210,9 @@ p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   dfree(ctx->pb);
   ctx->cap = 0;
   ctx->force_cached = false;
-  HIPCHK(dalloc(&ctx->sb.keys_a, (size_t)n));
-  HIPCHK(dalloc(&ctx->sb.vals_a, (size_t)n));
-  HIPCHK(dalloc(&ctx->sb.keys_b, (size_t)n));
-  HIPCHK(dalloc(&ctx->sb.vals_b, (size_t)n));
-  HIPCHK(dalloc(&ctx->sb.counts, (size_t)3 * 2048 * sort_blocks(n)));   // per pass (at most 3)
+  HIPCHK(dalloc(&ctx->sb.keys_in, (size_t)n));
+  HIPCHK(dalloc(&ctx->sb.keys, (size_t)n));
+  HIPCHK(dalloc(&ctx->sb.perm, (size_t)n));
   HIPCHK(dalloc(&ctx->groups, (size_t)pp_group_bound(n, ctx->geo)));
   HIPCHK(dalloc(&ctx->fcache, (size_t)3 * n));
   ctx->cap = n;
@@ -289,8 +284,7 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   g.wpacked = (std::is_same<R, float>::value && !qw) ? 1 : 0;
   {
     StageTimer t(ctx, 1, st);
-    launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
-    launch_pp_groups(ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, ctx->group_scratch, st);
+    launch_cell_sort(n, x, ctx->place, g, ctx->sb, ctx->groups, &ctx->keys, &ctx->perm, st);
   }
   {
     StageTimer t(ctx, 2, st);
@@ -342,7 +336,7 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
   if ((s = ensure_adjoint(ctx, n)) != P3M_OK) return s;
   const Geo& g = ctx->geo;
-  launch_cell_sort(n, x, ctx->place, g, ctx->sb, &ctx->keys, &ctx->perm, st);
+  launch_cell_sort(n, x, ctx->place, g, ctx->sb, ctx->groups, &ctx->keys, &ctx->perm, st);
   launch_reorder<double>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, Carry{}, st);
   launch_sort_vector<double>(n, v, ctx->perm, ctx->v_sorted, st);
   launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
@@ -443,10 +437,12 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   hipStream_t st = 0;
   if (dalloc(&ctx->place, 1) != hipSuccess || dalloc(&ctx->status, 1) != hipSuccess ||
       dalloc(&ctx->bbox_part, 6 * 1024) != hipSuccess || dalloc(&ctx->acc, 64) != hipSuccess ||
-      dalloc(&ctx->sb.ghist, 3 * 2048) != hipSuccess || dalloc(&ctx->sb.counter, 2) != hipSuccess ||
-      dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess ||
-      dalloc(&ctx->group_scratch, (size_t)pp_scratch_ints(g)) != hipSuccess)
+      dalloc(&ctx->sb.counter, 2) != hipSuccess || dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess ||
+      dalloc(&ctx->sb.ccount, (size_t)g.ncells) != hipSuccess || dalloc(&ctx->sb.cfill, (size_t)g.ncells) != hipSuccess ||
+      dalloc(&ctx->sb.btot, (size_t)2 * cell_blocks(g.ncells)) != hipSuccess)
     return bail(P3M_ENOMEM);
+  // the per-cell counts start at zero; each sort leaves them at zero
+  if (hipMemset(ctx->sb.ccount, 0, (size_t)g.ncells * sizeof(int)) != hipSuccess) return bail(P3M_EHIP);
   if (hipMemset(ctx->status, 0, sizeof(int)) != hipSuccess) return bail(P3M_EHIP);
   // Fourier table of the mesh kernel (float64), built once.
   const size_t oct = (size_t)(grid[0] + 1) * (grid[1] + 1) * (grid[2] + 1);
@@ -740,7 +736,7 @@ p3m_status p3m_status_sync(p3m_ctx* ctx, void* stream) {
 
 p3m_status p3m_info(const p3m_ctx* ctx, int64_t out[8]) {
   if (!ctx || !out) return P3M_EINVAL;
-  out[0] = sort_passes(ctx->geo.ncells);
+  out[0] = 1;   // one counting pass over the keys
   out[1] = ctx->geo.ncells;
   out[2] = ctx->geo.ncell[0];
   out[3] = ctx->geo.ncell[1];
@@ -761,15 +757,14 @@ void p3m_destroy(p3m_ctx* ctx) {
   for (auto& e : ctx->prof_ev) (void)hipEventDestroy(e);
   engine_free(ctx->e32);
   engine_free(ctx->e64);
-  dfree(ctx->sb.keys_a);
-  dfree(ctx->sb.vals_a);
-  dfree(ctx->sb.keys_b);
-  dfree(ctx->sb.vals_b);
-  dfree(ctx->sb.counts);
-  dfree(ctx->sb.ghist);
+  dfree(ctx->sb.keys_in);
+  dfree(ctx->sb.keys);
+  dfree(ctx->sb.perm);
+  dfree(ctx->sb.ccount);
+  dfree(ctx->sb.cfill);
+  dfree(ctx->sb.btot);
   dfree(ctx->sb.counter);
   dfree(ctx->groups);
-  dfree(ctx->group_scratch);
   dfree(ctx->sb.cell_start);
   dfree(ctx->place);
   dfree(ctx->status);

@@ -11,6 +11,9 @@ constexpr int kBitDomain = 1;     // a particle outside the mesh with zoom off
 constexpr int kBitNonFinite = 2;  // a non-finite position
 
 constexpr int kThreads = 256;     // block size of the particle kernels
+// PP work groups: runs of at most kGroupRun consecutive sorted particles of
+// one cell, listed in cell order (built by the cell sort, read by the PP kernel).
+constexpr int kGroupRun = 16;
 constexpr int kXcds = 8;          // MI355X: work-groups are dealt round-robin to 8 XCDs
 
 // Placement of one evaluation, written on the device by the finalize kernel.

@@ -16,16 +16,18 @@ void launch_place_finalize(int nblk, const double* part, const Geo& geo, const d
 
 // ---- linked cells (sort.hip) ----------------------------------------------
 struct SortBufs {
-  uint32_t *keys_a, *vals_a, *keys_b, *vals_b;
-  int* counts;      // [passes][2048][nblocks]
-  int* ghist;       // [passes][2048]
+  uint32_t *keys_in, *keys, *perm;   // [n]: keys in input order; sorted keys and input index
+  int* ccount;      // [ncells] particles per cell, zero between sorts
+  int* cfill;       // [ncells] the scatter's fill pointers
+  int* btot;        // [2 cell_blocks] particles and groups per block of cells
   int* cell_start;  // [ncells + 1]
-  int* counter;     // [0] PP groups built, [1] PP groups taken; cleared by the key kernel
+  int* counter;     // [0] PP groups built
 };
-int sort_passes(long long ncells);
-int sort_blocks(int64_t n);
-// Sorts particles by PP cell; on return *keys/*perm point at the sorted arrays.
-void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b,
+int cell_blocks(long long ncells);
+// Counting sort of the particles by PP cell: keys, cell starts and the PP
+// work groups (desc, counter[0]); on return *keys/*perm point at the sorted
+// key and input index arrays.
+void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b, int2* desc,
                       uint32_t** keys, uint32_t** perm, hipStream_t st);
 // Stepping in cell order: the reorder also moves the particle state into the
 // new order (x_out NULL: nothing is moved).
@@ -48,14 +50,8 @@ template <typename R>
 void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out, hipStream_t st);
 
 // ---- pair forces (pp.hip) ------------------------------------------------
-// Upper bound of the number of PP work groups (runs of <= 64 particles per cell row).
+// Upper bound of the number of PP work groups (runs of <= kGroupRun particles of one cell).
 int pp_group_bound(int64_t n, const Geo& geo);
-// Ints of scratch the group builder needs.
-int pp_scratch_ints(const Geo& geo);
-// Work groups of the PP kernel (runs of at most 16 particles of one cell, in
-// cell order) from the cell starts; counter[0] receives their number.
-void launch_pp_groups(const int* cell_start, const Geo& geo, int2* desc, int* counter, int* scratch,
-                      hipStream_t st);
 template <typename R>
 void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,

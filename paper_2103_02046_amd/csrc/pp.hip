@@ -91,54 +91,11 @@ struct Acc3<double> {
   __device__ __forceinline__ double get(int d) const { return s[d]; }
 };
 
-// Work groups: runs of at most 16 consecutive sorted particles of one cell.
-// The candidates of every particle of a group lie in 9 contiguous ranges:
-// cells cx-1 .. cx+1 of the 3 x 3 neighbouring rows (a row of cells is
-// contiguous in the sorted order). Groups are listed in cell order (count
-// per cell, prefix sum, emit), so consecutive groups are spatial neighbours.
-constexpr int kGroupMax = 16;
-
-__global__ void __launch_bounds__(kThreads) k_pp_groups_count(const int* __restrict__ cs, long long ncells,
-                                                              int* __restrict__ celloff, int* __restrict__ btot) {
-  const long long c = blockIdx.x * (long long)kThreads + threadIdx.x;
-  const int ng = c < ncells ? (cs[c + 1] - cs[c] + kGroupMax - 1) / kGroupMax : 0;
-  __shared__ int s[kThreads];
-  const int t = threadIdx.x;
-  s[t] = ng;
-  __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
-    const int add = t >= off ? s[t - off] : 0;
-    __syncthreads();
-    s[t] += add;
-    __syncthreads();
-  }
-  if (c < ncells) celloff[c] = s[t] - ng;
-  if (t == kThreads - 1) btot[blockIdx.x] = s[t];
-}
-
-
-// Each block sums the group totals of the blocks before it (a few thousand
-// cached ints) instead of a separate scan; the last block stores the total.
-__global__ void __launch_bounds__(kThreads) k_pp_groups_emit(const int* __restrict__ cs, long long ncells,
-                                                             const int* __restrict__ celloff,
-                                                             const int* __restrict__ btot,
-                                                             int2* __restrict__ desc, int* __restrict__ counter) {
-  __shared__ int red[kThreads / 64];
-  const int t = threadIdx.x;
-  int before = 0;
-  for (int q = t; q < (int)blockIdx.x; q += kThreads) before += btot[q];
-  for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off);
-  if ((t & 63) == 0) red[t >> 6] = before;
-  __syncthreads();
-  int boff = 0;
-  for (int w = 0; w < kThreads / 64; ++w) boff += red[w];
-  if (blockIdx.x == gridDim.x - 1 && t == 0) counter[0] = boff + btot[blockIdx.x];
-  const long long c = blockIdx.x * (long long)kThreads + t;
-  if (c >= ncells) return;
-  const int b = cs[c], cnt = cs[c + 1] - b;
-  int g = boff + celloff[c];
-  for (int k = 0; k < cnt; k += kGroupMax) desc[g++] = make_int2(b + k, min(kGroupMax, cnt - k));
-}
+// Work groups (kGroupRun particles at most, one cell) come from the cell
+// sort. The candidates of every particle of a group lie in 9 contiguous
+// ranges: cells cx-1 .. cx+1 of the 3 x 3 neighbouring rows (a row of cells
+// is contiguous in the sorted order); consecutive groups are spatial
+// neighbours.
 
 // (m << 1) | sign(v): one v_alignbit_b32 for float; the sign of a double is
 // the top bit of its high word.
@@ -515,23 +472,9 @@ __global__ void __launch_bounds__(kThreads) k_pp_hvp(int64_t n, const PPRec<doub
 int pp_group_bound(int64_t n, const Geo& geo) {
   // runs of <= 16 particles of one cell: at most n/16 full runs plus one
   // partial run per cell, and never more than n
-  long long b = n / kGroupMax + geo.ncells + 1;
+  long long b = n / kGroupRun + geo.ncells + 1;
   if (b > n + 1) b = n + 1;
   return (int)b;
-}
-
-int pp_scratch_ints(const Geo& geo) {
-  return (int)(geo.ncells + (geo.ncells + kThreads - 1) / kThreads);
-}
-
-void launch_pp_groups(const int* cell_start, const Geo& geo, int2* desc, int* counter, int* scratch,
-                      hipStream_t st) {
-  const long long nc = geo.ncells;
-  const int cb = (int)((nc + kThreads - 1) / kThreads);
-  int* celloff = scratch;
-  int* btot = scratch + nc;
-  k_pp_groups_count<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot);
-  k_pp_groups_emit<<<cb, kThreads, 0, st>>>(cell_start, nc, celloff, btot, desc, counter);
 }
 
 template <typename R>

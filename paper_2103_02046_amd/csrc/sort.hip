@@ -1,6 +1,6 @@
-// Linked cells on the device: PP-cell key per particle, a stable LSD radix
-// sort of (key, index) with digits of up to 11 bits, the start of every cell in the
-// sorted order, and the reorder of the particles into sorted records.
+// Linked cells on the device: PP-cell key per particle, a counting sort by
+// cell (per-cell counts, their prefix sum as the cell starts, and a scatter),
+// the PP work groups, and the reorder of the particles into sorted records.
 //
 // The paper sums the short-range force over particles "close to" each
 // particle (Sec. 1, eq. summation_short) inside the cutoff; cells of edge
@@ -13,73 +13,7 @@ namespace p3m {
 
 namespace {
 
-constexpr int kItems = 8;                  // keys per thread in a radix tile
-constexpr int kTile = kThreads * kItems;   // 2048 keys per block
 constexpr int kWaves = kThreads / 64;
-
-__global__ void __launch_bounds__(kThreads) k_keys(int64_t n, const double* __restrict__ x,
-                                                   const Place* __restrict__ pl, Geo geo,
-                                                   uint32_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals,
-                                                   int* __restrict__ ghist, int nhist,
-                                                   int* __restrict__ counter, int* __restrict__ counts,
-                                                   int64_t ncounts) {
-  if (blockIdx.x == 0) {
-    for (int k = threadIdx.x; k < nhist; k += kThreads) ghist[k] = 0;
-    if (threadIdx.x < 2) counter[threadIdx.x] = 0;
-  }
-  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  // the per-block digit counts of every pass start at zero (the count
-  // kernels write only the digits present in their tile)
-  for (int64_t e = i; e < ncounts; e += (int64_t)gridDim.x * kThreads) counts[e] = 0;
-  if (i >= n) return;
-  const Place P = *pl;
-  int c[3];
-  for (int d = 0; d < 3; ++d)
-    c[d] = floor_clamp((x[3 * i + d] - P.x0[d]) * P.inv_cell[d], 0, geo.ncell[d] - 1);
-  keys[i] = (uint32_t)(((long long)c[2] * geo.ncell[1] + c[1]) * geo.ncell[0] + c[0]);
-  vals[i] = (uint32_t)i;
-}
-
-// Digits of db <= 11 bits (nbins = 2^db <= kMaxBins): keys of at most 22
-// bits, the usual case, take two passes.
-constexpr int kMaxBins = 2048;
-
-__global__ void __launch_bounds__(kThreads) k_radix_count(int64_t n, const uint32_t* __restrict__ keys,
-                                                          int shift, int nbins, int* __restrict__ counts,
-                                                          int* __restrict__ ghist, int nb) {
-  __shared__ int h[kMaxBins];
-  for (int d = threadIdx.x; d < nbins; d += kThreads) h[d] = 0;
-  __syncthreads();
-  const uint32_t mask = (uint32_t)nbins - 1u;
-  const int lane = threadIdx.x & 63;
-  int64_t base = (int64_t)blockIdx.x * kTile;
-  // Keys stepped in cell order arrive in runs of equal digits: the first lane
-  // of each run within the wave adds the run's length (valid lanes form a
-  // prefix of the wave; equal digits in separate runs simply add separately).
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t i = base + k * kThreads + threadIdx.x;
-    const bool valid = i < n;
-    const int d = valid ? (int)((keys[i] >> shift) & mask) : -1;
-    const int prev = __shfl_up(d, 1);
-    const bool head = valid && (lane == 0 || prev != d);
-    const unsigned long long heads = __ballot(head);
-    const int nvalid = __popcll(__ballot(valid));
-    if (head) {
-      const unsigned long long after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
-      const int next = after ? (int)__builtin_ctzll(after) : nvalid;
-      atomicAdd(&h[d], next - lane);
-    }
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < nbins; d += kThreads) {
-    const int c = h[d];
-    if (c) {
-      counts[(int64_t)d * nb + blockIdx.x] = c;
-      atomicAdd(&ghist[d], c);
-    }
-  }
-}
 
 // Exclusive scan of 256 values held one per thread; returns the thread's
 // exclusive prefix and writes the block total to *total.
@@ -100,99 +34,148 @@ __device__ inline int block_exclusive_scan(int v, int* total) {
   return incl - v;
 }
 
-// One block per digit: offsets[d][b] = (keys with a smaller digit) + (keys of
-// digit d in blocks before b). counts is overwritten with the offsets. The
-// first term is the sum of the digit histogram below d, formed by each block.
-__global__ void __launch_bounds__(kThreads) k_radix_scan(int* __restrict__ counts,
-                                                         const int* __restrict__ ghist, int nb) {
-  const int d = blockIdx.x, t = threadIdx.x;
-  if (ghist[d] == 0) return;   // no key has this digit: its offsets are never read
-  int below = 0;
-  for (int q = t; q < d; q += kThreads) below += ghist[q];
-  int total;
-  (void)block_exclusive_scan(below, &total);
-  int carry = total;
-  int* row = counts + (int64_t)d * nb;
-  for (int b0 = 0; b0 < nb; b0 += kThreads) {
-    int v = (b0 + t < nb) ? row[b0 + t] : 0;
-    int ex = block_exclusive_scan(v, &total);
-    if (b0 + t < nb) row[b0 + t] = carry + ex;
-    carry += total;
+// ---- counting sort by cell ------------------------------------------------
+// Keys stepped in cell order arrive in runs of equal cells. Within a wave
+// (valid lanes form a prefix) the first lane of each run of equal
+// consecutive keys is its head: *head_lane is the head of this lane's run,
+// *len the run's length (meaningful at heads).
+__device__ __forceinline__ void wave_runs(bool valid, uint32_t key, int lane, int* head_lane, int* len) {
+  const uint32_t prev = __shfl_up(key, 1);
+  const bool head = valid && (lane == 0 || prev != key);
+  const unsigned long long heads = __ballot(head);
+  const int nvalid = __popcll(__ballot(valid));
+  const unsigned long long upto = heads & ((2ull << lane) - 1ull);   // heads at or below this lane
+  *head_lane = upto ? 63 - (int)__builtin_clzll(upto) : 0;
+  const unsigned long long after = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+  *len = (after ? (int)__builtin_ctzll(after) : nvalid) - lane;
+}
+
+// Cell key of every particle, in the input order, and the number of
+// particles per cell (ccount starts at zero; the start kernel re-zeroes it).
+__global__ void __launch_bounds__(kThreads) k_cell_keys(int64_t n, const double* __restrict__ x,
+                                                        const Place* __restrict__ pl, Geo geo,
+                                                        uint32_t* __restrict__ keys, int* __restrict__ ccount) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < n;
+  uint32_t key = 0;
+  if (valid) {
+    const Place P = *pl;
+    int c[3];
+    for (int d = 0; d < 3; ++d)
+      c[d] = floor_clamp((x[3 * i + d] - P.x0[d]) * P.inv_cell[d], 0, geo.ncell[d] - 1);
+    key = (uint32_t)(((long long)c[2] * geo.ncell[1] + c[1]) * geo.ncell[0] + c[0]);
+    keys[i] = key;
+  }
+  int hl, len;
+  wave_runs(valid, key, lane, &hl, &len);
+  if (valid && hl == lane) atomicAdd(&ccount[key], len);
+}
+
+constexpr int kCellItems = 8;                        // cells per thread in the start scan
+constexpr int kCellTile = kThreads * kCellItems;     // 2048 cells per block
+
+// Particles and PP groups (runs of <= 16 of one cell) per block of cells.
+__global__ void __launch_bounds__(kThreads) k_cell_totals(const int* __restrict__ ccount, long long ncells,
+                                                          int* __restrict__ btot) {
+  const long long c0 = blockIdx.x * (long long)kCellTile + (long long)threadIdx.x * kCellItems;
+  int s = 0, gs = 0;
+#pragma unroll
+  for (int k = 0; k < kCellItems; ++k) {
+    if (c0 + k < ncells) {
+      const int v = ccount[c0 + k];
+      s += v;
+      gs += (v + kGroupRun - 1) / kGroupRun;
+    }
+  }
+  int tot_s, tot_g;
+  (void)block_exclusive_scan(s, &tot_s);
+  (void)block_exclusive_scan(gs, &tot_g);
+  if (threadIdx.x == 0) {
+    btot[2 * blockIdx.x] = tot_s;
+    btot[2 * blockIdx.x + 1] = tot_g;
   }
 }
 
-// Stable scatter of one tile: keys keep their order within a digit. Per
-// round of 256 keys, each wave ranks its lanes by matching the digit bit by
-// bit (ballots); the first lane of each digit run in a wave records the
-// run's length for the waves after it, adds it to the digit's running count
-// and clears its entry, so the per-wave counts never need a full clear.
-__global__ void __launch_bounds__(kThreads) k_radix_scatter(
-    int64_t n, const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift, int db,
-    const int* __restrict__ offsets, int nb) {
-  __shared__ int run[kMaxBins];
-  __shared__ int base[kMaxBins];
-  __shared__ int wcnt[kWaves][kMaxBins];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int nbins = 1 << db;
-  // a digit's offset is fetched when the digit first occurs in the tile (a
-  // tile of sorted keys holds few digits; two waves may fetch the same one)
-  for (int d = t; d < nbins; d += kThreads) {
-    run[d] = 0;
-    base[d] = -1;
-    for (int q = 0; q < kWaves; ++q) wcnt[q][d] = 0;
+// Cell starts (exclusive prefix of the counts), the scatter's fill pointers,
+// and the PP work groups in cell order. Each block sums the totals of the
+// blocks before it; ccount is cleared for the next sort; the last block
+// stores cell_start[ncells] and the number of groups (counter[0]).
+__global__ void __launch_bounds__(kThreads) k_cell_starts(int* __restrict__ ccount, long long ncells,
+                                                          const int* __restrict__ btot,
+                                                          int* __restrict__ cell_start, int* __restrict__ cfill,
+                                                          int2* __restrict__ desc, int* __restrict__ counter) {
+  __shared__ int red[2][kWaves];
+  const int t = threadIdx.x;
+  int ps = 0, pg = 0;
+  for (int q = t; q < (int)blockIdx.x; q += kThreads) {
+    ps += btot[2 * q];
+    pg += btot[2 * q + 1];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ps += __shfl_xor(ps, off);
+    pg += __shfl_xor(pg, off);
+  }
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = ps;
+    red[1][t >> 6] = pg;
   }
   __syncthreads();
-  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t mask = (uint32_t)nbins - 1u;
-  int64_t tile = (int64_t)blockIdx.x * kTile;
-  for (int k = 0; k < kItems; ++k) {
-    int64_t i = tile + k * kThreads + t;
-    const bool valid = i < n;
-    uint32_t key = valid ? kin[i] : 0u;
-    uint32_t val = valid ? vin[i] : 0u;
-    const int d = (int)((key >> shift) & mask);
-    unsigned long long peers = __ballot(valid);
-    for (int bit = 0; bit < db; ++bit) {
-      const bool b = (d >> bit) & 1;
-      unsigned long long m = __ballot(b);
-      peers &= b ? m : ~m;
+  int P = 0, G = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    P += red[0][w];
+    G += red[1][w];
+  }
+  const long long c0 = blockIdx.x * (long long)kCellTile + (long long)t * kCellItems;
+  int v[kCellItems];
+  int s = 0, gs = 0;
+#pragma unroll
+  for (int k = 0; k < kCellItems; ++k) {
+    v[k] = c0 + k < ncells ? ccount[c0 + k] : 0;
+    s += v[k];
+    gs += (v[k] + kGroupRun - 1) / kGroupRun;
+  }
+  int tot;
+  int start = P + block_exclusive_scan(s, &tot);
+  int g = G + block_exclusive_scan(gs, &tot);
+#pragma unroll
+  for (int k = 0; k < kCellItems; ++k) {
+    if (c0 + k < ncells) {
+      cell_start[c0 + k] = start;
+      cfill[c0 + k] = start;
+      ccount[c0 + k] = 0;
+      for (int j = 0; j < v[k]; j += kGroupRun) desc[g++] = make_int2(start + j, min(kGroupRun, v[k] - j));
+      start += v[k];
     }
-    const int rank = __popcll(peers & lt);
-    const int cnt = __popcll(peers);
-    if (valid && rank == 0) {
-      wcnt[w][d] = cnt;
-      if (base[d] < 0) base[d] = offsets[(int64_t)d * nb + blockIdx.x];
-    }
-    __syncthreads();
-    if (valid) {
-      int pos = base[d] + run[d] + rank;
-      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
-      kout[pos] = key;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    if (valid && rank == 0) {
-      atomicAdd(&run[d], cnt);
-      wcnt[w][d] = 0;
-    }
-    __syncthreads();
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == kThreads - 1) {
+    cell_start[ncells] = start;
+    counter[0] = g;
   }
 }
 
-// cell_start[c] = first sorted index with key >= c, for c in [0, ncells]:
-// one thread per cell, binary search in the sorted keys.
-__global__ void k_cell_start(int64_t n, const uint32_t* __restrict__ keys, int* __restrict__ cs,
-                             long long ncells) {
-  const long long c = blockIdx.x * (long long)kThreads + threadIdx.x;
-  if (c > ncells) return;
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((long long)keys[mid] < c) lo = mid + 1;
-    else hi = mid;
+// Sorted position of every particle: one atomic per run of equal keys on
+// the cell's fill pointer, the run's lanes in input order after it. Runs of
+// one cell land in the order their atomics arrive, so the order inside a
+// cell may differ between runs of the program (the sums over a cell are
+// then added in another order, a difference at rounding level).
+__global__ void __launch_bounds__(kThreads) k_cell_scatter(int64_t n, const uint32_t* __restrict__ keys_in,
+                                                           int* __restrict__ cfill, uint32_t* __restrict__ keys_out,
+                                                           uint32_t* __restrict__ perm) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < n;
+  const uint32_t key = valid ? keys_in[i] : 0u;
+  int hl, len;
+  wave_runs(valid, key, lane, &hl, &len);
+  int base = 0;
+  if (valid && hl == lane) base = atomicAdd(&cfill[key], len);
+  base = __shfl(base, hl);
+  if (valid) {
+    const int dst = base + (lane - hl);
+    keys_out[dst] = key;
+    perm[dst] = (uint32_t)i;
   }
-  cs[c] = (int)lo;
 }
 
 template <typename R>
@@ -312,42 +295,17 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 }  // namespace
 
-static int key_bits(long long ncells) {
-  int bits = 1;
-  while ((1ll << bits) < ncells) ++bits;
-  return bits;
-}
+int cell_blocks(long long ncells) { return (int)((ncells + kCellTile - 1) / kCellTile); }
 
-int sort_passes(long long ncells) { return (key_bits(ncells) + 10) / 11; }
-
-static int digit_bits(long long ncells) {
-  const int bits = key_bits(ncells), passes = sort_passes(ncells);
-  return (bits + passes - 1) / passes;
-}
-
-int sort_blocks(int64_t n) { return (int)((n + kTile - 1) / kTile); }
-
-void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b,
+void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b, int2* desc,
                       uint32_t** keys, uint32_t** perm, hipStream_t st) {
-  const int passes = sort_passes(geo.ncells);
-  const int db = digit_bits(geo.ncells), nbins = 1 << db;
-  const int nb = sort_blocks(n);
-  const int64_t per_pass = (int64_t)nbins * nb;
-  k_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_a, b.vals_a, b.ghist, passes * nbins,
-                                             b.counter, b.counts, passes * per_pass);
-  uint32_t *ka = b.keys_a, *va = b.vals_a, *kb = b.keys_b, *vb = b.vals_b;
-  for (int p = 0; p < passes; ++p) {
-    int* gh = b.ghist + p * nbins;
-    int* cnt = b.counts + p * per_pass;
-    k_radix_count<<<nb, kThreads, 0, st>>>(n, ka, db * p, nbins, cnt, gh, nb);
-    k_radix_scan<<<nbins, kThreads, 0, st>>>(cnt, gh, nb);
-    k_radix_scatter<<<nb, kThreads, 0, st>>>(n, ka, va, kb, vb, db * p, db, cnt, nb);
-    uint32_t* tk = ka; ka = kb; kb = tk;
-    uint32_t* tv = va; va = vb; vb = tv;
-  }
-  k_cell_start<<<blocks_for(geo.ncells + 1), kThreads, 0, st>>>(n, ka, b.cell_start, geo.ncells);
-  *keys = ka;
-  *perm = va;
+  const int nbc = cell_blocks(geo.ncells);
+  k_cell_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_in, b.ccount);
+  k_cell_totals<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot);
+  k_cell_starts<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot, b.cell_start, b.cfill, desc, b.counter);
+  k_cell_scatter<<<blocks_for(n), kThreads, 0, st>>>(n, b.keys_in, b.cfill, b.keys, b.perm);
+  *keys = b.keys;
+  *perm = b.perm;
 }
 
 template <typename R>
