@@ -72,8 +72,8 @@ __global__ void __launch_bounds__(kThreads) k_cell_keys(int64_t n, const double*
   if (valid && hl == lane) atomicAdd(&ccount[key], len);
 }
 
-constexpr int kCellItems = 8;                        // cells per thread in the start scan
-constexpr int kCellTile = kThreads * kCellItems;     // 2048 cells per block
+constexpr int kCellItems = 2;                        // cells per thread in the start scan
+constexpr int kCellTile = kThreads * kCellItems;     // 512 cells per block
 
 // Particles and PP groups (runs of <= 16 of one cell) per block of cells.
 __global__ void __launch_bounds__(kThreads) k_cell_totals(const int* __restrict__ ccount, long long ncells,
