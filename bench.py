@@ -199,10 +199,10 @@ def main():
                 "frac": achieved / peak}
     else:
         # compulsory bytes per launch of the stage: the records each kernel must
-        # read and write once per particle, mesh node and kernel-table entry
+        # read and write once per particle, PP cell, mesh node and kernel-table entry
         per_stage = {
             "fft": 2 * fbytes * mesh_nodes + 8 * (wl.grid[0] + 1) * (wl.grid[1] + 1) * (wl.grid[2] + 1),
-            "sort": 3 * 16 * wl.n,
+            "sort": 40 * wl.n + 16 * ctx.info()["ncells"],
             "reorder": (4 + 4 + 24 + 2 * 4 * fbytes) * wl.n,
             "deposit": 8 * fbytes * wl.n + fbytes * mesh_nodes,
             "gather": (3 * 4 * fbytes + 4 + 2 * 24 + 24) * wl.n,
