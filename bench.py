@@ -59,11 +59,11 @@ def stage_sources():
     return {
         "pp": ["pp.hip", "erfcx_fit.h", "common.h"],
         "fft": ["fft.hip", "common.h"],
-        "sort": ["sort.hip", "pp.hip", "common.h"],
+        "sort": ["sort.hip", "common.h"],
         "deposit": ["mesh.hip", "common.h"],
-        "gather": ["mesh.hip", "common.h"],
+        "gather": ["mesh.hip", "bbox.h", "common.h"],
         "reorder": ["sort.hip", "common.h"],
-        "push+placement": ["placement.hip", "common.h"],
+        "push+placement": ["placement.hip", "bbox.h", "common.h"],
     }
 
 
@@ -205,8 +205,9 @@ def main():
             "sort": 40 * wl.n + 16 * ctx.info()["ncells"],
             "reorder": (4 + 4 + 24 + 2 * 4 * fbytes) * wl.n,
             "deposit": 8 * fbytes * wl.n + fbytes * mesh_nodes,
-            "gather": (3 * 4 * fbytes + 4 + 2 * 24 + 24) * wl.n,
-            "push+placement": 96 * wl.n,
+            # the gather also reads and writes x (the next step's drift, fused)
+            "gather": (3 * 4 * fbytes + 4 + 2 * 24 + 24 + 48) * wl.n,
+            "push+placement": 48 * ((wl.n + 255) // 256),   # the box partials
         }
         bytes_ = per_stage[stage]
         achieved = bytes_ / avg_s / 1e9

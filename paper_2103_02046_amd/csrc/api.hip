@@ -53,7 +53,8 @@ struct p3m_ctx {
   // placement, status, small scratch
   Place* place = nullptr;
   int* status = nullptr;
-  double* bbox_part = nullptr;
+  double* bbox_part = nullptr;  // [6][bbox_slots] bounding-box partials
+  int bbox_slots = 1024;
   double* acc = nullptr;        // 64 doubles of reduction scratch
   double* ghat = nullptr;
   // grounded plane: image table (rebuilt per evaluation), scratch, twiddles
@@ -215,6 +216,12 @@ p3m_status ensure_capacity(p3m_ctx* ctx, int64_t n) {
   HIPCHK(dalloc(&ctx->sb.perm, (size_t)n));
   HIPCHK(dalloc(&ctx->groups, (size_t)pp_group_bound(n, ctx->geo)));
   HIPCHK(dalloc(&ctx->fcache, (size_t)3 * n));
+  if (gather_blocks(n) > ctx->bbox_slots) {   // the gather's fused push writes one column per block
+    dfree(ctx->bbox_part);
+    ctx->bbox_slots = 0;
+    HIPCHK(dalloc(&ctx->bbox_part, (size_t)6 * gather_blocks(n)));
+    ctx->bbox_slots = gather_blocks(n);
+  }
   ctx->cap = n;
   return P3M_OK;
 }
@@ -541,9 +548,22 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
   // scatter at the end restores caller order. Placement (min/max) and the
   // fixed-point deposit do not depend on the order; the PP sums do only
   // through rounding.
+  // Every gather but the last of the call also applies the next step's
+  // kick and drift to the state it has just written, with the box partials
+  // of the new positions, so the step needs no separate push pass.
   if ((s = ensure_state(ctx, qw != nullptr)) != P3M_OK) return s;
+  const double inv_m = 1.0 / ctx->opts.m;
+  auto fuse_push = [&](GatherOut& o, double* xs, double* ps, double kick) {
+    o.p = ps;
+    o.half_dt = kick;
+    o.x = xs;
+    o.dt_over_m = dt * inv_m;
+    o.part = ctx->bbox_part;
+    o.status = ctx->status;
+  };
   int cur = 0;
   bool sorted = false;
+  bool pushed = false;   // the last gather applied the kick and drift of the step to come
   if (!reuse_force) {
     place(ctx, n, x, place_replay, place_record, st);
     Carry c;
@@ -553,10 +573,11 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
     c.id_out = ctx->ids[0];
     c.qw_out = ctx->qs[0];
     GatherOut out{ctx->fs, nullptr, nullptr, nullptr, 0.0, true};
+    if (nsteps > 0) fuse_push(out, ctx->xs[0], ctx->ps[0], 0.5 * dt);
     if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st, c)) != P3M_OK) return s;
     sorted = true;
+    pushed = nsteps > 0;
   }
-  const double inv_m = 1.0 / ctx->opts.m;
   const int nb = bbox_blocks(n);
   for (int k = 0; k < nsteps; ++k) {
     const size_t off = (size_t)P3M_PLACEMENT_DOUBLES * (k + 1);
@@ -565,10 +586,12 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
     const double* qk = sorted ? (qw ? ctx->qs[cur] : nullptr) : qw;
     {
       StageTimer t(ctx, 0, st);
-      launch_kick_drift_bbox(n, xk, pk, sorted ? ctx->fs : ctx->fcache, dt, inv_m, ctx->bbox_part, nb,
-                             ctx->status, st);
-      launch_place_finalize(nb, ctx->bbox_part, ctx->geo, place_replay ? place_replay + off : nullptr,
-                            ctx->place, place_record ? place_record + off : nullptr, ctx->status, st);
+      if (!pushed)
+        launch_kick_drift_bbox(n, xk, pk, sorted ? ctx->fs : ctx->fcache, dt, inv_m, ctx->bbox_part, nb,
+                               ctx->status, st);
+      launch_place_finalize(pushed ? gather_blocks(n) : nb, ctx->bbox_part, ctx->geo,
+                            place_replay ? place_replay + off : nullptr, ctx->place,
+                            place_record ? place_record + off : nullptr, ctx->status, st);
     }
     const int nxt = sorted ? 1 - cur : 0;
     Carry c;
@@ -579,6 +602,8 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
     c.id_out = ctx->ids[nxt];
     c.qw_out = ctx->qs[nxt];
     GatherOut out{ctx->fs, nullptr, nullptr, ctx->ps[nxt], 0.5 * dt, true};
+    pushed = k + 1 < nsteps;
+    if (pushed) fuse_push(out, ctx->xs[nxt], ctx->ps[nxt], dt);   // this step's half kick, the next one's
     if ((s = evaluate_any(ctx, n, xk, qk, out, nullptr, nullptr, st, c)) != P3M_OK) return s;
     cur = nxt;
     sorted = true;

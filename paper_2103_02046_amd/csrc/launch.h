@@ -74,7 +74,16 @@ struct GatherOut {
   double* p;        // momenta to kick by half_dt * f (may be NULL)
   double half_dt;
   bool sorted = false;   // all of the above in cell order instead of caller order
+  // Fused push (with p): after the kick, x += dt_over_m p, and the block
+  // partials of the new bounding box go to part ([6][gather_blocks(n)]);
+  // a non-finite position sets the status bit. NULL x: no drift.
+  double* x = nullptr;
+  double dt_over_m = 0.0;
+  double* part = nullptr;
+  int* status = nullptr;
 };
+// Blocks of the gather launch (the column count of its box partials).
+int gather_blocks(int64_t n);
 template <typename R, typename M>
 void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,
                    const uint32_t* perm, const Geo& geo, const Place* pl, const M* phi,

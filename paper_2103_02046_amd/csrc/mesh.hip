@@ -14,6 +14,7 @@
 // Lengths are in the unit Lu = s r_c, so grad = (1/hu_d) d/du with hu = h/r_c.
 #include <climits>
 
+#include "bbox.h"
 #include "launch.h"
 
 namespace p3m {
@@ -244,6 +245,8 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
                                                      double* __restrict__ energy) {
   const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   double e_acc = 0.0;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
   if (j < n) {
     const MeshRec<R> m = mesh[j];
     const R q = rec_w(pp[j], geo);
@@ -318,9 +321,26 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
       for (int d = 0; d < 3; ++d) out.f_pp[3 * i + d] = fs * fp[d];
     if (out.f_pm)
       for (int d = 0; d < 3; ++d) out.f_pm[3 * i + d] = fs * fpm[d];
-    if (out.p)
-      for (int d = 0; d < 3; ++d) out.p[3 * i + d] += out.half_dt * ft[d];
+    if (out.p) {
+      if (out.x) {
+        // the next step's kick and drift (leapfrog, Sec. 2.4.3 eq. leapfrog)
+        double xi[3];
+        for (int d = 0; d < 3; ++d) {
+          const double pd = out.p[3 * i + d] + out.half_dt * ft[d];
+          out.p[3 * i + d] = pd;
+          xi[d] = out.x[3 * i + d] + out.dt_over_m * pd;
+          out.x[3 * i + d] = xi[d];
+        }
+        bbox_accumulate(xi, lo, hi, bad);
+      } else {
+        for (int d = 0; d < 3; ++d) out.p[3 * i + d] += out.half_dt * ft[d];
+      }
+    }
     e_acc = 0.5 * (double)q * (double)pot;
+  }
+  if (out.x) {   // uniform: every thread of the block reduces the box
+    if (bad) atomicOr(out.status, kBitNonFinite);
+    bbox_block_store(lo, hi, out.part, (int)gridDim.x);
   }
   if (energy) {
     __shared__ double s[kThreads];
@@ -433,6 +453,8 @@ void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const
   else
     k_deposit<R, M, 2><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, Q);
 }
+
+int gather_blocks(int64_t n) { return (int)blocks_for(n); }
 
 template <typename R, typename M>
 void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const PPRec<R>* fpp,

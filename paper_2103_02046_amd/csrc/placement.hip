@@ -9,6 +9,7 @@
 //
 // Push: kick-drift-kick leapfrog, the variational integrator of
 // Sec. 2.4.3 (eq. leapfrog) applied to the P3M Lagrangian (Sec. 2.5).
+#include "bbox.h"
 #include "launch.h"
 
 namespace p3m {
@@ -17,40 +18,15 @@ namespace {
 
 constexpr int kBboxItems = 4;
 
-__device__ inline void block_minmax(double (&lo)[3], double (&hi)[3], double* part, int nblk) {
-  __shared__ double s[6][kThreads];
-  const int t = threadIdx.x;
-  for (int d = 0; d < 3; ++d) { s[d][t] = lo[d]; s[3 + d][t] = hi[d]; }
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (t < w)
-      for (int d = 0; d < 3; ++d) {
-        s[d][t] = fmin(s[d][t], s[d][t + w]);
-        s[3 + d][t] = fmax(s[3 + d][t], s[3 + d][t + w]);
-      }
-    __syncthreads();
-  }
-  if (t < 6) part[t * nblk + blockIdx.x] = s[t][0];
-}
-
-__device__ inline void accumulate(const double* xi, double (&lo)[3], double (&hi)[3], int& bad) {
-  for (int d = 0; d < 3; ++d) {
-    double v = xi[d];
-    if (!isfinite(v)) { bad = 1; continue; }
-    lo[d] = fmin(lo[d], v);
-    hi[d] = fmax(hi[d], v);
-  }
-}
-
 __global__ void __launch_bounds__(kThreads) k_bbox(int64_t n, const double* __restrict__ x,
                                                    double* __restrict__ part, int nblk,
                                                    int* __restrict__ status) {
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   int bad = 0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)nblk * kThreads)
-    accumulate(x + 3 * i, lo, hi, bad);
+    bbox_accumulate(x + 3 * i, lo, hi, bad);
   if (bad) atomicOr(status, kBitNonFinite);
-  block_minmax(lo, hi, part, nblk);
+  bbox_block_store(lo, hi, part, nblk);
 }
 
 __global__ void __launch_bounds__(kThreads) k_kick_drift_bbox(
@@ -66,10 +42,10 @@ __global__ void __launch_bounds__(kThreads) k_kick_drift_bbox(
       xi[d] = x[3 * i + d] + dt_over_m * pd;
       x[3 * i + d] = xi[d];
     }
-    accumulate(xi, lo, hi, bad);
+    bbox_accumulate(xi, lo, hi, bad);
   }
   if (bad) atomicOr(status, kBitNonFinite);
-  block_minmax(lo, hi, part, nblk);
+  bbox_block_store(lo, hi, part, nblk);
 }
 
 __global__ void k_kick(int64_t n, double* __restrict__ p, const double* __restrict__ f, double half_dt) {
@@ -77,29 +53,53 @@ __global__ void k_kick(int64_t n, double* __restrict__ p, const double* __restri
   if (i < 3 * n) p[i] += half_dt * f[i];
 }
 
-__global__ void __launch_bounds__(kThreads) k_place_finalize(int nblk, const double* __restrict__ part,
-                                                             Geo geo, const double* __restrict__ place_in,
-                                                             Place* __restrict__ out,
-                                                             double* __restrict__ place_out,
-                                                             int* __restrict__ status) {
-  __shared__ double s[6][kThreads];
-  const int t = threadIdx.x;
+// One block of kFinThreads reduces the [6][nblk] box partials. Each thread
+// issues the loads of up to kFinItems columns before it reduces them, so
+// the few thousand partials of a gather-sized grid take one round trip per
+// batch rather than one per column.
+constexpr int kFinThreads = 1024;
+constexpr int kFinItems = 4;
+
+__global__ void __launch_bounds__(kFinThreads) k_place_finalize(int nblk, const double* __restrict__ part,
+                                                                Geo geo, const double* __restrict__ place_in,
+                                                                Place* __restrict__ out,
+                                                                double* __restrict__ place_out,
+                                                                int* __restrict__ status) {
+  __shared__ double s[6][kFinThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = t; b < nblk; b += kThreads)
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = fmin(lo[d], part[d * nblk + b]);
-      hi[d] = fmax(hi[d], part[(3 + d) * nblk + b]);
+  for (int b0 = 0; b0 < nblk; b0 += kFinItems * kFinThreads) {
+    double v[kFinItems][6];
+#pragma unroll
+    for (int k = 0; k < kFinItems; ++k) {
+      const int b = b0 + k * kFinThreads + t;
+#pragma unroll
+      for (int d = 0; d < 6; ++d) v[k][d] = b < nblk ? part[d * nblk + b] : (d < 3 ? INFINITY : -INFINITY);
     }
-  for (int d = 0; d < 3; ++d) { s[d][t] = lo[d]; s[3 + d][t] = hi[d]; }
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (t < w)
+#pragma unroll
+    for (int k = 0; k < kFinItems; ++k)
       for (int d = 0; d < 3; ++d) {
-        s[d][t] = fmin(s[d][t], s[d][t + w]);
-        s[3 + d][t] = fmax(s[3 + d][t], s[3 + d][t + w]);
+        lo[d] = fmin(lo[d], v[k][d]);
+        hi[d] = fmax(hi[d], v[k][3 + d]);
       }
-    __syncthreads();
   }
+  for (int d = 0; d < 3; ++d) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[d] = fmin(lo[d], __shfl_xor(lo[d], off));
+      hi[d] = fmax(hi[d], __shfl_xor(hi[d], off));
+    }
+    if (lane == 0) {
+      s[d][w] = lo[d];
+      s[3 + d][w] = hi[d];
+    }
+  }
+  __syncthreads();
+  if (t < 6) {
+    double r = s[t][0];
+    for (int k = 1; k < kFinThreads / 64; ++k) r = t < 3 ? fmin(r, s[t][k]) : fmax(r, s[t][k]);
+    s[t][0] = r;
+  }
+  __syncthreads();
   if (t != 0) return;
   double x0[3], zoom;
   if (place_in) {
@@ -176,7 +176,7 @@ void launch_kick(int64_t n, double* p, const double* f, double dt, hipStream_t s
 
 void launch_place_finalize(int nblk, const double* part, const Geo& geo, const double* place_in,
                            Place* out, double* place_out, int* status, hipStream_t st) {
-  k_place_finalize<<<1, kThreads, 0, st>>>(nblk, part, geo, place_in, out, place_out, status);
+  k_place_finalize<<<1, kFinThreads, 0, st>>>(nblk, part, geo, place_in, out, place_out, status);
 }
 
 }  // namespace p3m
