@@ -548,17 +548,22 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
   // scatter at the end restores caller order. Placement (min/max) and the
   // fixed-point deposit do not depend on the order; the PP sums do only
   // through rounding.
-  // Every gather but the last of the call also applies the next step's
-  // kick and drift to the state it has just written, with the box partials
-  // of the new positions, so the step needs no separate push pass.
+  // Every gather moves x and p into its evaluation's order (read through
+  // the permutation from the previous order) with the closing kick; every
+  // gather but the last of the call also applies the next step's kick and
+  // drift and stores the box partials of the new positions, so the step
+  // needs no separate push pass. The reorder carries the caller indices and
+  // weights.
   if ((s = ensure_state(ctx, qw != nullptr)) != P3M_OK) return s;
   const double inv_m = 1.0 / ctx->opts.m;
-  auto fuse_push = [&](GatherOut& o, double* xs, double* ps, double kick) {
-    o.p = ps;
+  auto move_state = [&](GatherOut& o, const double* x_src, const double* p_src, int to, double kick, bool push) {
+    o.p = ctx->ps[to];
+    o.p_src = p_src;
+    o.x = ctx->xs[to];
+    o.x_src = x_src;
     o.half_dt = kick;
-    o.x = xs;
     o.dt_over_m = dt * inv_m;
-    o.part = ctx->bbox_part;
+    o.part = push ? ctx->bbox_part : nullptr;
     o.status = ctx->status;
   };
   int cur = 0;
@@ -567,16 +572,13 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
   if (!reuse_force) {
     place(ctx, n, x, place_replay, place_record, st);
     Carry c;
-    c.x_out = ctx->xs[0];
-    c.p_in = p;
-    c.p_out = ctx->ps[0];
     c.id_out = ctx->ids[0];
     c.qw_out = ctx->qs[0];
     GatherOut out{ctx->fs, nullptr, nullptr, nullptr, 0.0, true};
-    if (nsteps > 0) fuse_push(out, ctx->xs[0], ctx->ps[0], 0.5 * dt);
+    pushed = nsteps > 0;
+    move_state(out, x, p, 0, pushed ? 0.5 * dt : 0.0, pushed);
     if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st, c)) != P3M_OK) return s;
     sorted = true;
-    pushed = nsteps > 0;
   }
   const int nb = bbox_blocks(n);
   for (int k = 0; k < nsteps; ++k) {
@@ -595,15 +597,13 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
     }
     const int nxt = sorted ? 1 - cur : 0;
     Carry c;
-    c.x_out = ctx->xs[nxt];
-    c.p_in = pk;
-    c.p_out = ctx->ps[nxt];
     c.id_in = sorted ? ctx->ids[cur] : nullptr;
     c.id_out = ctx->ids[nxt];
     c.qw_out = ctx->qs[nxt];
-    GatherOut out{ctx->fs, nullptr, nullptr, ctx->ps[nxt], 0.5 * dt, true};
+    GatherOut out{ctx->fs, nullptr, nullptr, nullptr, 0.0, true};
     pushed = k + 1 < nsteps;
-    if (pushed) fuse_push(out, ctx->xs[nxt], ctx->ps[nxt], dt);   // this step's half kick, the next one's
+    // this step's closing half kick, and the next step's half kick when fused
+    move_state(out, xk, pk, nxt, pushed ? dt : 0.5 * dt, pushed);
     if ((s = evaluate_any(ctx, n, xk, qk, out, nullptr, nullptr, st, c)) != P3M_OK) return s;
     cur = nxt;
     sorted = true;

@@ -29,8 +29,9 @@ int cell_blocks(long long ncells);
 // key and input index arrays.
 void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b, int2* desc,
                       uint32_t** keys, uint32_t** perm, hipStream_t st);
-// Stepping in cell order: the reorder also moves the particle state into the
-// new order (x_out NULL: nothing is moved).
+// Stepping in cell order: the reorder can also move the particle state into
+// the new order (x_out NULL: x and p are not moved; id_out NULL: neither are
+// the caller indices and weights).
 struct Carry {
   double* x_out = nullptr;           // x[perm[j]]
   const double* p_in = nullptr;      // momenta, in the order of x
@@ -74,9 +75,13 @@ struct GatherOut {
   double* p;        // momenta to kick by half_dt * f (may be NULL)
   double half_dt;
   bool sorted = false;   // all of the above in cell order instead of caller order
-  // Fused push (with p): after the kick, x += dt_over_m p, and the block
-  // partials of the new bounding box go to part ([6][gather_blocks(n)]);
-  // a non-finite position sets the status bit. NULL x: no drift.
+  // State moved into the sorted order (sorted outputs only): with p_src, p
+  // = p_src[perm[j]] + half_dt f, and x (when given) = x_src[perm[j]] (x
+  // in place when x_src is NULL). Fused push (part given): x also drifts by
+  // dt_over_m p, and the block partials of the new bounding box go to part
+  // ([6][gather_blocks(n)]); a non-finite position sets the status bit.
+  const double* p_src = nullptr;
+  const double* x_src = nullptr;
   double* x = nullptr;
   double dt_over_m = 0.0;
   double* part = nullptr;

@@ -322,23 +322,30 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
     if (out.f_pm)
       for (int d = 0; d < 3; ++d) out.f_pm[3 * i + d] = fs * fpm[d];
     if (out.p) {
+      // the kick(s) and, fused, the next step's drift (leapfrog, Sec. 2.4.3
+      // eq. leapfrog), moving the state into this order on the way
+      const uint32_t src = out.p_src ? perm[j] : i;
+      const double* ps = out.p_src ? out.p_src : out.p;
+      double pd[3];
+      for (int d = 0; d < 3; ++d) {
+        pd[d] = ps[3 * src + d] + out.half_dt * ft[d];
+        out.p[3 * i + d] = pd[d];
+      }
       if (out.x) {
-        // the next step's kick and drift (leapfrog, Sec. 2.4.3 eq. leapfrog)
+        const double* xs = out.x_src ? out.x_src : out.x;
+        const uint32_t xsrc = out.x_src ? perm[j] : i;
+        const double drift = out.part ? out.dt_over_m : 0.0;
         double xi[3];
         for (int d = 0; d < 3; ++d) {
-          const double pd = out.p[3 * i + d] + out.half_dt * ft[d];
-          out.p[3 * i + d] = pd;
-          xi[d] = out.x[3 * i + d] + out.dt_over_m * pd;
+          xi[d] = xs[3 * xsrc + d] + drift * pd[d];
           out.x[3 * i + d] = xi[d];
         }
-        bbox_accumulate(xi, lo, hi, bad);
-      } else {
-        for (int d = 0; d < 3; ++d) out.p[3 * i + d] += out.half_dt * ft[d];
+        if (out.part) bbox_accumulate(xi, lo, hi, bad);
       }
     }
     e_acc = 0.5 * (double)q * (double)pot;
   }
-  if (out.x) {   // uniform: every thread of the block reduces the box
+  if (out.part) {   // uniform: every thread of the block reduces the box
     if (bad) atomicOr(out.status, kBitNonFinite);
     bbox_block_store(lo, hi, out.part, (int)gridDim.x);
   }

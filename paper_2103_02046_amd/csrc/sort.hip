@@ -226,6 +226,8 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
   if (carry.x_out) {
     for (int d = 0; d < 3; ++d) carry.x_out[3 * j + d] = xi[d];
     for (int d = 0; d < 3; ++d) carry.p_out[3 * j + d] = carry.p_in[3 * i + d];
+  }
+  if (carry.id_out) {
     carry.id_out[j] = carry.id_in ? carry.id_in[i] : i;
     if (qw) carry.qw_out[j] = w;
   }
