@@ -1,8 +1,9 @@
 // C ABI of libp3m: context, device buffers and the order of the kernels of
 // one P3M force evaluation, leapfrog step and adjoint step.
 //
-//   placement (bbox) -> cell keys -> radix sort -> cell starts -> reorder
-//   -> PP pair forces  -> deposit -> FFT convolution -> gather (+ push)
+//   placement (bbox) -> cell keys -> counting sort by cell (cell starts and
+//   PP work groups) -> reorder -> PP pair forces -> deposit -> FFT
+//   convolution -> gather (+ kick, state move and the next drift)
 //
 // Everything is enqueued on the caller's stream; the host never waits for
 // the device inside p3m_forces / p3m_step / p3m_hvp / p3m_backward.
