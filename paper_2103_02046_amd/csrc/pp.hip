@@ -136,6 +136,15 @@ constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
 //      cell-local positions plus cell-corner offsets (exact multiples of the
 //      cell edge). The tile sum is added to the per-particle total with
 //      Kahan compensation (float form).
+// The pair kernel runs one wave per work-group, so its syncs order only
+// that wave's LDS accesses: LDS operations of a wave complete in order, and
+// fences against compiler motion suffice (no s_barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R, bool ENERGY, bool PACKED>
 __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter,
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
@@ -198,7 +207,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   if (ql < 9) rpre[q][ql + 1] = inc;
   if (ql == 0) rpre[q][0] = 0;
   if (ql == 8) gtot[q] = inc;
-  __syncthreads();
+  wave_sync();
   // the target of this lane
   const bool active = gvalid && ql < gd.y;
   R lx = 0, ly = 0, lz = 0, tw = 0;
@@ -312,7 +321,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       }
       tile[TS * q + 16 * h + ql] = c;
     }
-    __syncthreads();
+    wave_sync();
     fetch(t + 1);
     // 2. hit masks (group-relative positions). The sign bit of r2 - lim is
     //    shifted into the mask (alignbit: m = (m << 1) | (bits >> 31)), so
@@ -388,7 +397,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       }
     }
     acc.add(sx, sy, sz);
-    __syncthreads();
+    wave_sync();
   }
   if (active) {
     const R unit = kFix ? fu : (R)1;
