@@ -118,6 +118,14 @@ constexpr float kCloseUnits2 = 70368744177664.0f;   // (2^23 units)^2: beyond, r
 __host__ __device__ inline float rec_w(const PPFix& r, const Geo& g) { return g.wpacked ? 1.0f : r.w; }
 template <typename R>
 __host__ __device__ inline R rec_w(const PPRec<R>& r, const Geo&) { return r.w; }
+// Weight of sorted particle j read from its record only when the records
+// carry weights (a uniform branch: residual-carrying records are not read).
+__device__ __forceinline__ float rec_weight(const PPFix* pp, int64_t j, const Geo& g) {
+  if (g.wpacked) return 1.0f;
+  return pp[j].w;
+}
+template <typename R>
+__device__ __forceinline__ R rec_weight(const PPRec<R>* pp, int64_t j, const Geo&) { return pp[j].w; }
 // Residual field f (0..2) of a packed weight slot, sign-extended. The bit
 // field builtin is typed unsigned; the cast keeps the field difference signed.
 __device__ __forceinline__ int res_field(int v, int f) {

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
     if (j < n) {
       int b[3];
       unpack_base(mesh[j], nx, nxy, b);
-      qmax = fmax(qmax, fabs((double)rec_w(pp[j], geo)));
+      qmax = fmax(qmax, fabs((double)rec_weight(pp, j, geo)));
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         lo[d] = min(lo[d], b[d]);
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
           const int64_t j = j0 + it * kDepThreads + t;
           if (j >= n) continue;
           const MeshRec<R> m = mesh[j];
-          const R q = rec_w(pp[j], geo);
+          const R q = rec_weight(pp, j, geo);
           int b[3];
           unpack_base(m, nx, nxy, b);
           const int rx = b[0] - o0, ry = b[1] - o1 - py, rz = b[2] - o2 - pz;
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
       const int64_t j = j0 + it * kDepThreads + t;
       if (j >= n) continue;
       const MeshRec<R> m = mesh[j];
-      const R q = rec_w(pp[j], geo);
+      const R q = rec_weight(pp, j, geo);
       int b[3];
       unpack_base(m, nx, nxy, b);
       const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
   int bad = 0;
   if (j < n) {
     const MeshRec<R> m = mesh[j];
-    const R q = rec_w(pp[j], geo);
+    const R q = rec_weight(pp, j, geo);
     Stencil<M, ORDER> S((M)m.fx, (M)m.fy, (M)m.fz);
     const int nx = geo.grid[0];
     const long long nxy = (long long)nx * geo.grid[1];
