@@ -344,16 +344,16 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     }
     if (!active) m0 = m1 = 0u;
     // 3. own hits (the particle itself and coincident ones give r2 = 0).
-    //    As one 64-bit word (m0 high), bit b is candidate 63 - b, so the
-    //    count of leading zeros is the candidate index; the highest set bit
-    //    is taken and cleared each round. Float form: separations
-    //    in fixed-point units, the unit applied to r2 here and to the sums
-    //    at the end.
+    //    The masks hold candidate k of a half-tile at bit 31 - k; reversed
+    //    once per tile into one 64-bit word, bit k is candidate k, and the
+    //    lowest set bit is taken and cleared each round. Float form:
+    //    separations in fixed-point units, the unit applied to r2 here and
+    //    to the sums at the end.
     R sx = 0, sy = 0, sz = 0;
-    uint64_t hm = ((uint64_t)m0 << 32) | m1;
+    uint64_t hm = ((uint64_t)__builtin_bitreverse32(m1) << 32) | __builtin_bitreverse32(m0);
     while (hm) {
-      const int k = (int)__builtin_clzll(hm);   // the highest set bit, 63 - k
-      hm ^= 0x8000000000000000ull >> k;
+      const int k = (int)__builtin_ctzll(hm);
+      hm &= hm - 1;
       R dx, dy, dz, wj, r2;
       if constexpr (kFix) {
         const int4 cf = tfix[TS * q + k];
