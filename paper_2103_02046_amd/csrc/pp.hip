@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
   const R cux = (R)geo.cu[0], cuy = (R)geo.cu[1], cuz = (R)geo.cu[2];
   const int kex = fix_edge(geo.cu, 0), key_ = fix_edge(geo.cu, 1), kez = fix_edge(geo.cu, 2);
-  const R fu = (R)fix_unit(geo.cu), fu2 = fu * fu;
+  const R fu = (R)fix_unit(geo.cu);
   int cx0 = 0, cy = 0, cz = 0;
   if (gvalid) {
     const uint32_t k0 = keys[gd.x];
@@ -281,11 +281,18 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     }
   };
   fetch(0);
+  // Float form: the pair function takes r^2 in fixed-point units squared,
+  // its constants scaled by the unit u (kappa u, 2 kappa u / sqrt(pi),
+  // -kappa^2 u^2 log2 e), so no hit multiplies by u^2. Its value is then
+  // g / u^3, and the sums are scaled back once per particle (1 / u^2 for
+  // the force, whose separations are in units; 1 / u for the potential).
+  const double fud = kFix ? fix_unit(geo.cu) : 1.0;
   PairK<R> pk;
-  pk.kappa = (R)geo.kappa;
-  pk.c2k = (R)(kTwoOverSqrtPi * geo.kappa);
-  pk.half_kappa = (R)(0.5 * geo.kappa);
-  pk.ek = (R)(-geo.kappa * geo.kappa * 1.44269504088896340736);
+  pk.kappa = (R)(geo.kappa * fud);
+  pk.c2k = (R)(kTwoOverSqrtPi * geo.kappa * fud);
+  pk.half_kappa = (R)(0.5 * geo.kappa * fud);
+  pk.ek = (R)(-geo.kappa * geo.kappa * fud * fud * 1.44269504088896340736);
+  const R rlim = (R)(1.0 / (fud * fud));   // the cutoff, in the units of r2
   Acc3<R> acc;
   double e_acc = 0.0;
   int pairs = 0;
@@ -347,8 +354,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     //    The masks hold candidate k of a half-tile at bit 31 - k; reversed
     //    once per tile into one 64-bit word, bit k is candidate k, and the
     //    lowest set bit is taken and cleared each round. Float form:
-    //    separations in fixed-point units, the unit applied to r2 here and
-    //    to the sums at the end.
+    //    separations and r2 in fixed-point units (the pair constants carry
+    //    the unit), scaled back in the sums at the end.
     R sx = 0, sy = 0, sz = 0;
     uint64_t hm = ((uint64_t)__builtin_bitreverse32(m1) << 32) | __builtin_bitreverse32(m0);
     while (hm) {
@@ -374,7 +381,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         } else {
           wj = __int_as_float(cf.w);
         }
-        r2 = d2 * fu2;
+        r2 = d2;
       } else {
         const V4 cl = tloc[TS * q + k];
         const V4 co = toff[TS * q + k];
@@ -384,7 +391,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         wj = cl.w;
         r2 = dx * dx + dy * dy + dz * dz;
       }
-      if (r2 > (R)0 && r2 < (R)1) {
+      if (r2 > (R)0 && r2 < rlim) {
         R ep;
         const R g = pair_scalar(r2, wj, pk, ENERGY ? &ep : nullptr);
         sx += g * dx;
@@ -400,7 +407,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     wave_sync();
   }
   if (active) {
-    const R unit = kFix ? fu : (R)1;
+    const R unit = (R)(1.0 / (fud * fud));   // separations in units: g u^-3 times d u
     PPRec<R> f;
     f.x = acc.get(0) * (tw * unit);
     f.y = acc.get(1) * (tw * unit);
@@ -409,7 +416,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     out[gd.x + ql] = f;
   }
   if (ENERGY) {
-    e_acc *= 0.5 * (double)tw;   // each unordered pair is met twice
+    e_acc *= 0.5 * (double)tw / fud;   // each unordered pair is met twice
     for (int off = 32; off > 0; off >>= 1) {
       e_acc += __shfl_xor(e_acc, off);
       pairs += __shfl_xor(pairs, off);
