@@ -447,7 +447,8 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
       dalloc(&ctx->bbox_part, 6 * 1024) != hipSuccess || dalloc(&ctx->acc, 64) != hipSuccess ||
       dalloc(&ctx->sb.counter, 2) != hipSuccess || dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess ||
       dalloc(&ctx->sb.ccount, (size_t)g.ncells) != hipSuccess || dalloc(&ctx->sb.cfill, (size_t)g.ncells) != hipSuccess ||
-      dalloc(&ctx->sb.btot, (size_t)2 * cell_blocks(g.ncells)) != hipSuccess)
+      dalloc(&ctx->sb.btot, (size_t)2 * cell_blocks(g.ncells)) != hipSuccess ||
+      dalloc(&ctx->sb.stot, (size_t)2 * cell_supers(g.ncells)) != hipSuccess)
     return bail(P3M_ENOMEM);
   // the per-cell counts start at zero; each sort leaves them at zero
   if (hipMemset(ctx->sb.ccount, 0, (size_t)g.ncells * sizeof(int)) != hipSuccess) return bail(P3M_EHIP);
@@ -789,6 +790,7 @@ void p3m_destroy(p3m_ctx* ctx) {
   dfree(ctx->sb.ccount);
   dfree(ctx->sb.cfill);
   dfree(ctx->sb.btot);
+  dfree(ctx->sb.stot);
   dfree(ctx->sb.counter);
   dfree(ctx->groups);
   dfree(ctx->sb.cell_start);

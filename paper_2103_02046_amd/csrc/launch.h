@@ -20,10 +20,12 @@ struct SortBufs {
   int* ccount;      // [ncells] particles per cell, zero between sorts
   int* cfill;       // [ncells] the scatter's fill pointers
   int* btot;        // [2 cell_blocks] particles and groups per block of cells
+  int* stot;        // [2 cell_supers] their sums per super-block
   int* cell_start;  // [ncells + 1]
   int* counter;     // [0] PP groups built
 };
 int cell_blocks(long long ncells);
+int cell_supers(long long ncells);
 // Counting sort of the particles by PP cell: keys, cell starts and the PP
 // work groups (desc, counter[0]); on return *keys/*perm point at the sorted
 // key and input index arrays.

@@ -52,9 +52,13 @@ __device__ __forceinline__ void wave_runs(bool valid, uint32_t key, int lane, in
 
 // Cell key of every particle, in the input order, and the number of
 // particles per cell (ccount starts at zero; the start kernel re-zeroes it).
+// Block 0 also clears the super-block totals of the start prefix.
 __global__ void __launch_bounds__(kThreads) k_cell_keys(int64_t n, const double* __restrict__ x,
                                                         const Place* __restrict__ pl, Geo geo,
-                                                        uint32_t* __restrict__ keys, int* __restrict__ ccount) {
+                                                        uint32_t* __restrict__ keys, int* __restrict__ ccount,
+                                                        int* __restrict__ stot, int nstot) {
+  if (blockIdx.x == 0)
+    for (int e = threadIdx.x; e < nstot; e += kThreads) stot[e] = 0;
   const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = i < n;
@@ -74,10 +78,15 @@ __global__ void __launch_bounds__(kThreads) k_cell_keys(int64_t n, const double*
 
 constexpr int kCellItems = 2;                        // cells per thread in the start scan
 constexpr int kCellTile = kThreads * kCellItems;     // 512 cells per block
+constexpr int kSuper = 64;                           // blocks per super-block of the start prefix
+constexpr int kDirectPrefix = 2048;                  // above this many blocks, super-block totals
 
-// Particles and PP groups (runs of <= 16 of one cell) per block of cells.
+// Particles and PP groups (runs of <= 16 of one cell) per block of cells,
+// and on large grids their sums per super-block of kSuper blocks (stot,
+// cleared by the key kernel).
 __global__ void __launch_bounds__(kThreads) k_cell_totals(const int* __restrict__ ccount, long long ncells,
-                                                          int* __restrict__ btot) {
+                                                          int* __restrict__ btot, int* __restrict__ stot,
+                                                          bool super_prefix) {
   const long long c0 = blockIdx.x * (long long)kCellTile + (long long)threadIdx.x * kCellItems;
   int s = 0, gs = 0;
 #pragma unroll
@@ -94,21 +103,35 @@ __global__ void __launch_bounds__(kThreads) k_cell_totals(const int* __restrict_
   if (threadIdx.x == 0) {
     btot[2 * blockIdx.x] = tot_s;
     btot[2 * blockIdx.x + 1] = tot_g;
+    if (super_prefix) {
+      atomicAdd(&stot[2 * (blockIdx.x / kSuper)], tot_s);
+      atomicAdd(&stot[2 * (blockIdx.x / kSuper) + 1], tot_g);
+    }
   }
 }
 
 // Cell starts (exclusive prefix of the counts), the scatter's fill pointers,
-// and the PP work groups in cell order. Each block sums the totals of the
-// blocks before it; ccount is cleared for the next sort; the last block
-// stores cell_start[ncells] and the number of groups (counter[0]).
+// and the PP work groups in cell order. A block's offset is the sum of the
+// block totals before it. Up to kDirectPrefix blocks each block adds them
+// all; above, it adds the super-block totals before its super-block and the
+// block totals before it inside its super-block (at most kSuper - 1), so the
+// work stays linear in the number of blocks. ccount is cleared for the next
+// sort; the last block stores cell_start[ncells] and the number of groups
+// (counter[0]).
 __global__ void __launch_bounds__(kThreads) k_cell_starts(int* __restrict__ ccount, long long ncells,
                                                           const int* __restrict__ btot,
+                                                          const int* __restrict__ stot, bool super_prefix,
                                                           int* __restrict__ cell_start, int* __restrict__ cfill,
                                                           int2* __restrict__ desc, int* __restrict__ counter) {
   __shared__ int red[2][kWaves];
   const int t = threadIdx.x;
+  const int sb = super_prefix ? (int)blockIdx.x / kSuper : 0, first = sb * kSuper;
   int ps = 0, pg = 0;
-  for (int q = t; q < (int)blockIdx.x; q += kThreads) {
+  for (int q = t; q < sb; q += kThreads) {
+    ps += stot[2 * q];
+    pg += stot[2 * q + 1];
+  }
+  for (int q = first + t; q < (int)blockIdx.x; q += kThreads) {
     ps += btot[2 * q];
     pg += btot[2 * q + 1];
   }
@@ -299,12 +322,17 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / k
 
 int cell_blocks(long long ncells) { return (int)((ncells + kCellTile - 1) / kCellTile); }
 
+int cell_supers(long long ncells) { return (cell_blocks(ncells) + kSuper - 1) / kSuper; }
+
 void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b, int2* desc,
                       uint32_t** keys, uint32_t** perm, hipStream_t st) {
   const int nbc = cell_blocks(geo.ncells);
-  k_cell_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_in, b.ccount);
-  k_cell_totals<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot);
-  k_cell_starts<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot, b.cell_start, b.cfill, desc, b.counter);
+  const bool sup = nbc > kDirectPrefix;
+  k_cell_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_in, b.ccount, b.stot,
+                                                  sup ? 2 * cell_supers(geo.ncells) : 0);
+  k_cell_totals<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot, b.stot, sup);
+  k_cell_starts<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot, b.stot, sup, b.cell_start, b.cfill,
+                                          desc, b.counter);
   k_cell_scatter<<<blocks_for(n), kThreads, 0, st>>>(n, b.keys_in, b.cfill, b.keys, b.perm);
   *keys = b.keys;
   *perm = b.perm;
