@@ -196,8 +196,10 @@ p3m_status p3m_forces_ex(p3m_ctx *ctx, int64_t n, const double *x, const double 
  * If place_replay (device) is not NULL it holds (nsteps+1) placement
  * records used instead of the bounding-box placement: record 0 for the start
  * position, record k for the end of step k (a recorded run replayed exactly).
+ * With reuse_force, record 0 is not read (the cached force stands for it).
  * If place_record (device) is not NULL it receives the (nsteps+1) placements
- * used, in the same order.
+ * used, in the same order; it needs a fresh start force (P3M_EINVAL with
+ * reuse_force).
  * Errors: as p3m_forces; P3M_ESTATE if reuse_force is asked with no cache.
  */
 p3m_status p3m_step(p3m_ctx *ctx, int64_t n, double *x, double *p, const double *qw,

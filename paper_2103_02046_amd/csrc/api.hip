@@ -540,8 +540,9 @@ p3m_status p3m_step(p3m_ctx* ctx, int64_t n, double* x, double* p, const double*
   if (reuse_force) {
     if (!ctx->force_cached || ctx->cached_x != x || ctx->cached_n != n)
       return fail(ctx, P3M_ESTATE, "no cached force for these positions");
-    if (place_record || place_replay)
-      return fail(ctx, P3M_EINVAL, "placement record/replay needs a fresh start force");
+    // a replay skips record 0 (the cached force stands for it); a record
+    // would leave record 0 unwritten
+    if (place_record) return fail(ctx, P3M_EINVAL, "placement record needs a fresh start force");
   }
   // The state is stepped in the cell order of the latest force evaluation:
   // each reorder moves x, p, the caller indices and the weights into the new

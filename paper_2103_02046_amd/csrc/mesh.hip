@@ -95,10 +95,14 @@ __device__ __forceinline__ void unpack_base(const MeshRec<R>& m, int nx, unsigne
   b[2] = (int)bz;
 }
 
-template <typename R, typename M, int ORDER>
+// GRAD: the derivative of the deposit along v (sorted [n][3], float64),
+// R_m = sum_j w_j grad W_m(x_j) . v_j, in place of the charge. Its values
+// are bounded by |w_j| sum_d |v_jd| / (h_d / r_c) (|W| <= 1, |W'| <= 1),
+// which takes the place of |w_j| in the fixed-point unit.
+template <typename R, typename M, int ORDER, bool GRAD>
 __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<R>* __restrict__ pp,
                                                       const MeshRec<R>* __restrict__ mesh, Geo geo,
-                                                      M* __restrict__ Q) {
+                                                      const double* __restrict__ v, M* __restrict__ Q) {
   constexpr int NS = ORDER + 1;
   __shared__ long long tile[kTileNodes];
   __shared__ int red[6];
@@ -115,7 +119,10 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
     if (j < n) {
       int b[3];
       unpack_base(mesh[j], nx, nxy, b);
-      qmax = fmax(qmax, fabs((double)rec_weight(pp, j, geo)));
+      double qa = fabs((double)rec_weight(pp, j, geo));
+      if constexpr (GRAD)
+        qa *= fabs(v[3 * j]) / geo.hu[0] + fabs(v[3 * j + 1]) / geo.hu[1] + fabs(v[3 * j + 2]) / geo.hu[2];
+      qmax = fmax(qmax, qa);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         lo[d] = min(lo[d], b[d]);
@@ -174,9 +181,11 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
           const int rx = b[0] - o0, ry = b[1] - o1 - py, rz = b[2] - o2 - pz;
           if (rz >= pe2 || rz + NS <= 0 || ry >= pe1 || ry + NS <= 0) continue;
           const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
-          double wx[NS];
+          double wx[NS], vd[3] = {0.0, 0.0, 0.0};
 #pragma unroll
           for (int a = 0; a < NS; ++a) wx[a] = (double)S.w[0][a];
+          if constexpr (GRAD)
+            for (int d = 0; d < 3; ++d) vd[d] = v[3 * j + d] / geo.hu[d];
 #pragma unroll
           for (int c = 0; c < NS; ++c) {
             const int z = rz + c;
@@ -185,10 +194,19 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
             for (int bb = 0; bb < NS; ++bb) {
               const int y = ry + bb;
               if ((unsigned)y >= (unsigned)pe1) continue;
-              const double wyz = (double)(q * S.w[1][bb] * S.w[2][c]) * toFix;
               unsigned long long* row = reinterpret_cast<unsigned long long*>(tile) + (z * pe1 + y) * e0 + rx;
+              if constexpr (GRAD) {
+                // q (W'_x W_y W_z v_x + W_x (W'_y W_z v_y + W_y W'_z v_z)) along the row
+                const double A = (double)q * S.w[1][bb] * S.w[2][c] * vd[0] * toFix;
+                const double B = (double)q * (S.dw[1][bb] * S.w[2][c] * vd[1] + S.w[1][bb] * S.dw[2][c] * vd[2]) * toFix;
 #pragma unroll
-              for (int a = 0; a < NS; ++a) atomicAdd(row + a, (unsigned long long)fix_round(wyz * wx[a]));
+                for (int a = 0; a < NS; ++a)
+                  atomicAdd(row + a, (unsigned long long)fix_round(fma((double)S.dw[0][a], A, wx[a] * B)));
+              } else {
+                const double wyz = (double)(q * S.w[1][bb] * S.w[2][c]) * toFix;
+#pragma unroll
+                for (int a = 0; a < NS; ++a) atomicAdd(row + a, (unsigned long long)fix_round(wyz * wx[a]));
+              }
             }
           }
         }
@@ -214,14 +232,24 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
       int b[3];
       unpack_base(m, nx, nxy, b);
       const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
+      double vd[3] = {0.0, 0.0, 0.0};
+      if constexpr (GRAD)
+        for (int d = 0; d < 3; ++d) vd[d] = v[3 * j + d] / geo.hu[d];
 #pragma unroll
       for (int c = 0; c < NS; ++c)
 #pragma unroll
         for (int bb = 0; bb < NS; ++bb) {
-          const R wyz = q * S.w[1][bb] * S.w[2][c];
           M* row = Q + ((long long)(b[2] + c) * ny + (b[1] + bb)) * nx + b[0];
+          if constexpr (GRAD) {
+            const double A = (double)q * S.w[1][bb] * S.w[2][c] * vd[0];
+            const double B = (double)q * (S.dw[1][bb] * S.w[2][c] * vd[1] + S.w[1][bb] * S.dw[2][c] * vd[2]);
 #pragma unroll
-          for (int a = 0; a < NS; ++a) atomicAdd(row + a, (M)(wyz * S.w[0][a]));
+            for (int a = 0; a < NS; ++a) atomicAdd(row + a, (M)(S.dw[0][a] * A + S.w[0][a] * B));
+          } else {
+            const R wyz = q * S.w[1][bb] * S.w[2][c];
+#pragma unroll
+            for (int a = 0; a < NS; ++a) atomicAdd(row + a, (M)(wyz * S.w[0][a]));
+          }
         }
     }
   }
@@ -361,29 +389,6 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
   }
 }
 
-// R_m = sum_j w_j grad W_m(x_j) . v_j (derivative of the deposit along v).
-template <int ORDER>
-__global__ void __launch_bounds__(kThreads) k_deposit_grad(int64_t n, const PPRec<double>* __restrict__ pp,
-                                                           const MeshRec<double>* __restrict__ mesh,
-                                                           const double* __restrict__ v, Geo geo,
-                                                           double* __restrict__ Rm) {
-  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (j >= n) return;
-  const MeshRec<double> m = mesh[j];
-  const double q = pp[j].w;
-  Stencil<double, ORDER> S(m.fx, m.fy, m.fz);
-  const double vx = v[3 * j] / geo.hu[0], vy = v[3 * j + 1] / geo.hu[1], vz = v[3 * j + 2] / geo.hu[2];
-  const int nx = geo.grid[0];
-  const long long nxy = (long long)nx * geo.grid[1];
-  for (int c = 0; c < S.N; ++c)
-    for (int b = 0; b < S.N; ++b)
-      for (int a = 0; a < S.N; ++a) {
-        double val = S.dw[0][a] * S.w[1][b] * S.w[2][c] * vx + S.w[0][a] * S.dw[1][b] * S.w[2][c] * vy +
-                     S.w[0][a] * S.w[1][b] * S.dw[2][c] * vz;
-        atomicAdd(Rm + m.base + c * nxy + (long long)b * nx + a, q * val);
-      }
-}
-
 // out_i = (fscale/Lu) [hpp_i - w_i (sum_m psi_m grad W_m(x_i) + sum_m phi_m (grad grad W_m(x_i)) v_i)]
 // in caller order: the PM part of the Hessian-vector product plus the PP part.
 template <int ORDER>
@@ -456,9 +461,9 @@ void launch_deposit(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const
   const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
   if (blocks == 0) return;
   if (geo.order == 1)
-    k_deposit<R, M, 1><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, M, 1, false><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, nullptr, Q);
   else
-    k_deposit<R, M, 2><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, Q);
+    k_deposit<R, M, 2, false><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, nullptr, Q);
 }
 
 int gather_blocks(int64_t n) { return (int)blocks_for(n); }
@@ -481,10 +486,14 @@ void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const 
 
 void launch_deposit_grad(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,
                          const double* v_sorted, const Geo& geo, double* Rm, hipStream_t st) {
+  // the tiled, fixed-point deposit with the gradient's node values (Rm is
+  // cleared by the caller)
+  const unsigned blocks = (unsigned)((n + kDepChunk - 1) / kDepChunk);
+  if (blocks == 0) return;
   if (geo.order == 1)
-    k_deposit_grad<1><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, v_sorted, geo, Rm);
+    k_deposit<double, double, 1, true><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, v_sorted, Rm);
   else
-    k_deposit_grad<2><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, v_sorted, geo, Rm);
+    k_deposit<double, double, 2, true><<<blocks, kDepThreads, 0, st>>>(n, pp, mesh, geo, v_sorted, Rm);
 }
 
 void launch_gather_hvp(int64_t n, const PPRec<double>* pp, const MeshRec<double>* mesh,

@@ -263,8 +263,10 @@ class P3MRollout(torch.autograd.Function):
             xs = [xk.clone()]
             x, p = xk.clone(), pk.clone()
             for s in range(seg):
+                # one step at a time to keep every position; after the first,
+                # the force cached at the end of the previous step is reused
                 rep = ctx.places[(k0 + s) * D:(k0 + s + 2) * D].contiguous()
-                c.step(x, p, dt, 1, qw=ctx.qw, place_replay=rep)
+                c.step(x, p, dt, 1, qw=ctx.qw, reuse_force=s > 0, place_replay=rep)
                 xs.append(x.clone())
             for s in range(seg - 1, -1, -1):
                 pn = ctx.places[(k0 + s) * D:(k0 + s + 1) * D].contiguous()
