@@ -464,16 +464,19 @@ __global__ void __launch_bounds__(kThreads) k_pp_hvp(int64_t n, const PPRec<doub
           const double d[3] = {me.x - o.x - sh[0], me.y - o.y - sh[1], me.z - o.z - sh[2]};
           const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
           if (!(r2 < 1.0 && r2 > 0.0)) continue;
-          const double r = sqrt(r2);
+          // one reciprocal per pair; every quotient below is a product with it
+          const double rinv = 1.0 / sqrt(r2);
+          const double r = r2 * rinv, rinv2 = rinv * rinv;
           const double ex = exp(-k * k * r2), ec = erfc(k * r);
-          const double g = ec / r + c2 * k * ex;
-          const double gp = -ec / r2 - c2 * k * ex / r - 2.0 * c2 * k * k * k * r * ex;
-          const double f = g / r2;
-          const double fp = gp / r2 - 2.0 * g / (r2 * r);
+          const double c2k = c2 * k;
+          const double g = ec * rinv + c2k * ex;
+          const double gp = -ec * rinv2 - c2k * ex * rinv - 2.0 * c2k * k * k * r * ex;
+          const double f = g * rinv2;
+          const double fp_r = (gp - 2.0 * g * rinv) * rinv2 * rinv;   // f'(r) / r
           const double dv[3] = {vi[0] - v[3 * q], vi[1] - v[3 * q + 1], vi[2] - v[3 * q + 2]};
           const double dd = d[0] * dv[0] + d[1] * dv[1] + d[2] * dv[2];
           const double s = me.w * o.w;
-          for (int c = 0; c < 3; ++c) o3[c] += s * (f * dv[c] + fp / r * d[c] * dd);
+          for (int c = 0; c < 3; ++c) o3[c] += s * (f * dv[c] + fp_r * d[c] * dd);
         }
       }
     }
