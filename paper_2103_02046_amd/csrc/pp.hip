@@ -68,12 +68,12 @@ __device__ __forceinline__ float pair_scalar(float r2, float wj, const PairK<flo
 
 __device__ __forceinline__ double pair_scalar(double r2, double wj, const PairK<double>& K, double* epair) {
   const double kappa = K.kappa, c2k = K.c2k;
-  double r = sqrt(r2);
-  double x = kappa * r;
-  double e = exp(-x * x);
-  double ec = erfc(x);
-  if (epair) *epair = ec / r * wj;
-  return (ec / r + c2k * e) / r2 * wj;
+  const double rinv = 1.0 / sqrt(r2);   // one reciprocal; the quotients are products with it
+  const double x = kappa * r2 * rinv;
+  const double e = exp(-x * x);
+  const double ec = erfc(x);
+  if (epair) *epair = ec * rinv * wj;
+  return (ec * rinv + c2k * e) * (rinv * rinv) * wj;
 }
 
 template <typename R>
