@@ -301,6 +301,26 @@ def test_step_reuse_force_and_records():
     assert (r[:, 3] >= 1.0).all()
 
 
+def test_replay_one_step_at_a_time_with_cached_force():
+    """A recorded run replayed step by step, each step after the first
+    reusing the force cached at the end of the previous call, ends where the
+    run did. Recording needs a fresh start force."""
+    wl = small_aniso(n=4096, grid=32)
+    x, p = wl.draw()
+    c = ctx_for(wl)
+    xa, pa = dev(x), dev(p)
+    rec = torch.empty(4 * 4, dtype=torch.float64, device="cuda")
+    c.step(xa, pa, wl.dt, 3, place_record=rec)
+    xb, pb = dev(x), dev(p)
+    for s in range(3):
+        c.step(xb, pb, wl.dt, 1, reuse_force=s > 0, place_replay=rec[4 * s:4 * s + 8].contiguous())
+    assert rms_err(host(xb) - x, host(xa) - x) < 1e-12
+    assert rms_err(host(pb) - p, host(pa) - p) < 1e-12
+    with pytest.raises(p3m.P3MError) as e:
+        c.step(xb, pb, wl.dt, 1, reuse_force=True, place_record=rec[:8].contiguous())
+    assert e.value.code == p3m.EINVAL
+
+
 # ---- adjoint -------------------------------------------------------------------------
 
 def _adj_case(order=2, n=600):
