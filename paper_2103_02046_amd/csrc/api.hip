@@ -347,7 +347,8 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   launch_cell_sort(n, x, ctx->place, g, ctx->sb, ctx->groups, &ctx->keys, &ctx->perm, st);
   launch_reorder<double>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, Carry{}, st);
   launch_sort_vector<double>(n, v, ctx->perm, ctx->v_sorted, st);
-  launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->v_sorted, ctx->hpp, st);
+  launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, ctx->v_sorted,
+                ctx->hpp, st);
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
   launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, st);
   const C2<double>* gimg = image_table(ctx, st);

@@ -60,8 +60,8 @@ void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* 
                const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
                hipStream_t st);
 void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
-                   const int* cell_start, const Geo& geo, const double* v_sorted,
-                   double* out_sorted, hipStream_t st);
+                   const int* cell_start, const Geo& geo, const int2* desc, int* counter,
+                   const double* v_sorted, double* out_sorted, hipStream_t st);
 
 // ---- mesh assignment (mesh.hip) --------------------------------------------
 // Deposit into a mesh of type M (float or double) from records of type R in

@@ -145,12 +145,19 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R, bool ENERGY, bool PACKED>
+// HVP (float64 only): the pair part of the Hessian-vector product in place
+// of the force, (H_PP v)_i = sum_j K_ij (v_i - v_j) with K_ij = w_i w_j
+// [f I + (f'/r) d d^T], the derivative of the pair force F_ij = w_i w_j f d;
+// f = g / r^2, g = erfc(kr)/r + (2k/sqrt(pi)) e^{-k^2 r^2} (internal units).
+// v and hv_out are sorted [n][3].
+template <typename R, bool ENERGY, bool PACKED, bool HVP = false>
 __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter,
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
                                            const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
-                                           double* __restrict__ energy) {
+                                           double* __restrict__ energy, const double* __restrict__ hv_in = nullptr,
+                                           double* __restrict__ hv_out = nullptr) {
   using V4 = typename Vec4<R>::T;
+  static_assert(!HVP || (std::is_same<R, double>::value && !ENERGY && !PACKED), "HVP: float64 forces only");
   // per-group tiles padded by one element so the four groups' broadcast
   // reads fall in different LDS banks
   constexpr int TS = kTileK + 1;
@@ -162,6 +169,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   __shared__ int4 tfix[kFix ? NT : 1];      // float: fixed-point x, y, z from the group's corner; weight bits
   __shared__ V4 tloc[kFix ? 1 : NT];        // double: cell-local x, y, z and the charge weight
   __shared__ V4 toff[kFix ? 1 : NT];        // double: cell-corner offset from the group's first cell
+  __shared__ V4 tvel[HVP ? NT : 1];         // HVP: the candidates' v
   __shared__ int rstart[kWaveGroups][9], rpre[kWaveGroups][10];
   __shared__ int gtot[kWaveGroups];
   const int ngroups = counter[0];
@@ -214,6 +222,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   int ix = 0, iy = 0, iz = 0;
   int tres = 0;   // float form, packed records: the target's position residuals
   int tdc = 0;
+  double vi[3] = {0.0, 0.0, 0.0};   // HVP: the target's v
   if (active) {
     const int j = gd.x + ql;
     const PPPos<R> me = rec[j];
@@ -229,6 +238,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       lz = me.z;
     }
     tw = PACKED ? (R)1 : rec_w(me, geo);
+    if constexpr (HVP)
+      for (int d = 0; d < 3; ++d) vi[d] = hv_in[3 * j + d];
   }
   const R tox = (R)tdc * cux;
   // cutoff test: r^2 - lim = (|t|^2 + (|c|^2 - lim)) - 2 t.c with lim =
@@ -267,6 +278,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   PPPos<R> nx_o[kPerLane];
   int nx_c[kPerLane];
   bool nx_ok[kPerLane];
+  double nx_v[HVP ? kPerLane : 1][3];
   auto fetch = [&](int t) {
 #pragma unroll
     for (int h = 0; h < kPerLane; ++h) {
@@ -277,6 +289,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         const int k = rstart[q][cr[h]] + (qi - rpre[q][cr[h]]);
         nx_o[h] = rec[k];
         nx_c[h] = (int)(keys[k] % (uint32_t)nx) - cx0;
+        if constexpr (HVP)
+          for (int d = 0; d < 3; ++d) nx_v[h][d] = hv_in[3 * k + d];
       }
     }
   };
@@ -325,6 +339,9 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         }
         tloc[TS * q + 16 * h + ql] = cl;
         toff[TS * q + 16 * h + ql] = co;
+        if constexpr (HVP)
+          tvel[TS * q + 16 * h + ql] = nx_ok[h] ? V4{(R)nx_v[h][0], (R)nx_v[h][1], (R)nx_v[h][2], (R)0}
+                                                : V4{(R)0, (R)0, (R)0, (R)0};
       }
       tile[TS * q + 16 * h + ql] = c;
     }
@@ -391,7 +408,25 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         wj = cl.w;
         r2 = dx * dx + dy * dy + dz * dz;
       }
-      if (r2 > (R)0 && r2 < rlim) {
+      if constexpr (HVP) {
+        if (r2 > (R)0 && r2 < rlim) {
+          // the pair Jacobian applied to v_i - v_j, one reciprocal per pair
+          const V4 vj = tvel[TS * q + k];
+          const double dvx = vi[0] - vj.x, dvy = vi[1] - vj.y, dvz = vi[2] - vj.z;
+          const double dd = dx * dvx + dy * dvy + dz * dvz;
+          const double kap = geo.kappa, c2k = kTwoOverSqrtPi * kap;
+          const double rinv = 1.0 / sqrt(r2);
+          const double r = r2 * rinv, rinv2 = rinv * rinv;
+          const double ex = exp(-kap * kap * r2), ec = erfc(kap * r);
+          const double g = ec * rinv + c2k * ex;
+          const double gp = -ec * rinv2 - c2k * ex * rinv - 2.0 * c2k * kap * kap * r * ex;
+          const double f = g * rinv2;
+          const double fp_r = (gp - 2.0 * g * rinv) * rinv2 * rinv;
+          sx += wj * (f * dvx + fp_r * dx * dd);
+          sy += wj * (f * dvy + fp_r * dy * dd);
+          sz += wj * (f * dvz + fp_r * dz * dd);
+        }
+      } else if (r2 > (R)0 && r2 < rlim) {
         R ep;
         const R g = pair_scalar(r2, wj, pk, ENERGY ? &ep : nullptr);
         sx += g * dx;
@@ -406,7 +441,9 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     acc.add(sx, sy, sz);
     wave_sync();
   }
-  if (active) {
+  if (HVP && active) {
+    for (int d = 0; d < 3; ++d) hv_out[3 * (gd.x + ql) + d] = (double)acc.get(d) * (double)tw;
+  } else if (active) {
     const R unit = (R)(1.0 / (fud * fud));   // separations in units: g u^-3 times d u
     PPRec<R> f;
     f.x = acc.get(0) * (tw * unit);
@@ -426,64 +463,6 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       atomicAdd(energy + 2, (double)pairs);
     }
   }
-}
-
-// (H_PP v)_i = sum_j K_ij (v_i - v_j), K_ij = f I + (f'/r) d d^T, F_ij = w_i w_j f(r) d;
-// f(r) = g(r)/r^2, g = erfc(kr)/r + (2k/sqrt(pi)) e^{-k^2 r^2}. Internal units,
-// double. The derivative of the pair force of the kernel above.
-__global__ void __launch_bounds__(kThreads) k_pp_hvp(int64_t n, const PPRec<double>* __restrict__ rec,
-                                                     const uint32_t* __restrict__ keys,
-                                                     const int* __restrict__ cs, Geo geo,
-                                                     const double* __restrict__ v,
-                                                     double* __restrict__ out) {
-  const int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (j >= n) return;
-  const PPRec<double> me = rec[j];
-  const double vi[3] = {v[3 * j], v[3 * j + 1], v[3 * j + 2]};
-  const uint32_t key = keys[j];
-  const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
-  const int cx = (int)(key % (uint32_t)nx);
-  const int cy = (int)((key / (uint32_t)nx) % (uint32_t)ny);
-  const int cz = (int)(key / ((uint32_t)nx * (uint32_t)ny));
-  const double k = geo.kappa, c2 = kTwoOverSqrtPi;
-  double o3[3] = {0, 0, 0};
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int z = cz + dz;
-    if (z < 0 || z >= nz) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int y = cy + dy;
-      if (y < 0 || y >= ny) continue;
-      const int rowc = (z * ny + y) * nx;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = cx + dx;
-        if (xx < 0 || xx >= nx) continue;
-        const double sh[3] = {dx * geo.cu[0], dy * geo.cu[1], dz * geo.cu[2]};
-        const int b = cs[rowc + xx], e = cs[rowc + xx + 1];
-        for (int q = b; q < e; ++q) {
-          const PPRec<double> o = rec[q];
-          const double d[3] = {me.x - o.x - sh[0], me.y - o.y - sh[1], me.z - o.z - sh[2]};
-          const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-          if (!(r2 < 1.0 && r2 > 0.0)) continue;
-          // one reciprocal per pair; every quotient below is a product with it
-          const double rinv = 1.0 / sqrt(r2);
-          const double r = r2 * rinv, rinv2 = rinv * rinv;
-          const double ex = exp(-k * k * r2), ec = erfc(k * r);
-          const double c2k = c2 * k;
-          const double g = ec * rinv + c2k * ex;
-          const double gp = -ec * rinv2 - c2k * ex * rinv - 2.0 * c2k * k * k * r * ex;
-          const double f = g * rinv2;
-          const double fp_r = (gp - 2.0 * g * rinv) * rinv2 * rinv;   // f'(r) / r
-          const double dv[3] = {vi[0] - v[3 * q], vi[1] - v[3 * q + 1], vi[2] - v[3 * q + 2]};
-          const double dd = d[0] * dv[0] + d[1] * dv[1] + d[2] * dv[2];
-          const double s = me.w * o.w;
-          for (int c = 0; c < 3; ++c) o3[c] += s * (f * dv[c] + fp_r * d[c] * dd);
-        }
-      }
-    }
-  }
-  out[3 * j] = o3[0];
-  out[3 * j + 1] = o3[1];
-  out[3 * j + 2] = o3[2];
 }
 
 }  // namespace
@@ -517,9 +496,12 @@ void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* 
 }
 
 void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys, const int* cell_start,
-                   const Geo& geo, const double* v_sorted, double* out_sorted, hipStream_t st) {
-  unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
-  k_pp_hvp<<<blocks, kThreads, 0, st>>>(n, rec, keys, cell_start, geo, v_sorted, out_sorted);
+                   const Geo& geo, const int2* desc, int* counter, const double* v_sorted, double* out_sorted,
+                   hipStream_t st) {
+  // the tiled pair kernel in its Hessian-vector mode, over the cell sort's groups
+  const unsigned blocks = (unsigned)((pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups);
+  k_pp<double, false, false, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
+                                                           nullptr, v_sorted, out_sorted);
 }
 
 template void launch_pp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
