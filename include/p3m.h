@@ -231,6 +231,22 @@ p3m_status p3m_backward(p3m_ctx *ctx, int64_t n, const double *x_n, const double
                         double *xbar_n, double *pbar_n, double dt, const double *place_n,
                         const double *place_np1, void *stream);
 
+/*
+ * Adjoint of nsteps leapfrog steps at once (the same steps as p3m_backward).
+ * xs (device, [nsteps+1][n][3]) holds the positions x_0 .. x_nsteps of the
+ * forward run and places (device, [nsteps+1][P3M_PLACEMENT_DOUBLES]) its
+ * placements. xbar, pbar (device [n][3]) hold the gradients with respect to
+ * (x_nsteps, p_nsteps) on entry and with respect to (x_0, p_0) on return.
+ * The product H(x_k) pbar_k that ends the step k+1 -> k also begins the step
+ * k -> k-1, so it is formed once: nsteps + 1 Hessian-vector products in all,
+ * not 2 nsteps. nsteps = 0 leaves xbar, pbar unchanged.
+ * P3M_EINVAL for nsteps < 0 or missing arrays; P3M_ESTATE with the
+ * momentum-conserving gather.
+ */
+p3m_status p3m_backward_steps(p3m_ctx *ctx, int64_t n, int32_t nsteps, const double *xs,
+                              const double *qw, double *xbar, double *pbar, double dt,
+                              const double *places, void *stream);
+
 typedef struct {
     double momentum[3];   /* sum_i p_i                                   kg m/s */
     double kinetic;       /* sum_i |p_i|^2 / (2m)                        J      */

@@ -669,6 +669,35 @@ p3m_status p3m_backward(p3m_ctx* ctx, int64_t n, const double* x_n, const double
   return check_last(ctx);
 }
 
+p3m_status p3m_backward_steps(p3m_ctx* ctx, int64_t n, int32_t nsteps, const double* xs, const double* qw,
+                              double* xbar, double* pbar, double dt, const double* places, void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  if (n < 0 || nsteps < 0 || !std::isfinite(dt) || (n > 0 && nsteps > 0 && (!xs || !xbar || !pbar || !places)))
+    return fail(ctx, P3M_EINVAL, "bad backward arguments");
+  if (ctx->geo.gather) return fail(ctx, P3M_ESTATE, "the adjoint is that of the variational force");
+  ctx->force_cached = false;
+  if (n == 0 || nsteps == 0) return P3M_OK;
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if ((s = ensure_capacity(ctx, n)) != P3M_OK) return s;
+  if ((s = ensure_adjoint(ctx, n)) != P3M_OK) return s;
+  const size_t stride = (size_t)3 * n;
+  auto xk = [&](int k) { return xs + (size_t)k * stride; };
+  auto pk = [&](int k) { return places + (size_t)k * P3M_PLACEMENT_DOUBLES; };
+  // hv = H(x_N) pbar_N; then per step k+1 -> k:
+  //   xbar += dt/2 hv;  pbar += dt/m xbar;  hv = H(x_k) pbar;  xbar += dt/2 hv
+  place(ctx, n, xk(nsteps), pk(nsteps), nullptr, st);
+  if ((s = hvp_core(ctx, n, xk(nsteps), qw, pbar, ctx->hv, st)) != P3M_OK) return s;
+  for (int k = nsteps - 1; k >= 0; --k) {
+    launch_kick(n, xbar, ctx->hv, dt, st);
+    launch_kick(n, pbar, xbar, 2.0 * dt / ctx->opts.m, st);
+    place(ctx, n, xk(k), pk(k), nullptr, st);
+    if ((s = hvp_core(ctx, n, xk(k), qw, pbar, ctx->hv, st)) != P3M_OK) return s;
+    launch_kick(n, xbar, ctx->hv, dt, st);
+  }
+  return check_last(ctx);
+}
+
 p3m_status p3m_diagnostics(p3m_ctx* ctx, int64_t n, const double* x, const double* p, const double* qw,
                            p3m_diag* out, void* stream) {
   if (!ctx || !out) return P3M_EINVAL;

@@ -23,7 +23,7 @@ PLACEMENT_DOUBLES = 4
 # Every symbol include/p3m.h declares.
 SYMBOLS = (
     "p3m_default_opts", "p3m_create", "p3m_forces", "p3m_forces_ex", "p3m_step", "p3m_hvp",
-    "p3m_backward", "p3m_diagnostics", "p3m_mesh", "p3m_status_sync", "p3m_info",
+    "p3m_backward", "p3m_backward_steps", "p3m_diagnostics", "p3m_mesh", "p3m_status_sync", "p3m_info",
     "p3m_last_error", "p3m_destroy", "p3m_profile_begin", "p3m_profile_end",
 )
 STAGES = ("push+placement", "sort", "reorder", "pp", "deposit", "fft", "gather")
@@ -75,6 +75,7 @@ def lib():
             "p3m_step": (i32, [P, i64, P, P, P, dbl, i32, i32, P, P, P]),
             "p3m_hvp": (i32, [P, i64, P, P, P, P, P, P]),
             "p3m_backward": (i32, [P, i64, P, P, P, P, P, P, P, dbl, P, P, P]),
+            "p3m_backward_steps": (i32, [P, i64, i32, P, P, P, P, dbl, P, P]),
             "p3m_diagnostics": (i32, [P, i64, P, P, P, P, P]),
             "p3m_mesh": (i32, [P, i32, P, P]),
             "p3m_status_sync": (i32, [P, P]),
@@ -189,6 +190,12 @@ class Context:
                                        _ptr(place_np1), _stream()))
         return xbar_out, pbar_out
 
+    def backward_steps(self, xs, xbar, pbar, dt, places, qw=None):
+        """Adjoint of len(xs) - 1 steps; xbar, pbar are updated in place."""
+        self._check(lib().p3m_backward_steps(self._ctx, xs.shape[1], xs.shape[0] - 1, _ptr(xs), _ptr(qw),
+                                             _ptr(xbar), _ptr(pbar), float(dt), _ptr(places), _stream()))
+        return xbar, pbar
+
     def diagnostics(self, x, p, qw=None):
         d = Diag()
         self._check(lib().p3m_diagnostics(self._ctx, x.shape[0], _ptr(x), _ptr(p), _ptr(qw), ctypes.byref(d),
@@ -260,18 +267,17 @@ class P3MRollout(torch.autograd.Function):
                 xb = torch.zeros_like(xk)
             if pb is None:
                 pb = torch.zeros_like(pk)
-            xs = [xk.clone()]
+            xs = torch.empty((seg + 1,) + tuple(xk.shape), dtype=xk.dtype, device=xk.device)
+            xs[0].copy_(xk)
             x, p = xk.clone(), pk.clone()
             for s in range(seg):
                 # one step at a time to keep every position; after the first,
                 # the force cached at the end of the previous step is reused
                 rep = ctx.places[(k0 + s) * D:(k0 + s + 2) * D].contiguous()
                 c.step(x, p, dt, 1, qw=ctx.qw, reuse_force=s > 0, place_replay=rep)
-                xs.append(x.clone())
-            for s in range(seg - 1, -1, -1):
-                pn = ctx.places[(k0 + s) * D:(k0 + s + 1) * D].contiguous()
-                pn1 = ctx.places[(k0 + s + 1) * D:(k0 + s + 2) * D].contiguous()
-                xb, pb = c.backward(xs[s], xs[s + 1], xb, pb, dt, pn, pn1, qw=ctx.qw)
+                xs[s + 1].copy_(x)
+            seg_places = ctx.places[k0 * D:(k0 + seg + 1) * D].contiguous()
+            c.backward_steps(xs, xb, pb, dt, seg_places, qw=ctx.qw)
         return xb, pb, None, None, None, None, None
 
 

@@ -362,6 +362,41 @@ def test_backward_step_parity():
     assert rms_err(host(gp), rp) < 1e-10
 
 
+def test_backward_steps_equals_chained_backward():
+    """The multi-step adjoint (each H(x_k) pbar_k formed once) against a chain
+    of one-step adjoints, and against the oracle's steps."""
+    x, prm = _adj_case()
+    rng = np.random.default_rng(11)
+    p = 0.05 * rng.standard_normal(x.shape)
+    c = p3m.Context(prm.grid, prm.h, prm.r_cut, prm.split, order=2, ke=1.0, q=1.0, m=1.0)
+    nst = 4
+    rec = torch.empty(4 * (nst + 1), dtype=torch.float64, device="cuda")
+    xd, pd = dev(x), dev(p)
+    c.step(xd, pd, prm.dt, nst, place_record=rec)
+    xs = torch.empty((nst + 1,) + x.shape, dtype=torch.float64, device="cuda")
+    xr, pr = dev(x), dev(p)
+    xs[0].copy_(xr)
+    for s in range(nst):
+        c.step(xr, pr, prm.dt, 1, reuse_force=s > 0, place_replay=rec[4 * s:4 * s + 8].contiguous())
+        xs[s + 1].copy_(xr)
+    xb0, pb0 = rng.standard_normal(x.shape), rng.standard_normal(x.shape)
+    gx, gp = dev(xb0), dev(pb0)
+    for s in range(nst - 1, -1, -1):
+        gx, gp = c.backward(xs[s], xs[s + 1], gx, gp, prm.dt, rec[4 * s:4 * s + 4].contiguous(),
+                            rec[4 * s + 4:4 * s + 8].contiguous())
+    mx, mp = dev(xb0), dev(pb0)
+    c.backward_steps(xs, mx, mp, prm.dt, rec)
+    assert rms_err(host(mx), host(gx)) < 1e-13
+    assert rms_err(host(mp), host(gp)) < 1e-13
+    # and the oracle, step by step on the same positions (its own placements)
+    ox, op = xb0, pb0
+    for s in range(nst - 1, -1, -1):
+        xa, xc = host(xs[s]), host(xs[s + 1])
+        ox, op = O.step_backward(xa, xc, O.placement(xa, prm), O.placement(xc, prm), ox, op, prm)
+    assert rms_err(host(mx), ox) < 1e-10
+    assert rms_err(host(mp), op) < 1e-10
+
+
 def test_rollout_gradient_vs_oracle_and_fd():
     x, prm = _adj_case(n=400)
     rng = np.random.default_rng(10)
