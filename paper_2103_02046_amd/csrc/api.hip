@@ -6,7 +6,7 @@
 //   convolution -> gather (+ kick, state move and the next drift)
 //
 // Everything is enqueued on the caller's stream; the host never waits for
-// the device inside p3m_forces / p3m_step / p3m_hvp / p3m_backward.
+// the device inside p3m_forces / p3m_step / p3m_hvp / p3m_backward(_steps).
 #include <cmath>
 #include <cstdio>
 #include <cstring>
