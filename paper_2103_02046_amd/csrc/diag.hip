@@ -58,9 +58,15 @@ __global__ void __launch_bounds__(kThreads) k_moments(int64_t n, const double* _
   }
 }
 
-__global__ void k_fill(uint32_t* __restrict__ p, long long words) {
-  long long k = blockIdx.x * (long long)kThreads + threadIdx.x;
-  for (; k < words; k += (long long)gridDim.x * kThreads) p[k] = 0u;
+// Zero `words` 32-bit words: 16-byte stores over the 16-byte-aligned body,
+// the few words before and after it one at a time.
+__global__ void k_fill(uint32_t* __restrict__ p, long long words, long long head, long long quads) {
+  const long long k0 = blockIdx.x * (long long)kThreads + threadIdx.x;
+  const long long tail = words - head - 4 * quads;
+  if (k0 < head) p[k0] = 0u;
+  if (k0 < tail) p[head + 4 * quads + k0] = 0u;
+  uint4* q = reinterpret_cast<uint4*>(p + head);
+  for (long long k = k0; k < quads; k += (long long)gridDim.x * kThreads) q[k] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 }  // namespace
@@ -74,11 +80,15 @@ void launch_moments(int64_t n, const double* x, const double* p, const double* q
 }
 
 void launch_fill(void* ptr, size_t bytes, hipStream_t st) {
-  long long words = (long long)(bytes / 4);
+  const long long words = (long long)(bytes / 4);
   if (words == 0) return;
-  long long b = (words + kThreads - 1) / kThreads;
+  long long head = (long long)(((16 - ((uintptr_t)ptr & 15)) & 15) / 4);
+  if (head > words) head = words;
+  const long long quads = (words - head) / 4;
+  long long b = (quads + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
   if (b > 4096) b = 4096;
-  k_fill<<<(unsigned)b, kThreads, 0, st>>>((uint32_t*)ptr, words);
+  k_fill<<<(unsigned)b, kThreads, 0, st>>>((uint32_t*)ptr, words, head, quads);
 }
 
 }  // namespace p3m

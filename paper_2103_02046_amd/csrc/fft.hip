@@ -380,6 +380,16 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_y_reg(Geo geo, C2<float>* _
 
 // z pass on 256-point float lines, free space: forward, times the kernel
 // table, inverse, keep z < N.
+//
+// Block order: the kernel table is float, so a block's 16 k_x values are half
+// a 128-byte line, and rows k_y and 2 N_y - k_y read the same table row. The
+// four blocks of one table line (two k_x chunks of a row and of its mirror)
+// take slots kXcds apart in a run of 4 kXcds, so that they run on one XCD at
+// about the same time and its L2 fetches the line once; slots with no row or
+// chunk (self-mirrored rows 0 and N_y, an odd last chunk) end at once.
+__host__ __device__ inline int z_reg_groups(const Geo& g) {
+  return (g.grid[1] + 1) * ((g.grid[0] + 1 + 31) / 32);
+}
 __global__ void __launch_bounds__(kFftThreads) k_fft_z_reg(Geo geo, C2<float>* __restrict__ S,
                                                            const float* __restrict__ gz,
                                                            const C2<float>* __restrict__ tw) {
@@ -387,8 +397,14 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z_reg(Geo geo, C2<float>* _
   __shared__ C2<float> s[L * 16];
   const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
   const int ly = 2 * geo.grid[1];
-  const int nch = (K + 15) / 16;
-  const int ky = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * 16;
+  const int nch = (K + 15) / 16, ncp = (nch + 1) / 2;
+  const int slot = (int)blockIdx.x;
+  const int grp = (slot / (4 * kXcds)) * kXcds + slot % kXcds;
+  const int member = (slot / kXcds) % 4;
+  const int rg = grp / ncp, c = 2 * (grp % ncp) + (member >> 1);
+  if (rg > geo.grid[1] || c >= nch) return;   // whole block: no barrier passed yet
+  if ((member & 1) && (rg == 0 || rg == geo.grid[1])) return;
+  const int ky = (member & 1) ? ly - rg : rg, kx0 = c * 16;
   const int b = threadIdx.x & 15, q = threadIdx.x >> 4;
   const int kx = kx0 + b;
   const bool valid = kx < K;
@@ -402,8 +418,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z_reg(Geo geo, C2<float>* _
   }
   // the kernel table at this thread's frequencies kz = q + 16 k2 (after the
   // forward transform), loaded now so that its latency overlaps the transform
-  const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
-  const float* grow = gz + (long long)kyp * KS + (valid ? kx : K - 1);
+  const float* grow = gz + (long long)rg * KS + (valid ? kx : K - 1);
   const long long gplane_s = (long long)(geo.grid[1] + 1) * KS;
   float g[16];
 #pragma unroll
@@ -810,7 +825,8 @@ void run_z(const Geo& g, C2<T>* S, const T* gz, const C2<double>* gimg, const C2
   unsigned blocks = (unsigned)(2 * g.grid[1] * ((K + B - 1) / B));
   if constexpr (std::is_same<T, float>::value && L == kRegL) {
     if (!gimg) {
-      k_fft_z_reg<<<(unsigned)(2 * g.grid[1] * ((K + 15) / 16)), kFftThreads, 0, st>>>(g, S, gz, tw);
+      const unsigned slots = (unsigned)((z_reg_groups(g) + kXcds - 1) / kXcds * 4 * kXcds);
+      k_fft_z_reg<<<slots, kFftThreads, 0, st>>>(g, S, gz, tw);
       return;
     }
   }
