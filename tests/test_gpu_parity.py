@@ -8,6 +8,7 @@ Tolerances (relative rms over all particles, e = sqrt(sum|dF|^2 / sum|F|^2)):
     sums (up to ~1e3 near the bunch centre);
   * float32 path: 1e-5, the accuracy target of the compensated form.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -136,6 +137,26 @@ def test_fp32c_parity_aniso():
     e_pp, e_pm, e = rms_err(fpp, parts["pp"]), rms_err(fpm, parts["pm"]), rms_err(fpp + fpm, ref)
     print(f"fp32c vs oracle: pp {e_pp:.2e} pm {e_pm:.2e} total {e:.2e}")
     assert e < TOL32 and e_pp < TOL32 and e_pm < TOL32
+
+
+@pytest.mark.parametrize("grid", [(64, 32, 128), (16, 128, 128), (128, 16, 128)])
+def test_fp32c_meshes_with_128_z_nodes(grid):
+    """Float meshes with 128 nodes along z take the register-resident z pass
+    for any N_x and N_y. Its block order pairs mirrored rows k_y, 2N_y - k_y
+    and adjacent 16-wide k_x chunks, so every line must still be transformed
+    once: an odd chunk count (N_x = 64, 128), a single chunk pair (N_x = 16)
+    and few rows (N_y = 16) against the oracle's mesh force."""
+    sig = (1e-3, 1e-3, 3e-3)
+    h = tuple(8 * s / (g - 2) for s, g in zip(sig, grid))
+    rc = 2 * max(h)
+    wl = dataclasses.replace(small_aniso(n=1 << 13), grid=grid, h=h, r_cut=rc, split=3.0 / rc)
+    x, _ = wl.draw()
+    prm = O.Params.from_workload(wl)
+    _, parts = O.forces(x, prm, parts=True)
+    fpp, fpm, _ = ctx_for(wl, p3m.FP32C).forces_parts(dev(x))
+    e_pm, e_pp = rms_err(host(fpm), parts["pm"]), rms_err(host(fpp), parts["pp"])
+    print(f"grid {grid}: fp32c vs oracle pm {e_pm:.2e} pp {e_pp:.2e}")
+    assert e_pm < TOL32 and e_pp < TOL32
 
 
 def test_mesh_precision_option():
