@@ -232,8 +232,8 @@ hipError_t build_lattice_kernel(const Geo& geo, double* out, hipStream_t st) {
   }
   // the host vector and the device tables must outlive the launches
   const hipError_t es = hipStreamSynchronize(st);
-  hipFree(buf);
-  return e != hipSuccess ? e : es;
+  const hipError_t ef = hipFree(buf);
+  return e != hipSuccess ? e : (es != hipSuccess ? es : ef);
 }
 
 }  // namespace p3m
