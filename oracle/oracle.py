@@ -56,13 +56,35 @@ def build(force=False):
 
 
 _lib = None
+_lib_path = None
+
+
+def build_native(out_path):
+    """Compile the C part for the host it runs on (-O3 -march=native, OpenMP,
+    still no FMA contraction) into out_path, for timing the oracle as a
+    CPU baseline; the arithmetic is the same as build()'s."""
+    tmp = out_path + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                           "-shared", "-std=c11", _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, out_path)
+    return out_path
+
+
+def use_library(path):
+    """Load the C part from path (a build_native output) instead of the default build."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
+    return lib()
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        path = _lib_path
+        if path is None:
+            build()
+            path = _LIB
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, dbl, i32 = ctypes.c_int64, ctypes.c_double, ctypes.c_int
         sig = {
@@ -250,7 +272,7 @@ def lattice_kernel(nmax, hp, a):
     """Mesh kernel of the lattice form on the octant 0 <= n_d <= nmax_d:
     K = 4 pi G_L (x) g, where G_L solves the 7-point discrete Poisson equation
     of the free (unbounded) lattice, -sum_d D_d G_L / h_d^2 = delta / (h_x h_y h_z)
-    (D_d the second difference of Sec. 2.4.3 eq. 1d_ddiff, summed as in eq.
+    (D_d the second difference of Sec. 2.4.2 eq. 1d_ddiff, summed as in eq.
     3dim_second_order_fin_diff_tensor; the Green's function of Sec. 3 eq.
     def_G_L), and g = prod_d g_d the Gaussian screening integrated over cells
     (lattice_cell_weights). K -> 1/r far away, like the sampled erf(a r)/r.

@@ -2,7 +2,7 @@
 // float64, on the octant of node offsets 0 <= n_d <= N_d, in internal units
 // (spacings hu, screening kappa): the free-space Green's function of the
 // 7-point discrete Laplacian L = -sum_d D_d / h_d^2 (the second differences of
-// Sec. 2.4.3, eq. 1d_ddiff, summed as in eq. 3dim_second_order_fin_diff_tensor;
+// Sec. 2.4.2, eq. 1d_ddiff, summed as in eq. 3dim_second_order_fin_diff_tensor;
 // the lattice Green's function of Sec. 3, eq. def_G_L), normalised so that
 // L G = delta / (h_x h_y h_z), convolved with the Gaussian screening charge
 // per cell g = prod_d g_d, g_d(m) = [erf(a (m+1/2) h_d) - erf(a (m-1/2) h_d)]/2,

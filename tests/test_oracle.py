@@ -540,7 +540,7 @@ def test_optimal_influence_force_is_minus_energy_gradient():
         assert fd == pytest.approx(parts["pm"][i, d], rel=1e-5, abs=1e-6 * np.abs(parts["pm"]).max())
 
 
-# ---- lattice Green's function of the discrete Laplacian (Sec. 2.4.3, Sec. 3) -----------
+# ---- lattice Green's function of the discrete Laplacian (Sec. 2.4.2, Sec. 3) -----------
 
 def _watson_sc():
     """Watson's simple-cubic integral (1/pi^3) int_[0,pi]^3 dx dy dz / (1 - (cos x +
@@ -579,7 +579,7 @@ def test_lattice_cell_weights_are_the_screening_charge_per_cell():
 @pytest.mark.parametrize("h,a", [((0.5, 0.7, 1.3), 1.9), ((0.4, 0.4, 0.4), None), ((0.25, 0.25, 0.75), 6.0)])
 def test_lattice_kernel_solves_the_discrete_poisson_equation(h, a):
     """Minus the 7-point Laplacian with spacings h_d (second differences D_d / h_d^2
-    of Sec. 2.4.3, eq. 1d_ddiff) of K is the screening charge per cell over the
+    of Sec. 2.4.2, eq. 1d_ddiff) of K is the screening charge per cell over the
     cell volume times 4 pi: prod_d g_d(n_d), g_d(m) = [erf(a (m+1/2) h_d) -
     erf(a (m-1/2) h_d)]/2, or the unit charge at the origin unscreened."""
     from scipy.special import erf
@@ -869,3 +869,109 @@ def test_gradient_matches_central_differences():
         fd = (jp - jm) / (2 * eps)
         an = (gx * dx).sum() + (gp * dp).sum()
         assert an == pytest.approx(fd, rel=1e-5)
+
+
+# ---- emittance (the adjoint's objective) ------------------------------------------
+
+def test_emittance_closed_form_phase_space():
+    """A discrete phase space with exactly known centred moments: points
+    (x, p) = (mu_x + a u_k, mu_p + b u_k + c v_k) with u = (1, 1, -1, -1) and
+    v = (1, -1, 1, -1) repeated, so <u> = <v> = <uv> = 0 and <u^2> = <v^2> = 1:
+    <dx^2> = a^2, <dp^2> = b^2 + c^2, <dx dp> = a b and the normalised rms
+    emittance is |a c| / (m c_light). Nonzero means test the centring, the
+    shear b the correlation term."""
+    u = np.tile([1.0, 1.0, -1.0, -1.0], 25)
+    v = np.tile([1.0, -1.0, 1.0, -1.0], 25)
+    m = 2.7e-3
+    for a, b, c, mx, mp in [(1e-3, 4e-24, 3e-24, 0.37, -8e-22), (2.5e-4, -1e-23, 7e-25, -1.2e-3, 5e-23)]:
+        x = np.zeros((len(u), 3))
+        p = np.zeros((len(u), 3))
+        for ax in range(3):
+            x[:, ax] = mx + a * u
+            p[:, ax] = mp + b * u + c * v
+        for ax in range(3):
+            assert O.emittance(x, p, m, ax) == pytest.approx(abs(a * c) / (m * O.C_LIGHT), rel=1e-9)
+        J = O.objective(x, p, O.Params((4, 4, 4), (1, 1, 1), 1.0, 0.0, 1, 1.0, m=m))
+        assert J == pytest.approx(abs(a * c) / (m * O.C_LIGHT), rel=1e-9)
+
+
+def test_emittance_invariant_under_drift_and_zero_for_a_line():
+    """A drift x -> x + t p / m is a shear of phase space: the covariance
+    determinant, hence the emittance, is unchanged. A beam on a straight line
+    p = k x in phase space has zero emittance."""
+    rng = np.random.default_rng(40)
+    x = rng.standard_normal((500, 3)) * 1e-3 + 0.2
+    p = rng.standard_normal((500, 3)) * 1e-24 - 3e-24
+    m = 1e-30
+    for ax in range(3):
+        e0 = O.emittance(x, p, m, ax)
+        e1 = O.emittance(x + 3e-9 * p / m, p, m, ax)
+        assert e1 == pytest.approx(e0, rel=1e-9)
+        assert O.emittance(x, 2e-21 * x + 5e-24, m, ax) < 1e-7 * e0
+
+
+def test_objective_gradient_closed_form_on_the_four_point_beam():
+    """dJ/dp for the four-point phase space of the closed-form test: with
+    eps = sqrt(a^2 (b^2 + c^2) - a^2 b^2) / (m c) and n points,
+    d eps / d p_k = (a^2 dp_k - a b dx_k) / (n eps (m c)^2), d eps / d x_k =
+    ((b^2 + c^2) dx_k - a b dp_k) / (n eps (m c)^2); J averages x and y."""
+    u = np.tile([1.0, 1.0, -1.0, -1.0], 5)
+    v = np.tile([1.0, -1.0, 1.0, -1.0], 5)
+    n = len(u)
+    a, b, c, m = 2e-3, 3e-24, 5e-24, 1e-30
+    x = np.zeros((n, 3))
+    p = np.zeros((n, 3))
+    for ax in range(3):
+        x[:, ax] = 0.1 + a * u
+        p[:, ax] = -2e-24 + b * u + c * v
+    prm = O.Params((4, 4, 4), (1, 1, 1), 1.0, 0.0, 1, 1.0, m=m)
+    gx, gp = O.objective_grad(x, p, prm)
+    mc = m * O.C_LIGHT
+    eps = abs(a * c) / mc
+    dx, dp = a * u, b * u + c * v
+    ex = ((b * b + c * c) * dx - a * b * dp) / (n * eps * mc * mc)
+    ep = (a * a * dp - a * b * dx) / (n * eps * mc * mc)
+    for ax in (0, 1):
+        np.testing.assert_allclose(gx[:, ax], 0.5 * ex, rtol=1e-9)
+        np.testing.assert_allclose(gp[:, ax], 0.5 * ep, rtol=1e-9)
+    assert np.all(gx[:, 2] == 0) and np.all(gp[:, 2] == 0)
+
+
+def test_optimal_influence_small_screening_limit():
+    """When the screening is wide against the mesh (a h = 0.2), the screened
+    reference (R gamma)(k) = 4 pi exp(-k^2/4a^2)/k^2 vanishes at every alias
+    k - 2 pi m / h (m != 0) of a wavevector in the inner half of the zone, to
+    exp(-pi^2/(2 a^2 h^2)) = e^-123. There the numerator of eq. Ghfinal reduces
+    to its m = 0 term U^2(k) (R gamma)(k), whatever the alias loops do, and the
+    optimal table times the squared aliasing sums of the denominator (the
+    table's |m_d| <= 2, pinned to the closed forms above) must return exactly
+    that term; the principal table is (R gamma)(k) / U^2(k)."""
+    grid = (16, 16, 16)
+    hp = np.array([0.3, 0.3, 0.3])
+    a = 0.2 / 0.3
+    kz = 2 * math.pi * np.fft.fftfreq(32, d=hp[2])
+    ky = 2 * math.pi * np.fft.fftfreq(32, d=hp[1])
+    kx = 2 * math.pi * np.fft.rfftfreq(32, d=hp[0])
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    inner = (np.abs(KX) * hp[0] < 0.5 * math.pi) & (np.abs(KY) * hp[1] < 0.5 * math.pi) & \
+            (np.abs(KZ) * hp[2] < 0.5 * math.pi) & (k2 > 0)
+    rg = np.zeros_like(k2)
+    rg[k2 > 0] = 4 * math.pi * np.exp(-k2[k2 > 0] / (4 * a * a)) / k2[k2 > 0]
+    V = hp.prod()
+    for order in (1, 2):
+        u2 = np.ones_like(k2)
+        A = np.ones_like(k2)
+        for K, h in ((KX, hp[0]), (KY, hp[1]), (KZ, hp[2])):
+            s = np.sin(0.5 * K * h)
+            with np.errstate(invalid="ignore", divide="ignore"):
+                sinc = np.where(K == 0, 1.0, s / (0.5 * K * h))
+            u2 = u2 * sinc ** (2 * (order + 1))
+            A = A * O.alias_sum_u2(K * h, order, 2)
+        G_opt = O.influence_correction(grid, hp, a, order, "optimal", M=2) * V + rg
+        G_pri = O.influence_correction(grid, hp, a, order, "principal") * V + rg
+        np.testing.assert_allclose((G_opt * A ** 2)[inner], (u2 * rg)[inner], rtol=1e-10)
+        np.testing.assert_allclose(G_pri[inner], (rg / u2)[inner], rtol=1e-10)
+        # the optimal table is not the principal one here: the assignment's own
+        # aliases (not screened) enter the denominator
+        assert np.abs(G_opt[inner] / G_pri[inner] - 1).max() > 1e-3
