@@ -1,7 +1,11 @@
 """Throughput of the P3M leapfrog step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload aniso1m]
-                    [--precision fp32c|fp64] [--cpu-steps 6] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload halo32m]
+                    [--precision fp32c|fp64] [--fp64-steps 3] [--no-cpu-baseline]
+
+Default workload: the 2^25-particle core/halo bunch on a 512^3 mesh (1024^3
+zero-padded FFT), TSC, r_c = 2h, kappa = 3, dt = T_p/200, float-compensated
+path; the largest workload that runs on one GPU.
 
 One step = one kick-drift-kick leapfrog step of the whole bunch: push,
 placement, linked-cell sort, PP pair forces, deposit, FFT convolution,
@@ -38,9 +42,9 @@ PP_FLOP_PER_PAIR = 40          # per in-cutoff ordered pair: FMA 2, rsqrt/exp/rc
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="aniso1m")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="halo32m")
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--gather", default="variational", choices=["variational", "momentum"],
                     help="mesh force at the particles: variational (default) or momentum-conserving")
@@ -48,7 +52,10 @@ def parse():
                     help="Fourier table of the mesh kernel (built at create)")
     ap.add_argument("--cathode", action="store_true",
                     help="grounded plane 1 mm below the bunch (image charges on the mesh)")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="leapfrog steps of the float64 path timed for its own particle-steps/s (0: skip)")
+    ap.add_argument("--cpu-targets", type=int, default=32768,
+                    help="sampled PP targets of the CPU oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
@@ -88,20 +95,118 @@ def traffic_from_profiles(stage, workload, precision, launches_per_step):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, steps):
-    """The FP64 CPU oracle as it stands, on `steps` leapfrog steps of the same
-    workload (the initial force evaluation is not timed)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def workload_text(name, wl):
+    """The workload spelled out: particles, draw, mesh, assignment, cutoff, split, time step."""
+    draws = {
+        "gauss": "isotropic Gaussian sigma 1 mm",
+        "aniso": "Gaussian sigma (1, 1, 3) mm",
+        "sphere": "uniform ball of radius 1 mm at rest",
+        "halo": "90% Gaussian core sigma 0.5 mm + 10% r^-2 halo from 0.5 to 5 mm",
+    }
+    g = wl.grid
+    rc_h = wl.r_cut / min(wl.h)
+    return (f"{name}: {wl.n} particles, {draws[wl.name]}, seed {wl.seed}; "
+            f"{g[0]}x{g[1]}x{g[2]} mesh ({2 * g[0]}x{2 * g[1]}x{2 * g[2]} zero-padded FFT), "
+            f"{'TSC' if wl.order == 2 else 'CIC'}, r_c = {rc_h:g} h, kappa = a r_c = {wl.split * wl.r_cut:g}, "
+            f"dt = T_p/200 = {wl.dt:.4g} s")
+
+
+def cpu_baseline(wl, n_targets):
+    """The FP64 CPU oracle as it stands (compiled here with -O3 -march=native,
+    OpenMP on every core), timed part by part on a bounded sample of one
+    leapfrog step of the same workload, scaled to the whole step:
+      * PP: the pair forces of sampled targets through the oracle's cell
+        list over all particles; timed at K and 2K targets, so the cell build
+        (once per evaluation) and the cost per target separate, then scaled
+        to N targets;
+      * deposit, gather and the kick-drift-kick arrays: all N particles;
+      * mesh convolution (numpy FFTs, kernel table included): in full up to
+        a 256^3 mesh; above, on the mesh halved per axis and scaled by the
+        transform work M log M."""
+    import numpy as np
     from oracle import oracle as O
+    import tempfile
+    so = os.path.join(tempfile.gettempdir(), f"liboracle_native_{os.getpid()}.so")
+    O.build_native(so)
+    O.use_library(so)
     x, p = wl.draw()
     prm = O.Params.from_workload(wl)
-    f = O.forces(x, prm)
+    t_all = time.perf_counter()
+    pl = O.placement(x, prm)
+    # sampled targets: runs of 256 particles consecutive in an order by PP
+    # cell, started at random, so that each run is a spatial neighbourhood
+    # (the full evaluation's targets share neighbours in the caches too);
+    # the selection is not timed
+    rng = np.random.default_rng(123)
+    cell = np.floor((x - pl["x0"]) / pl["rc"]).astype(np.int64)
+    nc = cell.max(axis=0) + 1
+    order = np.argsort((cell[:, 2] * nc[1] + cell[:, 1]) * nc[0] + cell[:, 0], kind="stable")
+    del cell
+    run = 256
+    t_pp = []
+    for k in (n_targets, 2 * n_targets):
+        starts = rng.choice(max(wl.n - run, 1), max(k // run, 1), replace=False)
+        idx = np.sort(np.concatenate([order[s0:s0 + run] for s0 in starts]))
+        t0 = time.perf_counter()
+        O.pp_sample(x, prm, pl["rc"], pl["a"], idx)
+        t_pp.append(time.perf_counter() - t0)
+    del order
+    per_target = max(t_pp[1] - t_pp[0], 1e-12) / n_targets
+    build = max(t_pp[0] - per_target * n_targets, 0.0)
+    pp_est = build + per_target * wl.n
     t0 = time.perf_counter()
-    O.step(x, p, prm, steps, f)
-    t = time.perf_counter() - t0
-    return {"value": wl.n * steps / t, "unit": "particle-steps/s", "cores": O.threads(),
+    Q = O.deposit(x, prm, pl)
+    t_dep = time.perf_counter() - t0
+    g = np.asarray(prm.grid)
+    if g.max() <= 256:
+        t0 = time.perf_counter()
+        phi = O.mesh_potential(Q, prm, pl)
+        t_conv = time.perf_counter() - t0
+        conv_note = "in full"
+    else:
+        gh = tuple(int(v) // 2 for v in g)
+        Qh = np.ascontiguousarray(Q[:gh[2], :gh[1], :gh[0]])
+        t0 = time.perf_counter()
+        O.conv_fft(Qh, gh, pl["hp"], pl["a"])
+        t_half = time.perf_counter() - t0
+        m_full, m_half = 8.0 * g.prod(), 8.0 * np.prod(gh)
+        t_conv = t_half * (m_full * math.log2(m_full)) / (m_half * math.log2(m_half))
+        phi = np.zeros_like(Q)   # the gather's cost does not depend on phi's values
+        conv_note = f"on the {gh[0]}^3 mesh ({t_half:.1f} s), scaled by M log M"
+    t0 = time.perf_counter()
+    f = O.gather(x, prm, pl, phi)
+    p += 0.5 * prm.dt * f
+    x += prm.dt * p / prm.m
+    p += 0.5 * prm.dt * f
+    t_gat = time.perf_counter() - t0
+    step_s = pp_est + t_dep + t_conv + t_gat
+    wall = time.perf_counter() - t_all
+    try:
+        os.remove(so)
+    except OSError:
+        pass
+    return {"value": wl.n / step_s, "unit": "particle-steps/s", "cores": O.threads(),
             "kind": "oracle",
-            "sample": f"{steps} full leapfrog steps of the {wl.n}-particle workload "
-                      f"(FP64 C/OpenMP + numpy FFT), {t:.1f} s"}
+            "sample": (f"one leapfrog step of {wl.name} ({wl.n} particles) estimated from parts: PP of "
+                       f"{n_targets} and {2 * n_targets} targets (random runs of 256 in cell order) "
+                       f"over the full cell list "
+                       f"({t_pp[0]:.2f} s, {t_pp[1]:.2f} s; cell build {build:.2f} s + "
+                       f"{per_target * 1e6:.1f} us/target -> {pp_est:.1f} s for all), deposit {t_dep:.2f} s, "
+                       f"mesh convolution {t_conv:.1f} s ({conv_note}), gather + kicks + drift "
+                       f"{t_gat:.2f} s; {wall:.1f} s of CPU time"),
+            "cpu": cpu_model(), "build": "gcc -O3 -march=native -fopenmp -ffp-contract=off; numpy FFT",
+            "seconds_per_step": step_s}
 
 
 def main():
@@ -125,12 +230,31 @@ def main():
             "principal": p3m.INFLUENCE_PRINCIPAL, "lattice": p3m.INFLUENCE_LATTICE}[args.influence]
     ctx = p3m.Context.from_workload(wl, precision=prec, gather=gmode, cathode_z=zc, influence=infl)
 
-    # accuracy of this precision against the float64 path on the same GPU
+    # accuracy of this precision against the float64 path on the same GPU:
+    # relative rms over all particles, and the largest single-particle error
+    # against the rms force
     f_this = ctx.forces(x)
-    f64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode, cathode_z=zc,
-                                    influence=infl).forces(x)
+    ctx64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode, cathode_z=zc, influence=infl)
+    f64 = ctx64.forces(x)
     err = float(torch.sqrt(((f_this - f64) ** 2).sum() / (f64 ** 2).sum()))
+    err_max = float(torch.linalg.norm(f_this - f64, dim=1).max() / torch.sqrt((f64 ** 2).sum(dim=1).mean()))
+    del f_this, f64
+    # float64 path's own throughput: a few steps from the initial state, its
+    # start force evaluated before the timer
+    fp64_rate = None
+    if args.fp64_steps > 0 and prec != p3m.FP64:
+        x64, p64 = x.clone(), p.clone()
+        ctx64.step(x64, p64, wl.dt, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx64.step(x64, p64, wl.dt, args.fp64_steps, reuse_force=True)
+        torch.cuda.synchronize()
+        fp64_rate = wl.n * args.fp64_steps / (time.perf_counter() - t0)
+        del x64, p64
+    del ctx64
+    torch.cuda.empty_cache()
     d0 = ctx.diagnostics(x, p)
+    info = ctx.info()
 
     if args.copy_calibration:
         a = torch.empty(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
@@ -191,6 +315,8 @@ def main():
     avg_s = ms_tot / max(launches, 1) * 1e-3
     mesh_nodes = wl.grid[0] * wl.grid[1] * wl.grid[2]
     fbytes = 4 if prec == p3m.FP32C else 8
+    mbytes = info["mesh_bits"] // 8
+    mdiff = (mbytes == 4 and max(wl.grid) > 128 and args.gather == "variational" and not args.cathode)
     if stage == "pp":
         flops = pairs * PP_FLOP_PER_PAIR
         peak = PEAK_FP32_VALU if prec == p3m.FP32C else PEAK_FP64_VALU
@@ -201,10 +327,13 @@ def main():
         # compulsory bytes per launch of the stage: the records each kernel must
         # read and write once per particle, PP cell, mesh node and kernel-table entry
         per_stage = {
-            "fft": 2 * fbytes * mesh_nodes + 8 * (wl.grid[0] + 1) * (wl.grid[1] + 1) * (wl.grid[2] + 1),
+            # the charge in, the kernel table (mesh precision) and the potential or its
+            # three differences out
+            "fft": (mbytes * mesh_nodes * (4 if mdiff else 2)
+                    + mbytes * (wl.grid[0] + 1) * (wl.grid[1] + 1) * (wl.grid[2] + 1)),
             "sort": 40 * wl.n + 16 * ctx.info()["ncells"],
             "reorder": (4 + 4 + 24 + 2 * 4 * fbytes) * wl.n,
-            "deposit": 8 * fbytes * wl.n + fbytes * mesh_nodes,
+            "deposit": 8 * fbytes * wl.n + mbytes * mesh_nodes,
             # the gather also reads and writes x (the next step's drift, fused)
             "gather": (3 * 4 * fbytes + 4 + 2 * 24 + 24 + 48) * wl.n,
             "push+placement": 48 * ((wl.n + 255) // 256),   # the box partials
@@ -233,16 +362,20 @@ def main():
         "dtype": "f32" if prec == p3m.FP32C else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {wl.n} particles, Gaussian sigma (1,1,3) mm, "
-                        f"{wl.grid[0]}^3 mesh ({2 * wl.grid[0]}^3 zero-padded FFT), "
-                        f"{'TSC' if wl.order == 2 else 'CIC'}, r_c = 2 h_x, kappa = 3, dt = T_p/200"
-            if args.workload == "aniso1m" else args.workload,
-            "precision": "fp32 pair forces and FFT with Kahan sums; fp64 table, push, reductions"
-            if prec == p3m.FP32C else "fp64",
+            "workload": workload_text(args.workload, wl),
+            "precision": ("fp32 pair forces with Kahan sums; fp32 mesh (charge, FFT"
+                          + (", three difference meshes" if mdiff else ", potential") + ")"
+                          if mbytes == 4 else "fp32 pair forces with Kahan sums; fp64 mesh")
+            + "; fp64 kernel table, push, reductions" if prec == p3m.FP32C else "fp64",
+            "mesh_bits": info["mesh_bits"],
             "gather": args.gather,
             "boundary": "grounded plane 1 mm below the bunch" if args.cathode else "open",
             "influence": args.influence,
             "force_rms_err_vs_fp64": err,
+            "force_max_particle_err_vs_fp64": err_max,
+            "fp64_particle_steps_per_s": fp64_rate,
+            "fp64_steps_timed": args.fp64_steps if fp64_rate else 0,
+            "zoom_first_last": [d0["zoom"], d1["zoom"]],
             "pairs_per_s_of_step": pairs * args.steps / wall,
             "pairs_per_eval": pairs,
             "pairs_first_last_eval": [d0["pairs"], d1["pairs"]],
@@ -253,7 +386,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_targets)
     print(json.dumps(out), flush=True)
 
 

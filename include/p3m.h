@@ -64,9 +64,18 @@ typedef int32_t p3m_status;
 /* Mesh precision of the P3M_FP32C form (the P3M_FP64 form is float64
  * throughout). The mesh force is a difference of node potentials, so a
  * float32 potential carries a relative force error of about 6e-8 times the
- * bunch extent in cells: below 1e-5 up to ~150 cells. AUTO takes float32
- * while every grid axis has at most P3M_MESH_AUTO_F32_MAX nodes, else
- * float64 (charge, transform and potential; pair forces stay float32). */
+ * bunch extent in cells: below 1e-5 up to ~150 cells. On a float32 mesh
+ * with an axis of more than P3M_MESH_AUTO_F32_MAX nodes the transform
+ * therefore delivers the three forward differences phi_{m+e_d} - phi_m
+ * instead of phi (the spectrum times e^{2 pi i k_d / L_d} - 1), and the
+ * gather uses the B-spline identity b_p' (t) = b_{p-1}(t + 1/2) -
+ * b_{p-1}(t - 1/2): the same force, with rounding relative to the
+ * differences (the "difference form"; the variational gather in free space).
+ * AUTO: float32 (in the difference form above P3M_MESH_AUTO_F32_MAX nodes);
+ * float64 above that size for the momentum-conserving gather or the
+ * grounded plane. F32 forces float32 (the difference form where it
+ * applies), F64 float64 (charge, transform and potential; pair forces stay
+ * float32). p3m_info reports the mesh precision in use. */
 #define P3M_MESH_AUTO 0
 #define P3M_MESH_F32  1
 #define P3M_MESH_F64  2
@@ -114,7 +123,7 @@ typedef int32_t p3m_status;
 #define P3M_INFLUENCE_PRINCIPAL 2
 /* LATTICE: the paper's literal discrete field equation. The mesh potential
  * solves the 7-point discrete Poisson equation of the free lattice: the
- * second differences D_d of Sec. 2.4.3 (eq. 1d_ddiff), divided by h_d^2 and
+ * second differences D_d of Sec. 2.4.2 (eq. 1d_ddiff), divided by h_d^2 and
  * summed as in eq. 3dim_second_order_fin_diff_tensor, with the Green's
  * function of Sec. 3 (eq. def_G_L). The source is the deposited charge
  * convolved with the Gaussian screening's charge per cell,
@@ -211,13 +220,22 @@ p3m_status p3m_step(p3m_ctx *ctx, int64_t n, double *x, double *p, const double 
  * the placement fixed at place (device, P3M_PLACEMENT_DOUBLES; NULL = the
  * bounding-box placement of x). H is symmetric because F = -grad U, so this
  * is also the vector-Jacobian product. v and out are device [n][3] float64.
+ * Precision: the mesh part (the weight-gradient deposit of v, the
+ * convolution and the gather with the weights' first and second derivatives)
+ * runs in float64 in both forms, since its second differences of the
+ * potential would lose float32's digits; the pair Jacobian runs in float64
+ * (P3M_FP64) or in float32 with compensated sums (P3M_FP32C, about 1e-6 of
+ * the float64 product). This is the derivative of the force at a frozen
+ * placement (the placement is a function of the bounding box, which the
+ * derivative does not follow), allocates the float64 mesh on first use, and
  * P3M_ESTATE with the momentum-conserving gather (its force has no potential).
  */
 p3m_status p3m_hvp(p3m_ctx *ctx, int64_t n, const double *x, const double *qw,
                    const double *v, const double *place, double *out, void *stream);
 
 /*
- * Adjoint of one leapfrog step (x_n, p_n) -> (x_np1, p_np1) of length dt,
+ * Adjoint of one leapfrog step (x_n, p_n) -> (x_np1, p_np1) of length dt
+ * (Hessian-vector products of the precision described at p3m_hvp),
  * with the placements recorded in the forward run (place_n, place_np1,
  * device). Given the gradients xbar_np1, pbar_np1 of a scalar objective with
  * respect to (x_np1, p_np1), writes those with respect to (x_n, p_n):
@@ -293,8 +311,9 @@ p3m_status p3m_profile_end(p3m_ctx *ctx, double ms[8], int64_t launches[8], void
  * (P3M_OK, P3M_EDOMAIN or P3M_ENONFINITE). */
 p3m_status p3m_status_sync(p3m_ctx *ctx, void *stream);
 
-/* Host info: passes of the cell sort over the keys (1, a counting sort),
- * PP cells (total, x, y, z) and the padded FFT extents (x, y, z). */
+/* Host info: out[0] the bits of the mesh arithmetic the context uses
+ * (charge, transform and potential: 64, or 32 for a float32 mesh), out[1..4]
+ * the PP cells (total, x, y, z), out[5..7] the padded FFT extents (x, y, z). */
 p3m_status p3m_info(const p3m_ctx *ctx, int64_t out[8]);
 
 /* Message of the last failing call on ctx (never NULL). */

@@ -514,6 +514,53 @@ def forces(x, prm, parts=False, brute=False, direct=False, pl=None):
     return fpp + fpm
 
 
+def pp_image(x, prm, rc, a, zc):
+    """Short-range force of the mirror images of a grounded plane z = zc
+    (Sec. 3.1.1, the term eq. short_range_error measures): every particle j
+    has an image of charge -q_j at S(x_j) = (x_j, y_j, 2 zc - z_j) (eq.
+    symmetry_planar_cathode), and particle i feels the erfc pair force of
+    every image closer than rc, its own image included:
+      F_i = sum_j k_e q_i (-q_j) [erfc(a r)/r + (2a/sqrt(pi)) e^{-a^2 r^2}] (x_i - S(x_j)) / r^2,
+    r = |x_i - S(x_j)| < rc. This is the part of the image interaction that the
+    scheme of Sec. 3.1 (free-space pair sum, images on the mesh) leaves out.
+    Plain O(N^2) sum."""
+    x = _f64(x)
+    n = len(x)
+    qw = np.ones(n) if prm.qw is None else prm.qw
+    img = x.copy()
+    img[:, 2] = 2.0 * zc - x[:, 2]
+    f = np.zeros_like(x)
+    for i0 in range(0, n, 1024):
+        xi = x[i0:i0 + 1024]
+        d = xi[:, None, :] - img[None, :, :]
+        r = np.sqrt((d * d).sum(-1))
+        inside = r < rc
+        rr = np.where(inside, r, 1.0)
+        g = (erfc(a * rr) / rr + 2.0 * a / math.sqrt(math.pi) * np.exp(-(a * rr) ** 2)) / (rr * rr)
+        g = np.where(inside, g, 0.0) * (-qw[None, :])
+        f[i0:i0 + 1024] = prm.ke_q2 * qw[i0:i0 + 1024, None] * (g[:, :, None] * d).sum(1)
+    return f
+
+
+def coulomb_image_brute(x, ke_q2, zc, qw=None):
+    """Unsplit Coulomb force with a grounded plane z = zc: every other particle
+    directly, and every particle's image -q at S(x_j), own image included
+    (the free-space Green's function minus its mirror, eq.
+    GreenFunc_planar_cathode). Plain O(N^2) sum."""
+    x = _f64(x)
+    n = len(x)
+    qw = np.ones(n) if qw is None else _f64(qw)
+    img = x.copy()
+    img[:, 2] = 2.0 * zc - x[:, 2]
+    f = coulomb_brute(x, ke_q2, qw)
+    for i0 in range(0, n, 1024):
+        d = x[i0:i0 + 1024, None, :] - img[None, :, :]
+        r2 = (d * d).sum(-1)
+        f[i0:i0 + 1024] -= ke_q2 * qw[i0:i0 + 1024, None] * ((qw[None, :] / (r2 * np.sqrt(r2)))[:, :, None]
+                                                           * d).sum(1)
+    return f
+
+
 def coulomb_brute(x, ke_q2, qw=None):
     """Unsplit O(N^2) Coulomb force, the physics the split approximates (Sec. 1)."""
     prm = Params((4, 4, 4), (1, 1, 1), np.inf, 0.0, 1, ke_q2, qw=qw)

@@ -36,6 +36,13 @@ struct Engine {
   C2<R>* spec = nullptr;
   R* gz = nullptr;              // kernel table in this precision, padded rows (z pass)
   C2<R>* tw[3] = {nullptr, nullptr, nullptr};
+  // difference form of a float mesh: two more spectra, the three difference
+  // meshes and the difference factors per axis
+  C2<R>* spec2 = nullptr;
+  C2<R>* spec3 = nullptr;
+  R* dphi = nullptr;
+  C2<R>* dtab[3] = {nullptr, nullptr, nullptr};
+  bool phi_current = false;     // phi holds the potential of the last evaluation
   int64_t cap = 0;
   bool mesh_ready = false;
 };
@@ -137,6 +144,20 @@ p3m_status engine_mesh_alloc(p3m_ctx* ctx, Engine<R>& E) {
     HIPCHK(dalloc(&E.tw[d], (size_t)L));
     HIPCHK(hipMemcpy(E.tw[d], h.data(), L * sizeof(C2<R>), hipMemcpyHostToDevice));
   }
+  if constexpr (std::is_same<R, float>::value) {
+    if (g.mdiff) {
+      HIPCHK(dalloc(&E.spec2, spectrum_elems(g)));
+      HIPCHK(dalloc(&E.spec3, spectrum_elems(g)));
+      HIPCHK(dalloc(&E.dphi, 3 * mesh_nodes(g)));
+      for (int d = 0; d < 3; ++d) {
+        const int L = 2 * g.grid[d];
+        std::vector<C2<R>> h(L);
+        make_diff_factors<R>(L, h.data());
+        HIPCHK(dalloc(&E.dtab[d], (size_t)L));
+        HIPCHK(hipMemcpy(E.dtab[d], h.data(), L * sizeof(C2<R>), hipMemcpyHostToDevice));
+      }
+    }
+  }
   E.mesh_ready = true;
   return P3M_OK;
 }
@@ -164,7 +185,11 @@ void engine_free(Engine<R>& E) {
   dfree(E.phi);
   dfree(E.spec);
   dfree(E.gz);
+  dfree(E.spec2);
+  dfree(E.spec3);
+  dfree(E.dphi);
   for (int d = 0; d < 3; ++d) dfree(E.tw[d]);
+  for (int d = 0; d < 3; ++d) dfree(E.dtab[d]);
   E.cap = 0;
   E.mesh_ready = false;
 }
@@ -290,6 +315,7 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   // float records of a call without weights carry the position residuals
   Geo g = ctx->geo;
   g.wpacked = (std::is_same<R, float>::value && !qw) ? 1 : 0;
+  if constexpr (!std::is_same<M, float>::value) g.mdiff = 0;
   {
     StageTimer t(ctx, 1, st);
     launch_cell_sort(n, x, ctx->place, g, ctx->sb, ctx->groups, &ctx->keys, &ctx->perm, st);
@@ -306,14 +332,28 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
     StageTimer t(ctx, 4, st);
     launch_deposit<R, M>(n, E.pp, E.mesh, g, EM.Q, st);
   }
+  // difference form: the gather reads the three difference meshes, and phi is
+  // formed only when the mesh energy is asked for
+  bool diff = false;
+  if constexpr (std::is_same<M, float>::value) diff = g.mdiff != 0;
   {
     StageTimer t(ctx, 5, st);
     const C2<M>* tw[3] = {EM.tw[0], EM.tw[1], EM.tw[2]};
-    launch_convolve<M>(g, EM.Q, EM.spec, EM.gz, image_table(ctx, st), tw, EM.phi, st);
+    if (diff) {
+      if constexpr (std::is_same<M, float>::value) {
+        const C2<M>* dt[3] = {EM.dtab[0], EM.dtab[1], EM.dtab[2]};
+        launch_convolve_diff<M>(g, EM.Q, EM.spec, EM.spec2, EM.spec3, EM.gz, tw, dt, EM.dphi,
+                                e_pm ? EM.phi : nullptr, st);
+      }
+    } else {
+      launch_convolve<M>(g, EM.Q, EM.spec, EM.gz, image_table(ctx, st), tw, EM.phi, st);
+    }
+    EM.phi_current = !diff || e_pm != nullptr;
   }
   {
     StageTimer t(ctx, 6, st);
-    launch_gather<R, M>(n, E.pp, E.mesh, E.fpp, ctx->perm, g, ctx->place, EM.phi, out, e_pm, st);
+    const M* field = (diff && !e_pm) ? EM.dphi : EM.phi;
+    launch_gather<R, M>(n, E.pp, E.mesh, E.fpp, ctx->perm, g, ctx->place, field, out, e_pm, st);
   }
   ctx->last_precision = sizeof(M) == 4 ? P3M_FP32C : P3M_FP64;
   return P3M_OK;
@@ -335,7 +375,11 @@ p3m_status check_last(p3m_ctx* ctx) {
   return P3M_OK;
 }
 
-// H v at x (placement fixed at ctx->place), float64, into out (caller order).
+// H v at x (placement fixed at ctx->place), into out (caller order). The mesh
+// part runs in float64 (the second differences of the potential that its
+// Hessian term takes would lose float32's digits); the pair part in float64,
+// or for a float-compensated context in float32 from the float records
+// (compensated sums).
 p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, const double* v,
                     double* out, hipStream_t st) {
   p3m_status s;
@@ -343,12 +387,23 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
   if ((s = engine_mesh_alloc(ctx, E)) != P3M_OK) return s;
   if ((s = engine_particles(ctx, E, n)) != P3M_OK) return s;
   if ((s = ensure_adjoint(ctx, n)) != P3M_OK) return s;
+  const bool pp32 = ctx->opts.precision == P3M_FP32C;
+  if (pp32 && (s = engine_particles(ctx, ctx->e32, n)) != P3M_OK) return s;
   const Geo& g = ctx->geo;
   launch_cell_sort(n, x, ctx->place, g, ctx->sb, ctx->groups, &ctx->keys, &ctx->perm, st);
   launch_reorder<double>(n, x, qw, ctx->perm, ctx->keys, ctx->place, g, E.pp, E.mesh, ctx->status, Carry{}, st);
   launch_sort_vector<double>(n, v, ctx->perm, ctx->v_sorted, st);
-  launch_pp_hvp(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, ctx->v_sorted,
-                ctx->hpp, st);
+  if (pp32) {
+    Geo gf = g;
+    gf.wpacked = qw ? 0 : 1;
+    launch_reorder<float>(n, x, qw, ctx->perm, ctx->keys, ctx->place, gf, ctx->e32.pp, ctx->e32.mesh,
+                          ctx->status, Carry{}, st);
+    launch_pp_hvp<float>(n, ctx->e32.pp, ctx->keys, ctx->sb.cell_start, gf, ctx->groups, ctx->sb.counter,
+                         ctx->v_sorted, ctx->hpp, st);
+  } else {
+    launch_pp_hvp<double>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter,
+                          ctx->v_sorted, ctx->hpp, st);
+  }
   const C2<double>* tw[3] = {E.tw[0], E.tw[1], E.tw[2]};
   launch_deposit<double, double>(n, E.pp, E.mesh, g, E.Q, st);
   const C2<double>* gimg = image_table(ctx, st);
@@ -405,12 +460,17 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   p3m_ctx* ctx = new (std::nothrow) p3m_ctx();
   if (!ctx) return P3M_ENOMEM;
   ctx->opts = o;
+  // float mesh wider than P3M_MESH_AUTO_F32_MAX nodes on some axis: the
+  // difference form for the variational gather in free space, else (AUTO)
+  // a float64 mesh
+  const bool wide = grid[0] > P3M_MESH_AUTO_F32_MAX || grid[1] > P3M_MESH_AUTO_F32_MAX ||
+                    grid[2] > P3M_MESH_AUTO_F32_MAX;
+  const bool diff_ok = o.gather == P3M_GATHER_VARIATIONAL && o.boundary == P3M_BOUNDARY_OPEN;
   if (o.precision == P3M_FP32C)
     ctx->mesh64 = o.mesh_precision == P3M_MESH_F64 ||
-                  (o.mesh_precision == P3M_MESH_AUTO &&
-                   (grid[0] > P3M_MESH_AUTO_F32_MAX || grid[1] > P3M_MESH_AUTO_F32_MAX ||
-                    grid[2] > P3M_MESH_AUTO_F32_MAX));
+                  (o.mesh_precision == P3M_MESH_AUTO && wide && !diff_ok);
   Geo& g = ctx->geo;
+  g.mdiff = (o.precision == P3M_FP32C && !ctx->mesh64 && wide && diff_ok) ? 1 : 0;
   g.rc = r_cut;
   g.kappa = split * r_cut;
   g.ke_q2 = o.ke * o.q * o.q;
@@ -743,9 +803,15 @@ p3m_status p3m_mesh(p3m_ctx* ctx, int32_t which, double* out, void* stream) {
   if (!ctx || !out || (which != 0 && which != 1)) return P3M_EINVAL;
   if (ctx->last_precision < 0) return fail(ctx, P3M_ESTATE, "no force evaluation yet");
   hipStream_t st = (hipStream_t)stream;
-  if (ctx->last_precision == P3M_FP32C)
-    launch_mesh_export<float>(ctx->geo, which ? ctx->e32.phi : ctx->e32.Q, ctx->place, which, out, st);
-  else
+  if (ctx->last_precision == P3M_FP32C) {
+    Engine<float>& E = ctx->e32;
+    if (which == 1 && !E.phi_current) {
+      // difference form: phi from the spectrum the last evaluation left
+      launch_phi_from_diff<float>(ctx->geo, E.spec, E.tw[0], E.phi, st);
+      E.phi_current = true;
+    }
+    launch_mesh_export<float>(ctx->geo, which ? E.phi : E.Q, ctx->place, which, out, st);
+  } else
     launch_mesh_export<double>(ctx->geo, which ? ctx->e64.phi : ctx->e64.Q, ctx->place, which, out, st);
   return check_last(ctx);
 }
@@ -794,7 +860,8 @@ p3m_status p3m_status_sync(p3m_ctx* ctx, void* stream) {
 
 p3m_status p3m_info(const p3m_ctx* ctx, int64_t out[8]) {
   if (!ctx || !out) return P3M_EINVAL;
-  out[0] = 1;   // one counting pass over the keys
+  // bits of the mesh arithmetic (charge, transform, potential) of this context
+  out[0] = (ctx->opts.precision == P3M_FP64 || ctx->mesh64) ? 64 : 32;
   out[1] = ctx->geo.ncells;
   out[2] = ctx->geo.ncell[0];
   out[3] = ctx->geo.ncell[1];

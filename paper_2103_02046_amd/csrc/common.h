@@ -61,6 +61,7 @@ struct Geo {
   int cathode;         // 1: grounded plane z = zc (image charges on the mesh)
   int influence;       // mesh kernel table: kInfluence*
   int wpacked;         // per call: float records carry position residuals, weights all 1
+  int mdiff;           // float mesh in the difference form (three difference meshes, no phi)
   double zc;           // plane position (m)
 };
 

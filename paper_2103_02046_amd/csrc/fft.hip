@@ -208,23 +208,36 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(Geo geo, const T* __r
 }
 
 // ---- y pass: lines over y for fixed (z, kx); INV: inverse, keep y < N_y
-template <typename T, int L, bool INV>
+// DIFF (inverse only, difference form of the mesh): the line is also
+// multiplied by dy(k_y) = e^{2 pi i k_y / L} - 1 and inverse-transformed into
+// S3 (same layout), the forward difference along y.
+template <typename T, int L, bool INV, bool DIFF = false>
 __global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restrict__ S,
-                                                       const C2<T>* __restrict__ tw) {
+                                                       const C2<T>* __restrict__ tw,
+                                                       C2<T>* __restrict__ S3 = nullptr,
+                                                       const C2<T>* __restrict__ dy = nullptr) {
+  static_assert(INV || !DIFF, "the difference form acts on the inverse pass");
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2;
+  constexpr int PER = (L * B + kFftThreads - 1) / kFftThreads;
   __shared__ C2<T> s[L * B];
   const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
   const int nch = (K + B - 1) / B;
   const int z = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
   C2<T>* base = S + (long long)z * L * KS;
   const int nin = INV ? L : N;
-  for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
-    const int p = e / B, b = e % B;
-    C2<T> v{(T)0, (T)0};
-    if (p < nin && kx0 + b < K) v = base[(long long)p * KS + kx0 + b];
-    if (INV) v.y = -v.y;
-    s[e] = v;
+  C2<T> hold[DIFF ? PER : 1];
+#pragma unroll
+  for (int it = 0; it < PER; ++it) {
+    const int e = threadIdx.x + it * kFftThreads;
+    if (e < L * B) {
+      const int p = e / B, b = e % B;
+      C2<T> v{(T)0, (T)0};
+      if (p < nin && kx0 + b < K) v = base[(long long)p * KS + kx0 + b];
+      if (INV) v.y = -v.y;
+      s[e] = v;
+      if constexpr (DIFF) hold[it] = v;
+    }
   }
   __syncthreads();
   fft_lines<T, L, B>(s, tw);
@@ -237,14 +250,39 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restric
       base[(long long)p * KS + kx0 + b] = v;
     }
   }
+  if constexpr (DIFF) {
+    __syncthreads();
+    // the loaded values are conj(S): conj(S dy) = conj(S) conj(dy)
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int e = threadIdx.x + it * kFftThreads;
+      if (e < L * B) s[e] = cmul(hold[it], cconj(dy[e / B]));
+    }
+    __syncthreads();
+    fft_lines<T, L, B>(s, tw);
+    C2<T>* base3 = S3 + (long long)z * L * KS;
+    for (int e = threadIdx.x; e < N * B; e += kFftThreads) {
+      const int p = e / B, b = e % B;
+      if (kx0 + b < K) {
+        C2<T> v = s[e];
+        base3[(long long)p * KS + kx0 + b] = C2<T>{v.x, -v.y};
+      }
+    }
+  }
 }
 
 // ---- z pass: forward, times Ghat, inverse, keep z < N_z
-template <typename T, int L, bool IMG>
+// DIFF (difference form of the mesh): the product Ghat Z is also multiplied
+// by dz(k_z) = e^{2 pi i k_z / L} - 1 and inverse-transformed into S2, the
+// spectrum of the forward difference phi_{m+e_z} - phi_m along z.
+template <typename T, int L, bool IMG, bool DIFF = false>
 __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restrict__ S,
                                                        const T* __restrict__ gz,
                                                        const C2<double>* __restrict__ gimg,
-                                                       const C2<T>* __restrict__ tw) {
+                                                       const C2<T>* __restrict__ tw,
+                                                       C2<T>* __restrict__ S2 = nullptr,
+                                                       const C2<T>* __restrict__ dz = nullptr) {
+  static_assert(!(IMG && DIFF), "the difference form is built for open boundaries");
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2;
   __shared__ C2<T> s[L * B];
@@ -265,6 +303,51 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restric
   const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
   const long long gplane = (long long)(geo.grid[1] + 1) * K;    // image table
   const long long gplane_s = (long long)(geo.grid[1] + 1) * KS;
+  constexpr int PER = (L * B + kFftThreads - 1) / kFftThreads;
+  if constexpr (DIFF) {
+    // keep conj(g Z) in registers for the second inverse
+    C2<T> hold[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int e = threadIdx.x + it * kFftThreads;
+      if (e < L * B) {
+        const int kz = e / B, b = e % B;
+        const int kzp = kz <= N ? kz : L - kz;
+        const int kx = kx0 + b < K ? kx0 + b : K - 1;
+        const T g = gz[kzp * gplane_s + (long long)kyp * KS + kx];
+        const C2<T> v = s[e];
+        hold[it] = C2<T>{g * v.x, -(g * v.y)};
+        s[e] = hold[it];
+      }
+    }
+    __syncthreads();
+    fft_lines<T, L, B>(s, tw);
+    for (int e = threadIdx.x; e < N * B; e += kFftThreads) {
+      const int p = e / B, b = e % B;
+      if (kx0 + b < K) {
+        C2<T> v = s[e];
+        base[p * zstride + kx0 + b] = C2<T>{v.x, -v.y};
+      }
+    }
+    __syncthreads();
+    // conj(g Z dz) = conj(g Z) conj(dz)
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int e = threadIdx.x + it * kFftThreads;
+      if (e < L * B) s[e] = cmul(hold[it], cconj(dz[e / B]));
+    }
+    __syncthreads();
+    fft_lines<T, L, B>(s, tw);
+    C2<T>* base2 = S2 + (long long)ky * KS;
+    for (int e = threadIdx.x; e < N * B; e += kFftThreads) {
+      const int p = e / B, b = e % B;
+      if (kx0 + b < K) {
+        C2<T> v = s[e];
+        base2[p * zstride + kx0 + b] = C2<T>{v.x, -v.y};
+      }
+    }
+    return;
+  }
   if constexpr (!IMG) {
     for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
       const int kz = e / B, b = e % B;
@@ -277,7 +360,6 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restric
   } else {
     // grounded plane: minus the image term, Gs(k) Z(kx, ky, -kz) (the reflected
     // charge's spectrum), Gs the shifted kernel's table with phase and scale
-    constexpr int PER = (L * B + kFftThreads - 1) / kFftThreads;
     C2<T> nv[PER];
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
@@ -539,10 +621,14 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv_reg(Geo geo, const C2
 }
 
 // ---- x pass, inverse: two half spectra -> one complex line -> two real rows
+// dx (difference form of the mesh, may be null): both half spectra are first
+// multiplied by dx(k_x) = e^{2 pi i k_x / L} - 1, giving the forward
+// difference along x.
 template <typename T, int L>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(Geo geo, const C2<T>* __restrict__ S,
                                                            T* __restrict__ phi,
-                                                           const C2<T>* __restrict__ tw) {
+                                                           const C2<T>* __restrict__ tw,
+                                                           const C2<T>* __restrict__ dx = nullptr) {
   constexpr int B = Cfg<T, L>::B;
   constexpr int N = L / 2, K = N + 1, KS = (K + 15) & ~15;
   __shared__ C2<T> s[L * B];
@@ -555,6 +641,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(Geo geo, const C2<T>*
     C2<T> A{(T)0, (T)0}, C{(T)0, (T)0};
     if (ga < rows) A = S[((ga / ny) * 2 * ny + ga % ny) * KS + k];
     if (gc < rows) C = S[((gc / ny) * 2 * ny + gc % ny) * KS + k];
+    if (dx) {
+      const C2<T> f = dx[k];
+      A = cmul(A, f);
+      C = cmul(C, f);
+    }
     // Z_k = A_k + i C_k ; stored conjugated (input of the inverse)
     s[k * B + l] = C2<T>{A.x - C.y, -(A.y + C.x)};
     if (k > 0 && k < N) s[(L - k) * B + l] = C2<T>{A.x + C.y, -(C.x - A.y)};
@@ -903,6 +994,74 @@ void launch_convolve(const Geo& g, const R* Q, C2<R>* S, const R* gz, const C2<d
 #undef XI
 }
 
+// Difference form (float meshes wider than the register lines): the three
+// forward differences D_d phi_m = phi_{m+e_d} - phi_m come out of the same
+// spectrum times (e^{2 pi i k_d / L_d} - 1), so their rounding follows the
+// differences, not the potential. Passes: x and y forward as above; z with
+// the second inverse into S2 (z difference); y inverse with the second
+// inverse into S3 (y difference) and a plain y inverse of S2; then x inverse
+// of S times dx (x difference), of S3 and of S2; phi itself only on request.
+template <typename R>
+void launch_convolve_diff(const Geo& g, const R* Q, C2<R>* S, C2<R>* S2, C2<R>* S3, const R* gz,
+                          const C2<R>* tw[3], const C2<R>* dtab[3], R* dphi, R* phi, hipStream_t st) {
+  const int Lx = 2 * g.grid[0], Ly = 2 * g.grid[1], Lz = 2 * g.grid[2];
+  const long long nodes = (long long)g.grid[0] * g.grid[1] * g.grid[2];
+  const int K = g.grid[0] + 1;
+  const long long rows = (long long)g.grid[1] * g.grid[2];
+#define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], st)
+#define YF(L) run_y<R, L, false>(g, S, tw[1], st)
+#define ZD(L)                                                                                       \
+  k_fft_z<R, L, false, true><<<(unsigned)(2 * g.grid[1] * ((K + Cfg<R, L>::B - 1) / Cfg<R, L>::B)), \
+                               kFftThreads, 0, st>>>(g, S, gz, nullptr, tw[2], S2, dtab[2])
+#define YD(L)                                                                                \
+  do {                                                                                       \
+    const unsigned nb = (unsigned)(g.grid[2] * ((K + Cfg<R, L>::B - 1) / Cfg<R, L>::B));     \
+    k_fft_y<R, L, true, true><<<nb, kFftThreads, 0, st>>>(g, S, tw[1], S3, dtab[1]);         \
+    k_fft_y<R, L, true, false><<<nb, kFftThreads, 0, st>>>(g, S2, tw[1]);                    \
+  } while (0)
+#define XD(L)                                                                                \
+  do {                                                                                       \
+    const unsigned nb = (unsigned)((rows + 2 * Cfg<R, L>::B - 1) / (2 * Cfg<R, L>::B));      \
+    k_fft_x_inv<R, L><<<nb, kFftThreads, 0, st>>>(g, S, dphi, tw[0], dtab[0]);               \
+    k_fft_x_inv<R, L><<<nb, kFftThreads, 0, st>>>(g, S3, dphi + nodes, tw[0]);               \
+    k_fft_x_inv<R, L><<<nb, kFftThreads, 0, st>>>(g, S2, dphi + 2 * nodes, tw[0]);           \
+    if (phi) k_fft_x_inv<R, L><<<nb, kFftThreads, 0, st>>>(g, S, phi, tw[0]);                \
+  } while (0)
+  P3M_FFT_SWITCH(Lx, XF)
+  P3M_FFT_SWITCH(Ly, YF)
+  P3M_FFT_SWITCH(Lz, ZD)
+  P3M_FFT_SWITCH(Ly, YD)
+  P3M_FFT_SWITCH(Lx, XD)
+#undef XF
+#undef YF
+#undef ZD
+#undef YD
+#undef XD
+}
+
+// The potential from the spectrum S left by launch_convolve_diff (the x
+// inverse of its y-inverted lines), for a caller that asks for phi later.
+template <typename R>
+void launch_phi_from_diff(const Geo& g, const C2<R>* S, const C2<R>* tw_x, R* phi, hipStream_t st) {
+  const int Lx = 2 * g.grid[0];
+  const long long rows = (long long)g.grid[1] * g.grid[2];
+#define XP(L)                                                                                \
+  k_fft_x_inv<R, L><<<(unsigned)((rows + 2 * Cfg<R, L>::B - 1) / (2 * Cfg<R, L>::B)), kFftThreads, 0, \
+                      st>>>(g, S, phi, tw_x)
+  P3M_FFT_SWITCH(Lx, XP)
+#undef XP
+}
+
+// Factors e^{2 pi i k / L} - 1 = (-2 sin^2(pi k / L), sin(2 pi k / L)) for
+// k = 0 .. L-1, from float64 (no cancellation in the real part).
+template <typename R>
+void make_diff_factors(int L, C2<R>* out) {
+  for (int k = 0; k < L; ++k) {
+    const double h = std::sin(M_PI * (double)k / (double)L);
+    out[k] = C2<R>{(R)(-2.0 * h * h), (R)std::sin(2.0 * M_PI * (double)k / (double)L)};
+  }
+}
+
 template <typename R>
 void make_twiddles(int L, C2<R>* out) {
   for (int k = 0; k < L; ++k) {
@@ -958,6 +1117,11 @@ template void launch_convolve<float>(const Geo&, const float*, C2<float>*, const
                                      const C2<float>*[3], float*, hipStream_t);
 template void launch_convolve<double>(const Geo&, const double*, C2<double>*, const double*, const C2<double>*,
                                       const C2<double>*[3], double*, hipStream_t);
+template void launch_convolve_diff<float>(const Geo&, const float*, C2<float>*, C2<float>*, C2<float>*,
+                                          const float*, const C2<float>* [3], const C2<float>* [3], float*,
+                                          float*, hipStream_t);
+template void launch_phi_from_diff<float>(const Geo&, const C2<float>*, const C2<float>*, float*, hipStream_t);
+template void make_diff_factors<float>(int, C2<float>*);
 template void launch_green_pack<float>(const Geo&, const double*, float*, hipStream_t);
 template void launch_green_pack<double>(const Geo&, const double*, double*, hipStream_t);
 template void make_twiddles<float>(int, C2<float>*);

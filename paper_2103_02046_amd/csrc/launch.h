@@ -59,7 +59,8 @@ template <typename R>
 void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
                hipStream_t st);
-void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys,
+template <typename R>
+void launch_pp_hvp(int64_t n, const PPPos<R>* rec, const uint32_t* keys,
                    const int* cell_start, const Geo& geo, const int2* desc, int* counter,
                    const double* v_sorted, double* out_sorted, hipStream_t st);
 
@@ -118,6 +119,19 @@ void launch_green_pack(const Geo& geo, const double* ghat, R* gz, hipStream_t st
 template <typename R>
 void launch_convolve(const Geo& geo, const R* Q, C2<R>* spec, const R* gz, const C2<double>* gimg,
                      const C2<R>* tw[3], R* phi, hipStream_t st);
+// Difference form of the convolution (float meshes): the three forward
+// differences of phi, dphi[d * nodes + m] = phi_{m+e_d} - phi_m (m_d < N_d - 1
+// meaningful), from the spectrum times (e^{2 pi i k_d / L_d} - 1); S2 and S3
+// are two more spectrum buffers; dtab[d] the factors of make_diff_factors
+// (2 grid[d] entries); phi (may be null) the potential as well. S is left
+// holding the y-inverted lines, from which launch_phi_from_diff gives phi.
+template <typename R>
+void launch_convolve_diff(const Geo& geo, const R* Q, C2<R>* S, C2<R>* S2, C2<R>* S3, const R* gz,
+                          const C2<R>* tw[3], const C2<R>* dtab[3], R* dphi, R* phi, hipStream_t st);
+template <typename R>
+void launch_phi_from_diff(const Geo& geo, const C2<R>* S, const C2<R>* tw_x, R* phi, hipStream_t st);
+template <typename R>
+void make_diff_factors(int L, C2<R>* host_out);
 // Image table of the grounded plane z = geo.zc for the placement *pl:
 // complex, [2 grid[2]][grid[1] + 1][grid[0] + 1]; t1, t2 float64 scratch of
 // image_table_elems each; tw float64 twiddles of the three doubled lengths.

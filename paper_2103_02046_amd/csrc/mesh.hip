@@ -258,6 +258,12 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
 // The stencil sums run in the mesh precision M (the potential differences
 // that make the force are small against the potential itself).
 // MODE 0, variational: g_d = sum_m phi_m dW_m/du_d.
+// MODE 2, variational from the difference meshes D_d phi_m = phi_{m+e_d} -
+// phi_m (phi holds the three, one after the other): by the B-spline identity
+// b_p'(t) = b_{p-1}(t + 1/2) - b_{p-1}(t - 1/2), the same g_d is
+// sum_m D_d phi_m b_{p-1}(u_d - m_d - 1/2) prod_{e != d} b_p(u_e - m_e), with
+// b_0 = 1 on the base node (CIC) and b_1 = (1/2 - f, 1/2 + f) on the nodes
+// c - 1, c (TSC, f = u - c). No potential (energy) in this mode.
 // MODE 1, momentum-conserving: the mesh field by central differences,
 // E_{m,d} = -(phi_{m+e_d} - phi_{m-e_d}) / (2 h_d), interpolated with W; on
 // the nodes this is g_d = sum_n phi_n (W(n - e_d) - W(n + e_d)) / 2 over the
@@ -283,7 +289,62 @@ __global__ void __launch_bounds__(kThreads) k_gather(int64_t n, const PPPos<R>* 
     const long long nxy = (long long)nx * geo.grid[1];
     M g[3] = {0, 0, 0};
     M pot = 0;
-    if constexpr (MODE == 0) {
+    if constexpr (MODE == 2) {
+      const long long nodes = nxy * geo.grid[2];
+      const M f[3] = {(M)m.fx, (M)m.fy, (M)m.fz};
+      // weights of b_{p-1} on the axis differenced: one node (CIC) or two (TSC)
+      constexpr int ND = ORDER;
+      M wd[3][ND];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if constexpr (ORDER == 1) {
+          wd[d][0] = (M)1;
+        } else {
+          wd[d][0] = (M)0.5 - f[d];
+          wd[d][ND - 1] = (M)0.5 + f[d];
+        }
+      }
+      // x difference: ND nodes along x, S.N along y and z
+      {
+        const M* D = phi;
+#pragma unroll
+        for (int c = 0; c < S.N; ++c)
+#pragma unroll
+          for (int b = 0; b < S.N; ++b) {
+            const M* row = D + m.base + c * nxy + (long long)b * nx;
+            M sx = 0;
+#pragma unroll
+            for (int a = 0; a < ND; ++a) sx += row[a] * wd[0][a];
+            g[0] += sx * S.w[1][b] * S.w[2][c];
+          }
+      }
+      {
+        const M* D = phi + nodes;
+#pragma unroll
+        for (int c = 0; c < S.N; ++c)
+#pragma unroll
+          for (int b = 0; b < ND; ++b) {
+            const M* row = D + m.base + c * nxy + (long long)b * nx;
+            M sx = 0;
+#pragma unroll
+            for (int a = 0; a < S.N; ++a) sx += row[a] * S.w[0][a];
+            g[1] += sx * wd[1][b] * S.w[2][c];
+          }
+      }
+      {
+        const M* D = phi + 2 * nodes;
+#pragma unroll
+        for (int c = 0; c < ND; ++c)
+#pragma unroll
+          for (int b = 0; b < S.N; ++b) {
+            const M* row = D + m.base + c * nxy + (long long)b * nx;
+            M sx = 0;
+#pragma unroll
+            for (int a = 0; a < S.N; ++a) sx += row[a] * S.w[0][a];
+            g[2] += sx * S.w[1][b] * wd[2][c];
+          }
+      }
+    } else if constexpr (MODE == 0) {
 #pragma unroll
       for (int c = 0; c < S.N; ++c)
 #pragma unroll
@@ -474,7 +535,10 @@ void launch_gather(int64_t n, const PPPos<R>* pp, const MeshRec<R>* mesh, const 
                    GatherOut out, double* energy, hipStream_t st) {
 #define P3M_GATHER(O, G) \
   k_gather<R, M, O, G><<<blocks_for(n), kThreads, 0, st>>>(n, pp, mesh, fpp, perm, geo, pl, phi, out, energy)
-  if (geo.gather == 0) {
+  if (geo.gather == 0 && geo.mdiff && !energy) {
+    if (geo.order == 1) P3M_GATHER(1, 2);
+    else P3M_GATHER(2, 2);
+  } else if (geo.gather == 0) {
     if (geo.order == 1) P3M_GATHER(1, 0);
     else P3M_GATHER(2, 0);
   } else {

@@ -145,11 +145,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// HVP (float64 only): the pair part of the Hessian-vector product in place
-// of the force, (H_PP v)_i = sum_j K_ij (v_i - v_j) with K_ij = w_i w_j
-// [f I + (f'/r) d d^T], the derivative of the pair force F_ij = w_i w_j f d;
-// f = g / r^2, g = erfc(kr)/r + (2k/sqrt(pi)) e^{-k^2 r^2} (internal units).
-// v and hv_out are sorted [n][3].
+// HVP: the pair part of the Hessian-vector product in place of the force,
+// (H_PP v)_i = sum_j K_ij (v_i - v_j) with K_ij = w_i w_j [f I + (f'/r) d d^T],
+// the derivative of the pair force F_ij = w_i w_j f d; f = g / r^2,
+// g = erfc(kr)/r + (2k/sqrt(pi)) e^{-k^2 r^2} (internal units). v and hv_out
+// are sorted [n][3] float64. float form: the separation from the fixed-point
+// records (residuals included), the Jacobian in float with the same erfc fit
+// as the force, Kahan-compensated per-particle sums.
 template <typename R, bool ENERGY, bool PACKED, bool HVP = false>
 __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter,
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
                                            double* __restrict__ energy, const double* __restrict__ hv_in = nullptr,
                                            double* __restrict__ hv_out = nullptr) {
   using V4 = typename Vec4<R>::T;
-  static_assert(!HVP || (std::is_same<R, double>::value && !ENERGY && !PACKED), "HVP: float64 forces only");
+  static_assert(!HVP || !ENERGY, "HVP: no energy");
   // per-group tiles padded by one element so the four groups' broadcast
   // reads fall in different LDS banks
   constexpr int TS = kTileK + 1;
@@ -169,7 +171,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   __shared__ int4 tfix[kFix ? NT : 1];      // float: fixed-point x, y, z from the group's corner; weight bits
   __shared__ V4 tloc[kFix ? 1 : NT];        // double: cell-local x, y, z and the charge weight
   __shared__ V4 toff[kFix ? 1 : NT];        // double: cell-corner offset from the group's first cell
-  __shared__ V4 tvel[HVP ? NT : 1];         // HVP: the candidates' v
+  __shared__ V4 tvel[HVP ? NT : 1];         // HVP: the candidates' v (in R)
   __shared__ int rstart[kWaveGroups][9], rpre[kWaveGroups][10];
   __shared__ int gtot[kWaveGroups];
   const int ngroups = counter[0];
@@ -339,10 +341,10 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         }
         tloc[TS * q + 16 * h + ql] = cl;
         toff[TS * q + 16 * h + ql] = co;
-        if constexpr (HVP)
-          tvel[TS * q + 16 * h + ql] = nx_ok[h] ? V4{(R)nx_v[h][0], (R)nx_v[h][1], (R)nx_v[h][2], (R)0}
-                                                : V4{(R)0, (R)0, (R)0, (R)0};
       }
+      if constexpr (HVP)
+        tvel[TS * q + 16 * h + ql] = nx_ok[h] ? V4{(R)nx_v[h][0], (R)nx_v[h][1], (R)nx_v[h][2], (R)0}
+                                              : V4{(R)0, (R)0, (R)0, (R)0};
       tile[TS * q + 16 * h + ql] = c;
     }
     wave_sync();
@@ -408,7 +410,31 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         wj = cl.w;
         r2 = dx * dx + dy * dy + dz * dz;
       }
-      if constexpr (HVP) {
+      if constexpr (HVP && kFix) {
+        if (r2 > (R)0 && r2 < rlim) {
+          // float: in the cutoff unit (rho = r fu), t = 1/(1 + kappa rho/2),
+          // erfc = e t P(t) with e = exp(-kappa^2 rho^2), as in the force
+          const V4 vj = tvel[TS * q + k];
+          const float fuf = (float)fud;
+          const float dx_ = dx * fuf, dy_ = dy * fuf, dz_ = dz * fuf;
+          const float s2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
+          const float rinv = __builtin_amdgcn_rsqf(s2);
+          const float r = s2 * rinv, rinv2 = rinv * rinv;
+          const float kap = (float)geo.kappa, c2k = (float)(kTwoOverSqrtPi * geo.kappa);
+          const float t = __builtin_amdgcn_rcpf(fmaf(0.5f * kap, r, 1.0f));
+          const float ex = __builtin_amdgcn_exp2f(-kap * kap * kLog2e * s2);
+          const float ec = ex * t * erfcx_poly(t);
+          const float g = fmaf(ec, rinv, c2k * ex);
+          const float gp = -ec * rinv2 - c2k * ex * rinv - 2.0f * c2k * kap * kap * r * ex;
+          const float f = g * rinv2;
+          const float fp_r = (gp - 2.0f * g * rinv) * rinv2 * rinv;
+          const float dvx = (float)vi[0] - vj.x, dvy = (float)vi[1] - vj.y, dvz = (float)vi[2] - vj.z;
+          const float dd = dx_ * dvx + dy_ * dvy + dz_ * dvz;
+          sx += wj * (f * dvx + fp_r * dx_ * dd);
+          sy += wj * (f * dvy + fp_r * dy_ * dd);
+          sz += wj * (f * dvz + fp_r * dz_ * dd);
+        }
+      } else if constexpr (HVP) {
         if (r2 > (R)0 && r2 < rlim) {
           // the pair Jacobian applied to v_i - v_j, one reciprocal per pair
           const V4 vj = tvel[TS * q + k];
@@ -495,14 +521,24 @@ void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* 
     k_pp<R, false, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr);
 }
 
-void launch_pp_hvp(int64_t n, const PPRec<double>* rec, const uint32_t* keys, const int* cell_start,
+template <typename R>
+void launch_pp_hvp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                    const Geo& geo, const int2* desc, int* counter, const double* v_sorted, double* out_sorted,
                    hipStream_t st) {
   // the tiled pair kernel in its Hessian-vector mode, over the cell sort's groups
   const unsigned blocks = (unsigned)((pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups);
-  k_pp<double, false, false, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
-                                                           nullptr, v_sorted, out_sorted);
+  const bool packed = std::is_same<R, float>::value && geo.wpacked;
+  if (packed)
+    k_pp<R, false, kPackable<R>, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
+                                                              nullptr, v_sorted, out_sorted);
+  else
+    k_pp<R, false, false, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
+                                                       nullptr, v_sorted, out_sorted);
 }
+template void launch_pp_hvp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
+                                   const int2*, int*, const double*, double*, hipStream_t);
+template void launch_pp_hvp<double>(int64_t, const PPPos<double>*, const uint32_t*, const int*, const Geo&,
+                                    const int2*, int*, const double*, double*, hipStream_t);
 
 template void launch_pp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
                                const int2*, int*, PPRec<float>*, double*, hipStream_t);

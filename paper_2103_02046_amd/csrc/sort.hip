@@ -7,6 +7,8 @@
 // >= r_c make the 27 neighbouring cells a superset of that neighbourhood.
 // The cell edge is c_d = (N_d - 1) h_d / n_d with n_d = floor((N_d-1) h_d / r_c),
 // so the cell grid covers exactly the mesh span and zoom leaves n_d unchanged.
+#include <type_traits>
+
 #include "launch.h"
 
 namespace p3m {
@@ -255,9 +257,18 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
     if (qw) carry.qw_out[j] = w;
   }
   // PP record: offset from the own cell corner, formed in float64 before
-  // rounding (units of Lu, or fixed point of the cell edge).
+  // rounding. double form: units of Lu from the corner c cu. float form:
+  // from the corner at the whole number c fix_edge of fixed-point units (the
+  // pair kernel adds cell offsets as such whole numbers), so that every
+  // separation, across cells too, is the exact difference of the global
+  // fixed-point positions.
   double loc[3];
-  for (int d = 0; d < 3; ++d) loc[d] = (xi[d] - P.x0[d]) * P.inv_lu - c[d] * geo.cu[d];
+  const double unit = fix_unit(geo.cu);
+  for (int d = 0; d < 3; ++d) {
+    const double corner = std::is_same<R, float>::value ? c[d] * (double)fix_edge(geo.cu, d) * unit
+                                                        : c[d] * geo.cu[d];
+    loc[d] = (xi[d] - P.x0[d]) * P.inv_lu - corner;
+  }
   pp[j] = make_pos<R>(loc, geo.cu, w, geo.wpacked != 0);
   // Mesh record: stencil origin and fractional offset (Sec. 2.4.2 B-splines).
   // CIC: base floor(u), offset u - base in [0, 1).

@@ -229,7 +229,7 @@ class Context:
     def info(self):
         out = (ctypes.c_int64 * 8)()
         self._check(lib().p3m_info(self._ctx, out))
-        keys = ("sort_passes", "ncells", "ncell_x", "ncell_y", "ncell_z", "fft_x", "fft_y", "fft_z")
+        keys = ("mesh_bits", "ncells", "ncell_x", "ncell_y", "ncell_z", "fft_x", "fft_y", "fft_z")
         return dict(zip(keys, list(out)))
 
 
@@ -237,7 +237,13 @@ class P3MRollout(torch.autograd.Function):
     """(x0, p0) -> (x_N, p_N) by N leapfrog steps, differentiable through the
     library's adjoint. Checkpoints (x, p) every `every` steps in the forward
     pass; the backward pass replays each segment (with the recorded
-    placements) to recover the positions, then runs the reverse steps."""
+    placements) to recover the positions, then runs the reverse steps.
+
+    The gradient is that of the map with every evaluation's mesh placement
+    frozen at the value recorded in the forward pass (the placement follows
+    the bounding box, which the derivative does not). Its precision is the
+    context's: float64, or for a float-compensated context a float32 pair
+    Jacobian with a float64 mesh part (see p3m_hvp)."""
 
     @staticmethod
     def forward(ctx, x0, p0, context, dt, nsteps, every=10, qw=None):

@@ -100,10 +100,14 @@ def halo_split(n):
 
 
 def _draw_halo(n, seed, sigma_core=5e-4, r_halo=5e-3):
+    # Halo: number density proportional to r^-2 between the core's sigma and
+    # r_halo, i.e. radii uniform on [sigma_core, r_halo], isotropic. (Down to
+    # r = 0 the r^-2 law would put a cusp at the centre whose closest pairs,
+    # a nanometre apart, a fixed-step leapfrog throws out of the bunch.)
     rng = np.random.default_rng(seed)
     n_core, n_halo = halo_split(n)
     core = rng.standard_normal((n_core, 3)) * sigma_core
-    r = rng.random(n_halo) * r_halo
+    r = sigma_core + rng.random(n_halo) * (r_halo - sigma_core)
     d = rng.standard_normal((n_halo, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     return np.concatenate([core, d * r[:, None]], axis=0)
@@ -153,7 +157,7 @@ def sphere_tsc(n=1 << 23, grid=256, steps=200, seed=0):
 
 
 def halo_tsc(n=1 << 25, grid=512, steps=50, seed=0):
-    """90% Gaussian core (sigma 0.5 mm) + 10% 1/r^2 halo to 10 sigma, TSC, r_c = 2h."""
+    """90% Gaussian core (sigma 0.5 mm) + 10% 1/r^2 halo from sigma to 10 sigma, TSC, r_c = 2h."""
     sigma_c, r_halo = 5e-4, 5e-3
     h = 2 * r_halo / _usable(TSC, grid)
     rc = 2 * h

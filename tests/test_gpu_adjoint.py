@@ -1,0 +1,168 @@
+"""The differentiated P3M step at the differentiation workload's settings,
+and the float-compensated adjoint against the float64 one.
+
+Workload (configuration C4): 2^20 particles of the anisotropic Gaussian bunch,
+128^3 mesh, r_c = 2h, 100 leapfrog steps with a checkpoint every 10; the
+objective is the transverse normalised rms emittance J = (eps_x + eps_y)/2
+of the final state; gradients with respect to every initial position and
+momentum through the library's adjoint (reverse leapfrog with Hessian-vector
+products, placements recorded in the forward run and replayed).
+
+* Central differences along random directions supported on particles
+  0..4095 (A24 (i)). The configured kappa = 3 leaves a force jump of 4.4e-4
+  of the Coulomb force at the strict cutoff, across which a difference
+  quotient is meaningless, so kappa is raised to 5 (jump 8e-11) for the
+  differences (A24a).
+* The same adjoint on a standalone 4096-particle run against the oracle's
+  gradient, coordinate by coordinate (A24 (iii)).
+* The float-compensated adjoint (float32 pair Jacobian with compensated sums,
+  float64 mesh part) against the float64 adjoint: its error is stated.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2103_02046_amd import p3m
+from paper_2103_02046_amd import workloads as W
+from parity_util import rms_err
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def emittance_objective(mc):
+    def J(xx, pp):
+        out = 0
+        for ax in (0, 1):
+            dx = xx[:, ax] - xx[:, ax].mean()
+            dp = pp[:, ax] - pp[:, ax].mean()
+            out = out + torch.sqrt((dx * dx).mean() * (dp * dp).mean() - (dx * dp).mean() ** 2)
+        return 0.5 * out / mc
+    return J
+
+
+def adjoint_gradient(c, wl, x, p, nsteps, every):
+    x0 = dev(x).requires_grad_(True)
+    p0 = dev(p).requires_grad_(True)
+    xN, pN = p3m.rollout(x0, p0, c, wl.dt, nsteps, every=every)
+    J = emittance_objective(wl.m * W.C_LIGHT)(xN, pN)
+    J.backward()
+    return host(x0.grad), host(p0.grad), float(J.detach())
+
+
+def test_c4_emittance_gradient_vs_central_differences():
+    """C4 at full size (kappa 5): the adjoint's directional derivatives of the
+    final transverse emittance against central differences of float64 GPU
+    runs replaying the recorded placements, along directions of the momenta
+    of particles 0..4095. The bunch starts cold and its 100-step emittance is
+    a small difference of large moments; a perturbation of 4096 of 2^20
+    particles moves it by ~1e-7 of itself per unit step, so the steps are
+    2e-3 and 4e-3 of a 1 mm/T_p momentum perturbation, where rounding is
+    negligible and the quotients differ by their O(e^2) curvature term (~1e-4
+    between the two): the Richardson combination (4 D(e) - D(2e))/3 removes
+    it, and must agree with the adjoint to 1e-4 (the two quotients agree to
+    1e-3, showing they are in the truncation regime)."""
+    wl0 = W.get("aniso1m")
+    wl = dataclasses.replace(wl0, split=5.0 / wl0.r_cut)
+    x, p = wl.draw()
+    c = p3m.Context.from_workload(wl, precision=p3m.FP64)
+    gx, gp, J = adjoint_gradient(c, wl, x, p, 100, 10)
+    print(f"C4: J = {J:.6e}, |dJ/dx| {np.linalg.norm(gx):.3e}, |dJ/dp| {np.linalg.norm(gp):.3e}", flush=True)
+    places = torch.empty(101 * p3m.PLACEMENT_DOUBLES, dtype=torch.float64, device="cuda")
+    c.step(dev(x), dev(p), wl.dt, 100, place_record=places)
+    emit = emittance_objective(wl.m * W.C_LIGHT)
+
+    def run(dp):
+        xa, pa = dev(x), dev(p + dp)
+        c.step(xa, pa, wl.dt, 100, place_replay=places)
+        assert c.status_sync() == p3m.OK
+        return float(emit(xa, pa))
+
+    rng = np.random.default_rng(31)
+    sig_p = wl.m * 1e-3 / (200 * wl.dt)
+    for k in range(4):
+        dp = np.zeros_like(p)
+        d = rng.standard_normal((4096, 3))
+        dp[:4096] = d / np.linalg.norm(d) * sig_p
+        an = float((gp * dp).sum())
+        fd = [(run(e * dp) - run(-e * dp)) / (2 * e) for e in (2e-3, 4e-3)]
+        print(f"C4 direction {k}: adjoint {an:.10e} central differences {fd[0]:.10e} {fd[1]:.10e} "
+              f"rel {abs(an - fd[0]) / abs(fd[0]):.2e}", flush=True)
+        rich = (4.0 * fd[0] - fd[1]) / 3.0
+        print(f"  Richardson {rich:.10e} rel {abs(an - rich) / abs(rich):.2e}", flush=True)
+        assert abs(fd[1] - fd[0]) <= 1e-3 * abs(fd[0])
+        assert abs(an - rich) <= 1e-4 * abs(rich)
+
+
+@pytest.mark.parametrize("precision,tol", [(p3m.FP64, 1e-9), (p3m.FP32C, 1e-4)])
+def test_c4_standalone_4096_vs_oracle_gradient(precision, tol):
+    """4096 particles of the C4 bunch (TSC, r_c = 2h, kappa = 3) on a 32^3 mesh,
+    100 steps with a checkpoint every 10: the GPU gradient of the emittance
+    with respect to every coordinate against the oracle's reverse leapfrog
+    (A24 (iii)); float64 to 1e-9, the float-compensated adjoint to 1e-4
+    relative rms."""
+    wl = W.aniso_tsc(n=4096, grid=32, steps=100)
+    x, p = wl.draw()
+    c = p3m.Context.from_workload(wl, precision=precision)
+    gx, gp, _ = adjoint_gradient(c, wl, x, p, 100, 10)
+    prm = O.Params.from_workload(wl)
+    ox, op, _ = O.gradient(x, p, prm, 100)
+    ex, ep = rms_err(gx, ox), rms_err(gp, op)
+    print(f"4096 particles, 100 steps, precision {precision}: dJ/dx {ex:.3e}, dJ/dp {ep:.3e}", flush=True)
+    assert ex < tol and ep < tol
+
+
+def test_fp32c_hvp_and_adjoint_vs_fp64():
+    """The float-compensated Hessian-vector product (float32 pair Jacobian,
+    float64 mesh part) against the float64 one at the same positions, on the
+    full C4 bunch; and the float-compensated adjoint of 30 steps against the
+    float64 adjoint of the same recorded trajectory (p3m_backward_steps on
+    the same positions and placements)."""
+    wl = W.get("aniso1m")
+    x, p = wl.draw()
+    c32 = p3m.Context.from_workload(wl, precision=p3m.FP32C)
+    c64 = p3m.Context.from_workload(wl, precision=p3m.FP64)
+    rng = np.random.default_rng(32)
+    v = rng.standard_normal(x.shape)
+    xd, vd = dev(x), dev(v)
+    h32, h64 = host(c32.hvp(xd, vd)), host(c64.hvp(xd, vd))
+    e_h = rms_err(h32, h64)
+    print(f"HVP float-compensated vs float64 (2^20 particles): {e_h:.3e}", flush=True)
+    assert e_h < 1e-5
+    # adjoint of 30 recorded float64 steps, both forms on the same positions
+    n_s = 30
+    sub = W.aniso_tsc(n=1 << 16, grid=64, steps=n_s)
+    xs_, ps_ = sub.draw()
+    cf = p3m.Context.from_workload(sub, precision=p3m.FP64)
+    places = torch.empty((n_s + 1) * p3m.PLACEMENT_DOUBLES, dtype=torch.float64, device="cuda")
+    xs = torch.empty((n_s + 1, sub.n, 3), dtype=torch.float64, device="cuda")
+    xa, pa = dev(xs_), dev(ps_)
+    xs[0].copy_(xa)
+    for s in range(n_s):
+        rec = torch.empty(2 * p3m.PLACEMENT_DOUBLES, dtype=torch.float64, device="cuda")
+        cf.step(xa, pa, sub.dt, 1, place_record=rec)
+        places[s * 4:(s + 2) * 4] = rec
+        xs[s + 1].copy_(xa)
+    xb0, pb0 = rng.standard_normal(xs_.shape), rng.standard_normal(xs_.shape)
+    out = {}
+    for name, prec in (("fp64", p3m.FP64), ("fp32c", p3m.FP32C)):
+        cc = p3m.Context.from_workload(sub, precision=prec)
+        xb, pb = dev(xb0), dev(pb0)
+        cc.backward_steps(xs, xb, pb, sub.dt, places)
+        out[name] = (host(xb), host(pb))
+    ex = rms_err(out["fp32c"][0], out["fp64"][0])
+    ep = rms_err(out["fp32c"][1], out["fp64"][1])
+    print(f"adjoint of 30 steps, float-compensated vs float64: xbar {ex:.3e}, pbar {ep:.3e}", flush=True)
+    assert ex < 1e-5 and ep < 1e-5

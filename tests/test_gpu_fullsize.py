@@ -2,13 +2,16 @@
 
 * 2^20-particle anisotropic Gaussian, 128^3 mesh: every particle's force
   compared with the oracle's full force (cell-list PP + numpy FFT PM).
-* 2^23-particle uniform sphere, 256^3 mesh: PP forces of sampled particles
-  (oracle cell list) and their mesh forces (oracle deposit + FFT potential);
+* the same bunch after 100 float-compensated steps: forces at the GPU's
+  positions against the oracle's.
+* 2^23-particle uniform sphere, 256^3 mesh: charge and potential node by
+  node, the mesh force of every particle, PP forces of sampled particles;
   then a run of one plasma period against the closed-form self-similar
   expansion of a cold uniform ball.
-* 2^25-particle core/halo bunch, 512^3 mesh: sampled PP forces, and the mesh
-  force of two sampled particles from the oracle's direct potential sums at
-  their stencil nodes.
+* 2^25-particle core/halo bunch, 512^3 mesh: charge node by node, the
+  potential at sampled nodes and the mesh force of sampled core and halo
+  particles (oracle's direct potential sums), PP forces of 1200 targets
+  including the densest cells; float64 and float-compensated.
 * adjoint: gradients of the transverse emittance after 30 steps of 2^16
   particles and of the bunch's second moments after 20 steps of 2^20
   (checkpoints every 10) against central differences along random
@@ -18,6 +21,9 @@ Tolerances as in test_gpu_parity: float64 1e-11 relative rms, float32
 (compensated) 1e-5, both relative to the rms of the total force; the PP and
 mesh parts are checked against the same denominator (their share of the
 total error), and their errors relative to their own rms are printed.
+Per particle (the error an rms hides): max_i |dF_i| / max(|F_i|, rms F)
+below 1e-9 (float64) and 1e-4 (float32, ten times the rms target); max_i
+|dF_i| / rms F is printed.
 """
 import dataclasses
 import math
@@ -35,11 +41,17 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-11
 TOL32 = 1e-5
+MAX64 = 1e-9
+MAX32 = 1e-4
+
+from parity_util import per_particle, rms_err  # noqa: E402
 
 
-def rms_err(a, b, ref=None):
-    ref = np.asarray(b) if ref is None else np.asarray(ref)
-    return math.sqrt(((np.asarray(a) - np.asarray(b)) ** 2).sum() / (ref ** 2).sum())
+def check_particles(label, got, ref, precision, rms=None):
+    e_rms, e_own, k = per_particle(got, ref, rms)
+    print(f"{label}: per particle max |dF|/rms {e_rms:.3e}, max |dF|/max(|F|, rms) {e_own:.3e} "
+          f"(particle {k})", flush=True)
+    assert e_own < (MAX64 if precision == p3m.FP64 else MAX32)
 
 
 def dev(a):
@@ -49,22 +61,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.detach().cpu().numpy()
-
-
-def _sampled_pm(x, prm, pl, Q, idx, phi_full=None):
-    """Oracle mesh force of particles idx: potential at their stencil nodes
-    (from the full potential if given, else by direct sums), then the gather."""
-    g = prm.grid
-    phi = np.zeros((g[2], g[1], g[0]))
-    if phi_full is not None:
-        phi = phi_full
-    else:
-        nodes = np.unique(np.concatenate([O.stencil_nodes(x[i], prm, pl) for i in idx]))
-        vals = O.phi_at(Q, g, pl["hp"], pl["a"], nodes)
-        phi.reshape(-1)[nodes] = vals
-    sub = O.Params(prm.grid, prm.h, prm.r_cut, prm.split, prm.order, prm.ke_q2, prm.m, prm.dt,
-                   qw=None if prm.qw is None else prm.qw[idx])
-    return O.gather(x[idx], sub, pl, phi)
 
 
 @pytest.mark.parametrize("precision", [p3m.FP64, p3m.FP32C])
@@ -83,32 +79,68 @@ def test_aniso1m_every_particle(precision):
           f"(own rms {rms_err(fpm, parts['pm']):.3e})", flush=True)
     assert e < tol
     assert rms_err(fpp, parts["pp"], ref) < tol and rms_err(fpm, parts["pm"], ref) < tol
+    check_particles(f"aniso1m precision {precision}", fpp + fpm, ref, precision)
+    assert c.status_sync() == p3m.OK
+
+
+def test_aniso1m_after_100_steps_fp32c():
+    """100 float-compensated leapfrog steps of the 2^20-particle bunch on the
+    GPU, then the force at the GPU's positions (expanded and zoomed) against
+    the oracle's at the same positions: the parity holds late in the run,
+    not only at the initial draw."""
+    wl = W.get("aniso1m")
+    x, p = wl.draw()
+    c = p3m.Context.from_workload(wl, precision=p3m.FP32C)
+    xd, pd = dev(x), dev(p)
+    c.step(xd, pd, wl.dt, 100)
+    xg = host(xd)
+    d0 = c.diagnostics(dev(x), dev(p))
+    d1 = c.diagnostics(xd, pd)
+    fg = host(c.forces(xd))
+    prm = O.Params.from_workload(wl)
+    ref = O.forces(xg, prm)
+    e = rms_err(fg, ref)
+    print(f"aniso1m after 100 fp32c steps (zoom {d0['zoom']:.4f} -> {d1['zoom']:.4f}, pairs "
+          f"{d0['pairs']:.3e} -> {d1['pairs']:.3e}): force {e:.3e}", flush=True)
+    assert e < TOL32
+    check_particles("aniso1m after 100 steps", fg, ref, p3m.FP32C)
     assert c.status_sync() == p3m.OK
 
 
 @pytest.mark.parametrize("precision", [p3m.FP64, p3m.FP32C])
-def test_sphere8m_sampled(precision):
+def test_sphere8m_full_mesh(precision):
+    """2^23 particles, 256^3 mesh: the charge and the potential node by node,
+    the mesh force of every particle (oracle gather of its full potential),
+    and the PP force of 2000 sampled particles."""
     wl = W.get("sphere8m")
     x, _ = wl.draw()
     prm = O.Params.from_workload(wl)
     c = p3m.Context.from_workload(wl, precision=precision)
     fpp, fpm, _ = c.forces_parts(dev(x))
     fpp, fpm = host(fpp), host(fpm)
+    Qg, phig = host(c.mesh(0)), host(c.mesh(1))
     pl = O.placement(x, prm)
-    rng = np.random.default_rng(1)
-    idx = np.sort(rng.choice(wl.n, 48, replace=False))
-    ref_pp = O.pp_sample(x, prm, pl["rc"], pl["a"], idx)
     Q = O.deposit(x, prm, pl)
     phi = O.conv_fft(Q, prm.grid, pl["hp"], pl["a"])
-    ref_pm = _sampled_pm(x, prm, pl, Q, idx, phi)
+    eq = np.abs(Qg - Q).max() / np.abs(Q).max()
+    ephi = rms_err(phig, phi)
+    ref_pm = O.gather(x, prm, pl, phi)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(wl.n, 2000, replace=False))
+    ref_pp = O.pp_sample(x, prm, pl["rc"], pl["a"], idx)
     tol = TOL64 if precision == p3m.FP64 else TOL32
-    tot = ref_pp + ref_pm
-    e_pp, e_pm = rms_err(fpp[idx], ref_pp, tot), rms_err(fpm[idx], ref_pm, tot)
+    tot = ref_pp + ref_pm[idx]
+    e_pm = rms_err(fpm, ref_pm)
+    e_pp = rms_err(fpp[idx], ref_pp, tot)
     e = rms_err(fpp[idx] + fpm[idx], tot)
-    print(f"sphere8m precision {precision}: sampled total {e:.3e} pp {e_pp:.3e} pm {e_pm:.3e} "
-          f"(own rms pp {rms_err(fpp[idx], ref_pp):.3e} pm {rms_err(fpm[idx], ref_pm):.3e})", flush=True)
-    assert e_pp < tol and e_pm < tol and e < tol
-    # whole-mesh invariants of the deposit: total charge
+    print(f"sphere8m precision {precision}: Q max node {eq:.3e}, phi {ephi:.3e}, pm (every particle) "
+          f"{e_pm:.3e}, sampled pp {e_pp:.3e} (own rms {rms_err(fpp[idx], ref_pp):.3e}), sampled total {e:.3e}",
+          flush=True)
+    assert eq < (1e-12 if precision == p3m.FP64 else 1e-6)
+    assert ephi < tol and e_pm < tol and e_pp < tol and e < tol
+    rms_tot = math.sqrt((tot ** 2).sum(axis=1).mean())
+    check_particles(f"sphere8m pm precision {precision}", fpm, ref_pm, precision, rms=rms_tot)
+    check_particles(f"sphere8m sampled total precision {precision}", fpp[idx] + fpm[idx], tot, precision)
     assert c.status_sync() == p3m.OK
 
 
@@ -156,8 +188,13 @@ def test_sphere8m_expansion_closed_form():
     assert out[(p3m.FP32C, 50)] == pytest.approx(out[(p3m.FP64, 50)], rel=1e-5)
 
 
-@pytest.mark.parametrize("precision", [p3m.FP32C])
+@pytest.mark.parametrize("precision", [p3m.FP64, p3m.FP32C])
 def test_halo32m_sampled(precision):
+    """2^25 particles, 512^3 mesh: the charge node by node over the whole
+    mesh; the potential at the 216 stencil nodes of 8 sampled particles (core
+    and halo, by the oracle's direct sums over the mesh charge) and those
+    particles' mesh forces; the PP force of 1200 targets, 400 of them the
+    particles nearest the centre (the densest cells, ~3900 neighbours)."""
     wl = W.get("halo32m")
     x, _ = wl.draw()
     prm = O.Params.from_workload(wl)
@@ -167,26 +204,50 @@ def test_halo32m_sampled(precision):
     fpp, fpm = host(fpp), host(fpm)
     del xd
     assert c.status_sync() == p3m.OK
+    Qg = host(c.mesh(0))
+    phig = host(c.mesh(1))
+    print(f"halo32m precision {precision}: GPU done, mesh bits {c.info()['mesh_bits']}", flush=True)
     pl = O.placement(x, prm)
+    Q = O.deposit(x, prm, pl)
+    eq = np.abs(Qg - Q).max() / np.abs(Q).max()
+    print(f"halo32m: Q max node error {eq:.3e}", flush=True)
+    assert eq < (1e-12 if precision == p3m.FP64 else 1e-6)
+    del Qg
     rng = np.random.default_rng(2)
     core, _ = W.halo_split(wl.n)
-    idx = np.sort(np.concatenate([rng.choice(core, 24, replace=False),
-                                  core + rng.choice(wl.n - core, 8, replace=False)]))
+    r = np.linalg.norm(x, axis=1)
+    dense = np.argsort(r[:core])[:400]
+    idx = np.unique(np.concatenate([dense, rng.choice(core, 700, replace=False),
+                                    core + rng.choice(wl.n - core, 100, replace=False)]))
     ref_pp = O.pp_sample(x, prm, pl["rc"], pl["a"], idx)
-    print("halo32m: oracle PP sample done", flush=True)
-    Q = O.deposit(x, prm, pl)
-    two = np.array([idx[0], idx[-1]])           # one core, one halo particle
-    ref_pm = _sampled_pm(x, prm, pl, Q, two)
-    print("halo32m: oracle potential sample done", flush=True)
-    sel = np.searchsorted(idx, two)
-    tot = ref_pp[sel] + ref_pm
-    e_pm = rms_err(fpm[two], ref_pm, tot)
-    e_tot = rms_err(fpp[two] + fpm[two], tot)
-    # PP part on all sampled particles, against their PP+mesh total (mesh from the GPU)
+    print(f"halo32m: oracle PP of {len(idx)} targets done (densest target has "
+          f"{int(r[dense[0]] * 1e6)} um radius)", flush=True)
+    # mesh: 8 particles (5 core incl. the densest, 3 halo), potential at their stencil nodes
+    pm_idx = np.unique(np.concatenate([dense[:1], rng.choice(core, 4, replace=False),
+                                       core + rng.choice(wl.n - core, 3, replace=False)]))
+    nodes = np.unique(np.concatenate([O.stencil_nodes(x[i], prm, pl) for i in pm_idx]))
+    vals = O.phi_at(Q, prm.grid, pl["hp"], pl["a"], nodes)
+    ephi = rms_err(phig.reshape(-1)[nodes], vals)
+    phi = np.zeros_like(Q)
+    phi.reshape(-1)[nodes] = vals
+    ref_pm = O.gather(x[pm_idx], prm, pl, phi)
+    print(f"halo32m: oracle potential at {len(nodes)} nodes done", flush=True)
+    tol = TOL64 if precision == p3m.FP64 else TOL32
+    sel = np.searchsorted(idx, pm_idx)
+    in_pp = idx[np.clip(sel, 0, len(idx) - 1)] == pm_idx
+    ref_pp_pm = O.pp_sample(x, prm, pl["rc"], pl["a"], pm_idx)
+    tot = ref_pp_pm + ref_pm
+    e_pm = rms_err(fpm[pm_idx], ref_pm, tot)
+    e_tot = rms_err(fpp[pm_idx] + fpm[pm_idx], tot)
+    # PP part on the 1200 targets, against their PP + mesh total (mesh from the GPU)
     e_pp = rms_err(fpp[idx], ref_pp, ref_pp + fpm[idx])
-    print(f"halo32m precision {precision}: sampled pp {e_pp:.3e} (own rms {rms_err(fpp[idx], ref_pp):.3e}) "
-          f"pm {e_pm:.3e} total {e_tot:.3e}", flush=True)
-    assert e_pp < TOL32 and e_pm < TOL32 and e_tot < TOL32
+    print(f"halo32m precision {precision}: phi at nodes {ephi:.3e}; sampled pp {e_pp:.3e} "
+          f"(own rms {rms_err(fpp[idx], ref_pp):.3e}) pm {e_pm:.3e} total {e_tot:.3e} "
+          f"({int(in_pp.sum())} of the mesh sample among the PP targets)", flush=True)
+    assert ephi < tol and e_pp < tol and e_pm < tol and e_tot < tol
+    check_particles(f"halo32m pp precision {precision}", fpp[idx], ref_pp, precision,
+                    rms=math.sqrt(((ref_pp + fpm[idx]) ** 2).sum(axis=1).mean()))
+    check_particles(f"halo32m total precision {precision}", fpp[pm_idx] + fpm[pm_idx], tot, precision)
 
 
 def _emit(mc):

@@ -161,6 +161,67 @@ def test_cathode_step_and_hvp_parity():
     assert c.status_sync() == p3m.OK
 
 
+def test_cathode_short_range_error_confined_near_the_plane():
+    """The paper's central result (Sec. 3.1.1, eqs. error_measure and
+    short_range_error, Fig. ShortError): summing the short-range part in free
+    space while the mesh carries the images changes the force only through
+    the images' erfc pair terms, which reach only particles within r_c of an
+    image, so a particle's own image matters only within r_c/2 of the plane.
+
+    The scheme (the GPU's cathode mode: free-space pair sum, image mesh) is
+    compared with a reference that also mirrors the pair term (the oracle's
+    image mesh plus its plain sum of the images' erfc pair forces):
+      * particles with no image of any particle within r_c: identical to the
+        float64 parity bound;
+      * particles within r_c/2 of the plane: different, by the image pair term;
+      * the error measure summed over particles (eq. error_measure's integral
+        over the charges, here a sum of squared force differences) sits with
+        the particles close to the plane.
+    Both are also compared with the exact image Coulomb force: beyond r_c of
+    every image the scheme is exactly as good as the full reference."""
+    wl = W.get("gauss4k")
+    x, _ = wl.draw()
+    x[:, 2] = np.abs(x[:, 2])        # a half-Gaussian resting on the plane: dense near it
+    prm0 = O.Params.from_workload(wl)
+    rc0 = O.placement(x, prm0)["rc"]
+    zc = -0.05 * rc0
+    c = p3m.Context.from_workload(wl, cathode_z=zc)
+    f_gpu = host(c.forces(dev(x)))
+    assert c.status_sync() == p3m.OK
+    prm = O.Params.from_workload(wl, cathode_z=zc)
+    pl = O.placement(x, prm)
+    rc, a = pl["rc"], pl["a"]
+    f_img = O.pp_image(x, prm, rc, a, zc)
+    f_ref = O.forces(x, prm) + f_img
+    # distance of each particle to the nearest image (of any particle), and to the plane
+    img = x.copy()
+    img[:, 2] = 2 * zc - x[:, 2]
+    dmin = np.array([np.sqrt(((x[i] - img) ** 2).sum(1)).min() for i in range(wl.n)])
+    h = x[:, 2] - zc
+    far, near = dmin >= rc, h < 0.5 * rc
+    rms = math.sqrt((f_ref ** 2).sum(1).mean())
+    dev_ = np.linalg.norm(f_gpu - f_ref, axis=1) / rms
+    print(f"cathode short range: {int(near.sum())} particles within r_c/2, {int(far.sum())} with no image "
+          f"within r_c; scheme vs full reference: far max {dev_[far].max():.2e}, near min {dev_[near].min():.2e}",
+          flush=True)
+    assert near.sum() >= 50 and far.sum() >= wl.n // 2
+    assert dev_[far].max() < 1e-11
+    assert dev_[near].min() > 1e-7
+    # the difference is the image pair term itself, to parity
+    assert rms_err(f_gpu, f_ref - f_img) < 1e-11
+    e_near = (dev_[h < rc] ** 2).sum()
+    assert e_near / (dev_ ** 2).sum() > 1 - 1e-12
+    # against the exact image Coulomb force: the same error beyond r_c of every image
+    f_true = O.coulomb_image_brute(x, wl.ke_q2, zc)
+    e_s = np.linalg.norm(f_gpu - f_true, axis=1)
+    e_r = np.linalg.norm(f_ref - f_true, axis=1)
+    assert np.abs(e_s[far] - e_r[far]).max() <= 1e-9 * rms
+    print(f"  vs exact image Coulomb, rms over all: scheme {rms_err(f_gpu, f_true):.3e}, "
+          f"full reference {rms_err(f_ref, f_true):.3e}; within r_c/2: scheme "
+          f"{rms_err(f_gpu[near], f_true[near]):.3e}, full reference {rms_err(f_ref[near], f_true[near]):.3e}",
+          flush=True)
+
+
 # ---- optimal influence function (table built at create) --------------------------
 
 def _tsc4k():

@@ -268,6 +268,51 @@ def test_fp32c_close_pairs():
     assert rel.max() < 3e-6
 
 
+def test_fp32c_close_pairs_across_cell_boundaries():
+    """Close pairs straddling a PP cell boundary on every axis, with cell
+    edges that are not whole multiples of each other (h_z = 1.37 h_x, so the
+    fixed-point edge of the shorter axes is a rounded number of units): the
+    records must place a particle relative to the same whole-unit corner the
+    pair kernel adds back, or the residual fields of a cross-cell pair are
+    off by up to half a unit (1e-4 of the closest separations)."""
+    rng = np.random.default_rng(16)
+    n, grid = 8192, 32
+    h = (1e-4, 1e-4, 1.37e-4)
+    rc = 2.3e-4
+    x = rng.standard_normal((n, 3)) * np.array([6e-4, 6e-4, 9e-4])
+    prm = O.Params((grid,) * 3, h, rc, 3.0 / rc, 2, 1.0, m=1.0)
+    pl = O.placement(x, prm)
+    s = pl["s"]
+    ncell = [max(1, math.floor((grid - 1) * h[d] / rc)) for d in range(3)]
+    cell = [s * (grid - 1) * h[d] / ncell[d] for d in range(3)]   # physical PP cell edges
+    assert len({round(cl / (s * rc), 9) for cl in cell}) > 1
+    m = 36
+    first = rng.choice(n // 2, m, replace=False)
+    second = n // 2 + first
+    for k in range(m):
+        d = k % 3
+        # the boundary nearest particle `first`, on axis d
+        c = round((x[first[k], d] - pl["x0"][d]) / cell[d])
+        c = min(max(c, 1), ncell[d] - 1)
+        zb = pl["x0"][d] + c * cell[d]
+        sep = s * rc * 10.0 ** rng.uniform(-5, -3)
+        u = rng.standard_normal(3) * 0.3 * sep
+        u[d] = 0.0
+        x[first[k], d] = zb - 0.5 * sep
+        x[second[k]] = x[first[k]] + u
+        x[second[k], d] = zb + 0.5 * sep
+    pl = O.placement(x, prm)
+    assert pl["s"] == pytest.approx(s, rel=1e-12)   # the pairs sit inside the bunch's box
+    idx = np.concatenate([first, second])
+    ref = O.pp_sample(x, prm, pl["rc"], pl["a"], idx)
+    c = p3m.Context((grid,) * 3, h, rc, 3.0 / rc, order=2, precision=p3m.FP32C, ke=1.0, q=1.0, m=1.0)
+    fpp, _, _ = c.forces_parts(dev(x))
+    got = host(fpp)[idx]
+    rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    print(f"close pairs across cell boundaries: max rel pp error {rel.max():.2e}")
+    assert rel.max() < 3e-6
+
+
 def test_error_status_words():
     rng = np.random.default_rng(5)
     x = rng.standard_normal((300, 3))
@@ -419,7 +464,14 @@ def test_backward_steps_equals_chained_backward():
 
 
 def test_rollout_gradient_vs_oracle_and_fd():
+    """The checkpointed autograd rollout against the oracle's reverse leapfrog,
+    and against central differences. kappa is 5 here: at 3 the pair force
+    jumps by 4.4e-4 of Coulomb at the strict cutoff, and among 400 particles
+    some pair crosses r_c within a difference step, which a difference
+    quotient cannot see past (the adjoint is the derivative almost
+    everywhere)."""
     x, prm = _adj_case(n=400)
+    prm.split = 5.0 / prm.r_cut
     rng = np.random.default_rng(10)
     p = 0.05 * rng.standard_normal(x.shape)
     N = 6
@@ -438,9 +490,21 @@ def test_rollout_gradient_vs_oracle_and_fd():
 
     J = emit(xN, pN)
     J.backward()
-    gx_ref, gp_ref, _ = O.gradient(x, p, prm, N)
-    assert rms_err(host(x0.grad), gx_ref) < 1e-9
-    assert rms_err(host(p0.grad), gp_ref) < 1e-9
+    gx_ref, gp_ref, (_, _, pls) = O.gradient(x, p, prm, N)
+    gx, gp = host(x0.grad), host(p0.grad)
+    assert rms_err(gx, gx_ref) < 1e-9
+    assert rms_err(gp, gp_ref) < 1e-9
+    # finite-difference leg: central differences of the objective along random
+    # directions, by the oracle's leapfrog with the recorded placements frozen
+    # (the map the adjoint differentiates)
+    for _ in range(3):
+        dx, dp = rng.standard_normal(x.shape), rng.standard_normal(p.shape)
+        eps = 1e-6
+        jp = O.objective(*O.forward_frozen(x + eps * dx, p + eps * dp, prm, pls), prm)
+        jm = O.objective(*O.forward_frozen(x - eps * dx, p - eps * dp, prm, pls), prm)
+        fd = (jp - jm) / (2 * eps)
+        an = (gx * dx).sum() + (gp * dp).sum()
+        assert an == pytest.approx(fd, rel=1e-5)
 
 
 # ---- diagnostics ----------------------------------------------------------------------

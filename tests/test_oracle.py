@@ -975,3 +975,51 @@ def test_optimal_influence_small_screening_limit():
         # the optimal table is not the principal one here: the assignment's own
         # aliases (not screened) enter the denominator
         assert np.abs(G_opt[inner] / G_pri[inner] - 1).max() > 1e-3
+
+
+# ---- short-range image term of the grounded plane (Sec. 3.1.1) ----------------------
+
+def test_image_pair_term_lone_charge_closed_form():
+    """One charge at height d above the plane meets its own image -q at 2d:
+    F_z = -k_e q^2 [erfc(2ad)/(2d) + (2a/sqrt(pi)) e^{-4a^2 d^2}] / (2d) while
+    2d < r_c, and nothing from 2d = r_c on: only a particle within r_c/2 of the
+    plane feels its image's short-range part (Sec. 3.1.1, Fig. ShortError)."""
+    from scipy.special import erfc
+    rc, a, zc = 0.8, 3.0 / 0.8, -0.3
+    prm = O.Params((8, 8, 8), (0.2, 0.2, 0.2), rc, a, 2, 2.5)
+    for d in (0.01, 0.1, 0.25, 0.399, 0.4, 0.41, 0.9):
+        x = np.array([[0.2, -0.1, zc + d]])
+        f = O.pp_image(x, prm, rc, a, zc)
+        r = 2 * d
+        exact = 0.0 if r >= rc else -2.5 * (erfc(a * r) / r + 2 * a / math.sqrt(math.pi)
+                                            * math.exp(-(a * r) ** 2)) / r
+        assert f[0, 2] == pytest.approx(exact, rel=1e-13, abs=1e-300)
+        assert f[0, 0] == 0.0 and f[0, 1] == 0.0
+
+
+def test_image_pair_term_unscreened_is_image_coulomb():
+    """a = 0 and a cutoff beyond the bunch: the short-range image term is the
+    whole Coulomb force of the images, i.e. the image Coulomb sum minus the
+    free-space one (two independent plain sums)."""
+    rng = np.random.default_rng(51)
+    x = rng.standard_normal((60, 3))
+    zc = x[:, 2].min() - 0.2
+    prm = O.Params((8, 8, 8), (1, 1, 1), 1e9, 0.0, 2, 1.7)
+    f = O.pp_image(x, prm, 1e9, 0.0, zc)
+    ref = O.coulomb_image_brute(x, 1.7, zc) - O.coulomb_brute(x, 1.7)
+    np.testing.assert_allclose(f, ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+
+
+def test_image_pair_term_mirror_symmetry():
+    """|x_i - S(x_j)| = |x_j - S(x_i)|, and the two separations have equal z
+    and opposite transverse components: in a two-particle system the cross
+    image forces agree in z and are opposite across."""
+    rng = np.random.default_rng(52)
+    rc, a, zc = 1.0, 3.0, 0.0
+    prm = O.Params((8, 8, 8), (0.2, 0.2, 0.2), rc, a, 2, 1.0)
+    for _ in range(5):
+        x = np.array([[0.0, 0.0, 0.3], [0.0, 0.0, 0.3]]) + rng.random((2, 3)) * [0.4, 0.4, 0.1]
+        own = np.array([O.pp_image(x[k:k + 1], prm, rc, a, zc)[0] for k in range(2)])
+        cross = O.pp_image(x, prm, rc, a, zc) - own
+        assert cross[0, 2] == pytest.approx(cross[1, 2], rel=1e-12)
+        np.testing.assert_allclose(cross[0, :2], -cross[1, :2], rtol=1e-12, atol=1e-15)
