@@ -186,6 +186,27 @@ p3m_status p3m_forces(p3m_ctx *ctx, int64_t n, const double *x, const double *qw
                       double *f, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * force as p3m_forces, computed by the same kernels, with every per-call
+ * work buffer (cell keys, permutation, PP work groups, particle records,
+ * pair forces) in a static device array of P3M_NOALLOC_SCRATCH_BYTES per GPU
+ * instead of context buffers; the mesh buffers are the context's, allocated
+ * by p3m_create. This call allocates and frees nothing. The work buffers
+ * take 12 bytes per particle plus 48 (P3M_FP32C) or 96 (P3M_FP64) for the
+ * records and 8 per PP work group (n/16 plus the PP cells); above the array
+ * the call returns P3M_EINVAL (about 1.1 million particles in P3M_FP32C on a
+ * 128^3 mesh, 0.6 million in P3M_FP64). The array is shared by every call on
+ * one GPU, whatever the context or stream, and keeps the last call's
+ * contents (every call overwrites what it reads): calls that overlap on one
+ * GPU race. Each GPU the library runs on holds its array until the process
+ * ends. Errors as p3m_forces (no P3M_ENOMEM).
+ */
+#define P3M_NOALLOC_SCRATCH_BYTES (64u << 20)
+p3m_status p3m_forces_noalloc(p3m_ctx *ctx, int64_t n, const double *x, const double *qw,
+                              double *f, void *stream);
+
+/*
  * As p3m_forces, with the two parts written separately (either may be NULL)
  * and an optional fixed placement: if place_in (device, P3M_PLACEMENT_DOUBLES
  * float64) is not NULL the mesh is placed there instead of on the bounding

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -86,6 +87,7 @@ struct p3m_ctx {
   Engine<double> e64;
   uint32_t* keys = nullptr;     // sorted keys of the last evaluation
   uint32_t* perm = nullptr;     // sorted -> caller index of the last evaluation
+  int device = 0;               // the GPU the context's buffers live on
   int last_precision = -1;      // mesh precision of the last evaluation
   bool mesh64 = false;          // float32 particle path with a float64 mesh
   // stage timing
@@ -96,7 +98,35 @@ struct p3m_ctx {
   int prof_next = 0;
 };
 
+// Work buffers of p3m_forces_noalloc: one static array per GPU (each device
+// holds its own copy of a __device__ variable), found on the host through
+// hipGetSymbolAddress once per device. In host code `scratch` is only a
+// stand-in for the symbol; kernels get the address kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[P3M_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev` (must be the current device the first
+// time), or nullptr with the HIP error in *err.
+void* scratch_for(int dev, hipError_t* err) {
+  *err = hipSuccess;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
 
 size_t mesh_nodes(const Geo& g) { return (size_t)g.grid[0] * g.grid[1] * g.grid[2]; }
 
@@ -419,6 +449,67 @@ p3m_status hvp_core(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, 
 
 }  // namespace
 
+namespace {
+
+// Layout of the noalloc work buffers for n particles with records in R:
+// sort keys in input order, sorted keys, permutation, PP work groups, PP
+// positions, mesh records and PP forces, each at a 256-byte boundary.
+template <typename R>
+struct NoallocLayout {
+  size_t keys_in, keys, perm, groups, pp, mesh, fpp, total;
+  NoallocLayout(int64_t n, const Geo& g) {
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+      const size_t at = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return at;
+    };
+    keys_in = take((size_t)n * sizeof(uint32_t));
+    keys = take((size_t)n * sizeof(uint32_t));
+    perm = take((size_t)n * sizeof(uint32_t));
+    groups = take((size_t)pp_group_bound(n, g) * sizeof(int2));
+    pp = take((size_t)n * sizeof(PPPos<R>));
+    mesh = take((size_t)n * sizeof(MeshRec<R>));
+    fpp = take((size_t)n * sizeof(PPRec<R>));
+    total = off;
+  }
+};
+
+template <typename R, typename M>
+p3m_status forces_noalloc(p3m_ctx* ctx, Engine<M>& EM, int64_t n, const double* x, const double* qw,
+                          double* f, unsigned char* base, hipStream_t st) {
+  const NoallocLayout<R> lay(n, ctx->geo);
+  if (lay.total > (size_t)P3M_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, P3M_EINVAL,
+                "p3m_forces_noalloc: " + std::to_string(n) + " particles need " + std::to_string(lay.total) +
+                    " bytes of work buffers, above the static " + std::to_string(P3M_NOALLOC_SCRATCH_BYTES));
+  if (!EM.mesh_ready) return fail(ctx, P3M_ESTATE, "p3m_forces_noalloc: mesh buffers missing");
+  // particle records in the static array; the context's cell-sort tables,
+  // placement and mesh as allocated by p3m_create
+  Engine<R> E;
+  E.pp = reinterpret_cast<PPPos<R>*>(base + lay.pp);
+  E.mesh = reinterpret_cast<MeshRec<R>*>(base + lay.mesh);
+  E.fpp = reinterpret_cast<PPRec<R>*>(base + lay.fpp);
+  E.cap = n;
+  E.mesh_ready = true;   // never used for the mesh: EM is
+  const SortBufs saved = ctx->sb;
+  int2* saved_groups = ctx->groups;
+  ctx->sb.keys_in = reinterpret_cast<uint32_t*>(base + lay.keys_in);
+  ctx->sb.keys = reinterpret_cast<uint32_t*>(base + lay.keys);
+  ctx->sb.perm = reinterpret_cast<uint32_t*>(base + lay.perm);
+  ctx->groups = reinterpret_cast<int2*>(base + lay.groups);
+  place(ctx, n, x, nullptr, nullptr, st);
+  GatherOut out{f, nullptr, nullptr, nullptr, 0.0};
+  const p3m_status s = evaluate<R, M>(ctx, E, EM, n, x, qw, out, nullptr, nullptr, Carry{}, st);
+  ctx->sb = saved;
+  ctx->groups = saved_groups;
+  ctx->keys = nullptr;
+  ctx->perm = nullptr;
+  return s;
+}
+
+}  // namespace
+
 extern "C" {
 
 p3m_status p3m_default_opts(p3m_opts* o) {
@@ -460,6 +551,10 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   p3m_ctx* ctx = new (std::nothrow) p3m_ctx();
   if (!ctx) return P3M_ENOMEM;
   ctx->opts = o;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return P3M_EHIP;
+  }
   // float mesh wider than P3M_MESH_AUTO_F32_MAX nodes on some axis: the
   // difference form for the variational gather in free space, else (AUTO)
   // a float64 mesh
@@ -555,6 +650,17 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
         return bail(P3M_ENOMEM);
     }
   }
+  // the mesh buffers of the engine this precision evaluates with, allocated
+  // now (p3m_forces_noalloc allocates nothing), and the scratch symbol of
+  // this device resolved once
+  {
+    p3m_status ms = P3M_OK;
+    if (o.precision == P3M_FP32C && !ctx->mesh64) ms = engine_mesh_alloc(ctx, ctx->e32);
+    else ms = engine_mesh_alloc(ctx, ctx->e64);
+    if (ms != P3M_OK) return bail(ms);
+    hipError_t se;
+    if (!scratch_for(ctx->device, &se)) return bail(P3M_EHIP);
+  }
   *out = ctx;
   return P3M_OK;
 }
@@ -585,6 +691,28 @@ p3m_status p3m_forces(p3m_ctx* ctx, int64_t n, const double* x, const double* qw
   place(ctx, n, x, nullptr, nullptr, st);
   GatherOut out{f, nullptr, nullptr, nullptr, 0.0};
   if ((s = evaluate_any(ctx, n, x, qw, out, nullptr, nullptr, st)) != P3M_OK) return s;
+  return check_last(ctx);
+}
+
+p3m_status p3m_forces_noalloc(p3m_ctx* ctx, int64_t n, const double* x, const double* qw, double* f,
+                              void* stream) {
+  if (!ctx) return P3M_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !f))) return fail(ctx, P3M_EINVAL, "bad particle arguments");
+  if (n > 0xffffffffll / 2) return fail(ctx, P3M_EINVAL, "n exceeds the 32-bit particle index range");
+  ctx->force_cached = false;
+  if (n == 0) return P3M_OK;
+  hipError_t se;
+  unsigned char* base = static_cast<unsigned char*>(scratch_for(ctx->device, &se));
+  if (!base) return fail(ctx, P3M_EHIP, std::string("scratch symbol: ") + hipGetErrorString(se));
+  hipStream_t st = (hipStream_t)stream;
+  p3m_status s;
+  if (ctx->opts.precision == P3M_FP32C) {
+    if (ctx->mesh64) s = forces_noalloc<float, double>(ctx, ctx->e64, n, x, qw, f, base, st);
+    else s = forces_noalloc<float, float>(ctx, ctx->e32, n, x, qw, f, base, st);
+  } else {
+    s = forces_noalloc<double, double>(ctx, ctx->e64, n, x, qw, f, base, st);
+  }
+  if (s != P3M_OK) return s;
   return check_last(ctx);
 }
 

@@ -22,7 +22,8 @@ PLACEMENT_DOUBLES = 4
 
 # Every symbol include/p3m.h declares.
 SYMBOLS = (
-    "p3m_default_opts", "p3m_create", "p3m_forces", "p3m_forces_ex", "p3m_step", "p3m_hvp",
+    "p3m_default_opts", "p3m_create", "p3m_forces", "p3m_forces_noalloc", "p3m_forces_ex", "p3m_step",
+    "p3m_hvp",
     "p3m_backward", "p3m_backward_steps", "p3m_diagnostics", "p3m_mesh", "p3m_status_sync", "p3m_info",
     "p3m_last_error", "p3m_destroy", "p3m_profile_begin", "p3m_profile_end",
 )
@@ -71,6 +72,7 @@ def lib():
             "p3m_default_opts": (i32, [P]),
             "p3m_create": (i32, [P, P, P, dbl, dbl, P]),
             "p3m_forces": (i32, [P, i64, P, P, P, P]),
+            "p3m_forces_noalloc": (i32, [P, i64, P, P, P, P]),
             "p3m_forces_ex": (i32, [P, i64, P, P, P, P, P, P, P]),
             "p3m_step": (i32, [P, i64, P, P, P, dbl, i32, i32, P, P, P]),
             "p3m_hvp": (i32, [P, i64, P, P, P, P, P, P]),
@@ -157,6 +159,12 @@ class Context:
         if out is None:
             out = torch.empty_like(x)
         self._check(lib().p3m_forces(self._ctx, x.shape[0], _ptr(x), _ptr(qw), _ptr(out), _stream()))
+        return out
+
+    def forces_noalloc(self, x, out, qw=None):
+        """p3m_forces_noalloc: the force into the caller's `out`, with the work
+        buffers in the library's static device array (no allocation)."""
+        self._check(lib().p3m_forces_noalloc(self._ctx, x.shape[0], _ptr(x), _ptr(qw), _ptr(out), _stream()))
         return out
 
     def forces_ex(self, x, qw=None, f_pp=None, f_pm=None, place_in=None, place_out=None):
