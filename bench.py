@@ -209,6 +209,32 @@ def cpu_baseline(wl, n_targets):
             "seconds_per_step": step_s}
 
 
+def load_balance(waves):
+    """Load balance of one pair-kernel launch from the start and end (us) of
+    each of its waves: the span, the most waves resident at once, the
+    fraction of (resident slots x span) the waves kept busy, the fraction of
+    the span with fewer than half that many waves resident (the tail), and
+    the spread of the wave durations."""
+    import numpy as np
+    w = np.asarray(waves)
+    if len(w) == 0:
+        return None
+    t0, t1 = w[:, 0].min(), w[:, 1].max()
+    ev = np.concatenate([np.stack([w[:, 0], np.ones(len(w))], 1), np.stack([w[:, 1], -np.ones(len(w))], 1)])
+    ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]
+    busy = np.cumsum(ev[:, 1])
+    slots = int(busy.max())
+    dt = np.diff(ev[:, 0])
+    low = float((dt * (busy[:-1] < 0.5 * slots)).sum())
+    dur = w[:, 1] - w[:, 0]
+    span = t1 - t0
+    return {"waves": int(len(w)), "span_us": float(span), "max_resident_waves": slots,
+            "busy_fraction": float(dur.sum() / (slots * span)) if span > 0 else None,
+            "tail_fraction_below_half_resident": float(low / span) if span > 0 else None,
+            "wave_us_mean": float(dur.mean()), "wave_us_p50": float(np.percentile(dur, 50)),
+            "wave_us_p99": float(np.percentile(dur, 99)), "wave_us_max": float(dur.max())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -230,29 +256,6 @@ def main():
             "principal": p3m.INFLUENCE_PRINCIPAL, "lattice": p3m.INFLUENCE_LATTICE}[args.influence]
     ctx = p3m.Context.from_workload(wl, precision=prec, gather=gmode, cathode_z=zc, influence=infl)
 
-    # accuracy of this precision against the float64 path on the same GPU:
-    # relative rms over all particles, and the largest single-particle error
-    # against the rms force
-    f_this = ctx.forces(x)
-    ctx64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode, cathode_z=zc, influence=infl)
-    f64 = ctx64.forces(x)
-    err = float(torch.sqrt(((f_this - f64) ** 2).sum() / (f64 ** 2).sum()))
-    err_max = float(torch.linalg.norm(f_this - f64, dim=1).max() / torch.sqrt((f64 ** 2).sum(dim=1).mean()))
-    del f_this, f64
-    # float64 path's own throughput: a few steps from the initial state, its
-    # start force evaluated before the timer
-    fp64_rate = None
-    if args.fp64_steps > 0 and prec != p3m.FP64:
-        x64, p64 = x.clone(), p.clone()
-        ctx64.step(x64, p64, wl.dt, 0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx64.step(x64, p64, wl.dt, args.fp64_steps, reuse_force=True)
-        torch.cuda.synchronize()
-        fp64_rate = wl.n * args.fp64_steps / (time.perf_counter() - t0)
-        del x64, p64
-    del ctx64
-    torch.cuda.empty_cache()
     d0 = ctx.diagnostics(x, p)
     info = ctx.info()
 
@@ -279,13 +282,17 @@ def main():
     stage_ms = {s: 0.0 for s in p3m.STAGES}
     stage_n = {s: 0 for s in p3m.STAGES}
     done = 0
+    waves = None
     while done < args.steps:
         k = min(10, args.steps - done)
-        ctx.profile_begin(8 * (k + 2))
+        last = done + k >= args.steps
+        ctx.profile_begin(8 * (k + 2), pp_waves=last)
         ctx.step(xr, pr, wl.dt, k)
         for s_, (ms_, cnt_) in ctx.profile_end().items():
             stage_ms[s_] += ms_
             stage_n[s_] += cnt_
+        if last:
+            waves = ctx.pp_waves()   # the pair kernel's waves in the replica's last evaluation
         done += k
         counts.append(ctx.diagnostics(xr, pr)["pairs"])
     pairs = sum(0.5 * (a + b) for a, b in zip(counts, counts[1:])) / max(len(counts) - 1, 1)
@@ -309,6 +316,32 @@ def main():
     d1 = ctx.diagnostics(x, p)
     wall = t1 - t0
     value = wl.n * args.steps / wall
+
+    # after the timed region (the float64 kernels draw more power, and the
+    # clocks they leave behind would slow what follows): the accuracy of this
+    # precision against the float64 path on the same GPU at the initial
+    # state, relative rms over all particles and the largest single-particle
+    # error against the rms force; then the float64 path's own throughput,
+    # a few steps from the initial state with its start force evaluated
+    # before the timer
+    x = torch.tensor(x0, dtype=torch.float64, device=dev)
+    p = torch.tensor(p0, dtype=torch.float64, device=dev)
+    f_this = ctx.forces(x)
+    ctx64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode, cathode_z=zc, influence=infl)
+    f64 = ctx64.forces(x)
+    err = float(torch.sqrt(((f_this - f64) ** 2).sum() / (f64 ** 2).sum()))
+    err_max = float(torch.linalg.norm(f_this - f64, dim=1).max() / torch.sqrt((f64 ** 2).sum(dim=1).mean()))
+    del f_this, f64
+    fp64_rate = None
+    if args.fp64_steps > 0 and prec != p3m.FP64:
+        ctx64.step(x, p, wl.dt, 0)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter()
+        ctx64.step(x, p, wl.dt, args.fp64_steps, reuse_force=True)
+        torch.cuda.synchronize()
+        fp64_rate = wl.n * args.fp64_steps / (time.perf_counter() - t64)
+    del ctx64
+    torch.cuda.empty_cache()
 
     # dominant stage and its roofline, from its launches in the timed region
     ms_tot, launches = prof[stage]
@@ -382,6 +415,8 @@ def main():
             "status": status,
             "stage_ms_per_step": per_launch,
             "stage_ms_from": "replica of the timed trajectory with every stage timed",
+            "pp_load_balance": load_balance(waves) if waves is not None else None,
+            "pp_load_balance_from": "the pair kernel's waves in the replica's last force evaluation",
         },
         "roofline": roof,
     }

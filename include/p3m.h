@@ -319,14 +319,25 @@ p3m_status p3m_mesh(p3m_ctx *ctx, int32_t which, double *out, void *stream);
  *   0 push + placement, 1 linked-cell sort and PP work groups, 2 reorder,
  *   3 PP pair forces (the pair kernel alone), 4 deposit, 5 FFT convolution
  *   (five passes), 6 gather.
+ * Bit 7 instead records, for the load balance of the pair kernel, the start
+ * and end of each of its waves (a wave takes up to 4 work groups of up to 16
+ * particles of one cell) in every force evaluation of up to the largest n
+ * evaluated before this call; p3m_profile_pp_waves returns those of the last.
  * stage_mask selects the stages (bit s for stage s; 0x7f all, nonzero). An
  * event pair costs about 2 us of idle GPU between the kernels it separates,
  * so a throughput measurement times only the stages it needs.
  * p3m_profile_end synchronises `stream`, writes the summed milliseconds and
  * the number of timed launches per stage (arrays of 8, host) and stops.
- * P3M_EINVAL for max_records < 1 or a mask outside 0x01..0x7f. */
+ * P3M_EINVAL for max_records < 1 or a mask outside 0x01..0xff. */
 p3m_status p3m_profile_begin(p3m_ctx *ctx, int32_t max_records, int32_t stage_mask);
 p3m_status p3m_profile_end(p3m_ctx *ctx, double ms[8], int64_t launches[8], void *stream);
+
+/* The pair-kernel waves of the last force evaluation recorded under bit 7
+ * of p3m_profile_begin: *count (host) receives the number of waves, out
+ * (host, [cap][2]) the start and end of the first min(count, cap) waves in
+ * microseconds from the earliest start (100 MHz device clock). Synchronises
+ * `stream`. P3M_ESTATE if no evaluation recorded its waves. */
+p3m_status p3m_profile_pp_waves(p3m_ctx *ctx, int64_t cap, double *out, int64_t *count, void *stream);
 
 /* Synchronise `stream`, return and clear the device status word
  * (P3M_OK, P3M_EDOMAIN or P3M_ENONFINITE). */

@@ -92,7 +92,10 @@ struct p3m_ctx {
   bool mesh64 = false;          // float32 particle path with a float64 mesh
   // stage timing
   bool prof_on = false;
-  int prof_mask = 0;            // stages timed (bit s: stage s)
+  int prof_mask = 0;            // stages timed (bit s: stage s); bit 7: pair-kernel wave clocks
+  unsigned long long* wclock = nullptr;   // [2 wclock_cap] start/end of each pair-kernel wave
+  int64_t wclock_cap = 0;
+  bool wclock_valid = false;    // the last evaluation recorded its pair kernel's waves
   std::vector<hipEvent_t> prof_ev;
   std::vector<int> prof_stage;
   int prof_next = 0;
@@ -356,7 +359,11 @@ p3m_status evaluate(p3m_ctx* ctx, Engine<R>& E, Engine<M>& EM, int64_t n, const 
   }
   {
     StageTimer t(ctx, 3, st);
-    launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, E.fpp, e_pp, st);
+    unsigned long long* wc = nullptr;
+    if (ctx->prof_on && (ctx->prof_mask & 0x80) && !e_pp && (int64_t)pp_blocks(n, g) <= ctx->wclock_cap)
+      wc = ctx->wclock;
+    launch_pp<R>(n, E.pp, ctx->keys, ctx->sb.cell_start, g, ctx->groups, ctx->sb.counter, E.fpp, e_pp, st, wc);
+    if (wc) ctx->wclock_valid = true;
   }
   {
     StageTimer t(ctx, 4, st);
@@ -945,8 +952,19 @@ p3m_status p3m_mesh(p3m_ctx* ctx, int32_t which, double* out, void* stream) {
 }
 
 p3m_status p3m_profile_begin(p3m_ctx* ctx, int32_t max_records, int32_t stage_mask) {
-  if (!ctx || max_records < 1 || (stage_mask & ~0x7f) || !stage_mask) return P3M_EINVAL;
+  if (!ctx || max_records < 1 || (stage_mask & ~0xff) || !stage_mask) return P3M_EINVAL;
   ctx->prof_mask = stage_mask;
+  if (stage_mask & 0x80) {
+    // wave clocks of the pair kernel, for the largest n evaluated so far
+    const int64_t need = 2 * (int64_t)pp_blocks(ctx->cap > 0 ? ctx->cap : 1, ctx->geo);
+    if (need > ctx->wclock_cap) {
+      dfree(ctx->wclock);
+      ctx->wclock_cap = 0;
+      HIPCHK(dalloc(&ctx->wclock, (size_t)need));
+      ctx->wclock_cap = need / 2;
+    }
+    ctx->wclock_valid = false;
+  }
   for (auto& e : ctx->prof_ev) (void)hipEventDestroy(e);
   ctx->prof_ev.assign(2 * (size_t)max_records, nullptr);
   for (auto& e : ctx->prof_ev) HIPCHK(hipEventCreate(&e));
@@ -968,6 +986,26 @@ p3m_status p3m_profile_end(p3m_ctx* ctx, double ms[8], int64_t launches[8], void
   }
   ctx->prof_on = false;
   ctx->prof_next = 0;
+  return P3M_OK;
+}
+
+p3m_status p3m_profile_pp_waves(p3m_ctx* ctx, int64_t cap, double* out, int64_t* count, void* stream) {
+  if (!ctx || cap < 0 || (cap > 0 && !out) || !count) return P3M_EINVAL;
+  if (!ctx->wclock_valid) return fail(ctx, P3M_ESTATE, "no pair-kernel waves recorded");
+  hipStream_t st = (hipStream_t)stream;
+  int groups = 0;
+  HIPCHK(hipMemcpyAsync(&groups, ctx->sb.counter, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int64_t waves = (groups + 3) / 4;
+  *count = waves;
+  const int64_t m = waves < cap ? waves : cap;
+  if (m > 0) {
+    std::vector<unsigned long long> h(2 * (size_t)m);
+    HIPCHK(hipMemcpy(h.data(), ctx->wclock, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    unsigned long long t0 = h[0];
+    for (int64_t k = 0; k < m; ++k) t0 = h[2 * k] < t0 ? h[2 * k] : t0;
+    for (int64_t k = 0; k < 2 * m; ++k) out[k] = (double)(h[k] - t0) * 0.01;   // 100 MHz ticks -> us
+  }
   return P3M_OK;
 }
 
@@ -1030,6 +1068,7 @@ void p3m_destroy(p3m_ctx* ctx) {
   dfree(ctx->gimg_t2);
   for (int d = 0; d < 3; ++d) dfree(ctx->tw64[d]);
   dfree(ctx->fcache);
+  dfree(ctx->wclock);
   free_state(ctx);
   dfree(ctx->v_sorted);
   dfree(ctx->hpp);

@@ -55,10 +55,14 @@ void launch_sort_vector(int64_t n, const double* v, const uint32_t* perm, R* out
 // ---- pair forces (pp.hip) ------------------------------------------------
 // Upper bound of the number of PP work groups (runs of <= kGroupRun particles of one cell).
 int pp_group_bound(int64_t n, const Geo& geo);
+// wclock (may be null; profiling): each wave of the force kernel (no
+// energy) writes its start and end on the 100 MHz real-time clock at
+// [2 w], [2 w + 1], w its wave index (fewer than pp_blocks(n, geo)).
+unsigned pp_blocks(int64_t n, const Geo& geo);
 template <typename R>
 void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
-               hipStream_t st);
+               hipStream_t st, unsigned long long* wclock = nullptr);
 template <typename R>
 void launch_pp_hvp(int64_t n, const PPPos<R>* rec, const uint32_t* keys,
                    const int* cell_start, const Geo& geo, const int2* desc, int* counter,

@@ -117,6 +117,7 @@ constexpr int kWaveGroups = 4;           // groups per wave (16 lanes each)
 constexpr int kRun = 8;                  // consecutive candidates read together
 constexpr int kTileK = 64;               // candidates per group per tile
 constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
+constexpr int kXcdRun = 32;              // consecutive waves of groups given to one XCD
 
 // Pair forces of four groups in one wave (lanes 16q .. 16q+15 hold the
 // targets of group q).
@@ -157,7 +158,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
                                            const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
                                            double* __restrict__ energy, const double* __restrict__ hv_in = nullptr,
-                                           double* __restrict__ hv_out = nullptr) {
+                                           double* __restrict__ hv_out = nullptr,
+                                           unsigned long long* __restrict__ wclock = nullptr) {
   using V4 = typename Vec4<R>::T;
   static_assert(!HVP || !ENERGY, "HVP: no energy");
   // per-group tiles padded by one element so the four groups' broadcast
@@ -174,9 +176,20 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   __shared__ V4 tvel[HVP ? NT : 1];         // HVP: the candidates' v (in R)
   __shared__ int rstart[kWaveGroups][9], rpre[kWaveGroups][10];
   __shared__ int gtot[kWaveGroups];
+  // Work-group b runs on XCD b % 8 (round-robin dealing). Runs of kXcdRun
+  // consecutive waves of groups (spatial neighbours, which share candidates)
+  // go to one XCD, so its L2 serves their shared candidates once; the runs
+  // are dealt to the XCDs in turn, which keeps dense and sparse regions
+  // spread over all of them.
   const int ngroups = counter[0];
-  const int gbase = blockIdx.x * kWaveGroups;
-  if (gbase >= ngroups) return;
+  const int nwaves = (ngroups + kWaveGroups - 1) / kWaveGroups;
+  const int xcd = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
+  const int wave = ((k / kXcdRun) * kXcds + xcd) * kXcdRun + k % kXcdRun;
+  if (wave >= nwaves) return;
+  const int gbase = wave * kWaveGroups;
+  // load-balance record (profiling only): the wave's start and end on the
+  // constant 100 MHz real-time clock
+  const unsigned long long t_start = wclock ? __builtin_amdgcn_s_memrealtime() : 0ull;
   const int lane = threadIdx.x, q = lane >> 4, ql = lane & 15;
   const int gid = gbase + q;
   const bool gvalid = gid < ngroups;
@@ -478,6 +491,10 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     f.w = (R)0;
     out[gd.x + ql] = f;
   }
+  if (wclock && threadIdx.x == 0) {
+    wclock[2 * wave] = t_start;
+    wclock[2 * wave + 1] = __builtin_amdgcn_s_memrealtime();
+  }
   if (ENERGY) {
     e_acc *= 0.5 * (double)tw / fud;   // each unordered pair is met twice
     for (int off = 32; off > 0; off >>= 1) {
@@ -501,24 +518,35 @@ int pp_group_bound(int64_t n, const Geo& geo) {
   return (int)b;
 }
 
+// Work-groups of the pair kernel: the bound on its waves, rounded up to
+// whole rounds of kXcdRun waves on each of the 8 XCDs (every wave index
+// below the bound is then some work-group's under the XCD mapping).
+unsigned pp_blocks(int64_t n, const Geo& geo) {
+  const long long waves = (pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups;
+  const long long round = (long long)kXcds * kXcdRun;
+  return (unsigned)((waves + round - 1) / round * round);
+}
+
 template <typename R>
 constexpr bool kPackable = std::is_same<R, float>::value;
 
 template <typename R>
 void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
-               hipStream_t st) {
+               hipStream_t st, unsigned long long* wclock) {
   // one wave per quad of groups; waves beyond the groups built leave at once
-  const unsigned blocks = (unsigned)((pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups);
+  const unsigned blocks = pp_blocks(n, geo);
   const bool packed = std::is_same<R, float>::value && geo.wpacked;
   if (energy && packed)
     k_pp<R, true, kPackable<R>><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
   else if (energy)
     k_pp<R, true, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
   else if (packed)
-    k_pp<R, false, kPackable<R>><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr);
+    k_pp<R, false, kPackable<R>><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr,
+                                                         nullptr, nullptr, wclock);
   else
-    k_pp<R, false, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr);
+    k_pp<R, false, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr, nullptr,
+                                                  nullptr, wclock);
 }
 
 template <typename R>
@@ -526,7 +554,7 @@ void launch_pp_hvp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const i
                    const Geo& geo, const int2* desc, int* counter, const double* v_sorted, double* out_sorted,
                    hipStream_t st) {
   // the tiled pair kernel in its Hessian-vector mode, over the cell sort's groups
-  const unsigned blocks = (unsigned)((pp_group_bound(n, geo) + kWaveGroups - 1) / kWaveGroups);
+  const unsigned blocks = pp_blocks(n, geo);
   const bool packed = std::is_same<R, float>::value && geo.wpacked;
   if (packed)
     k_pp<R, false, kPackable<R>, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
@@ -541,8 +569,8 @@ template void launch_pp_hvp<double>(int64_t, const PPPos<double>*, const uint32_
                                     const int2*, int*, const double*, double*, hipStream_t);
 
 template void launch_pp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
-                               const int2*, int*, PPRec<float>*, double*, hipStream_t);
+                               const int2*, int*, PPRec<float>*, double*, hipStream_t, unsigned long long*);
 template void launch_pp<double>(int64_t, const PPPos<double>*, const uint32_t*, const int*, const Geo&,
-                                const int2*, int*, PPRec<double>*, double*, hipStream_t);
+                                const int2*, int*, PPRec<double>*, double*, hipStream_t, unsigned long long*);
 
 }  // namespace p3m

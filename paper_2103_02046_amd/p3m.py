@@ -25,7 +25,7 @@ SYMBOLS = (
     "p3m_default_opts", "p3m_create", "p3m_forces", "p3m_forces_noalloc", "p3m_forces_ex", "p3m_step",
     "p3m_hvp",
     "p3m_backward", "p3m_backward_steps", "p3m_diagnostics", "p3m_mesh", "p3m_status_sync", "p3m_info",
-    "p3m_last_error", "p3m_destroy", "p3m_profile_begin", "p3m_profile_end",
+    "p3m_last_error", "p3m_destroy", "p3m_profile_begin", "p3m_profile_end", "p3m_profile_pp_waves",
 )
 STAGES = ("push+placement", "sort", "reorder", "pp", "deposit", "fft", "gather")
 
@@ -86,6 +86,7 @@ def lib():
             "p3m_destroy": (None, [P]),
             "p3m_profile_begin": (i32, [P, i32, i32]),
             "p3m_profile_end": (i32, [P, P, P, P]),
+            "p3m_profile_pp_waves": (i32, [P, i64, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -212,10 +213,24 @@ class Context:
                 "mean": list(d.mean), "rms": list(d.rms), "emit_n": list(d.emit_n), "zoom": d.zoom,
                 "charge": d.charge, "pairs": d.pairs}
 
-    def profile_begin(self, max_records=1 << 16, stages=None):
-        """Time the named stages (all when None) from now on."""
+    def profile_begin(self, max_records=1 << 16, stages=None, pp_waves=False):
+        """Time the named stages (all when None) from now on; pp_waves: also
+        record the start and end of every pair-kernel wave."""
         mask = 0x7f if stages is None else sum(1 << STAGES.index(s) for s in stages)
+        if pp_waves:
+            mask |= 0x80
         self._check(lib().p3m_profile_begin(self._ctx, int(max_records), int(mask)))
+
+    def pp_waves(self, cap=1 << 24):
+        """(start, end) in us of each pair-kernel wave of the last recorded evaluation."""
+        import numpy as np
+        cnt = ctypes.c_int64()
+        probe = lib().p3m_profile_pp_waves(self._ctx, 0, None, ctypes.byref(cnt), _stream())
+        self._check(probe)
+        m = min(cnt.value, cap)
+        out = np.zeros((m, 2))
+        self._check(lib().p3m_profile_pp_waves(self._ctx, m, out.ctypes.data, ctypes.byref(cnt), _stream()))
+        return out
 
     def profile_end(self):
         """Per-stage (milliseconds summed, launches) since profile_begin; synchronises."""

@@ -102,6 +102,56 @@ def test_momentum_gather_refuses_adjoint():
     assert e.value.code == p3m.ESTATE
 
 
+def test_momentum_vs_variational_drift():
+    """The comparison the momentum-conserving gather is for (a reading of the
+    remark after Sec. 2.5, eq. eom_p3m_coord): 200 float64 leapfrog steps of
+    the 4096-particle bunch on a fixed mesh (one placement replayed at every
+    step, zoom 2.5 about the initial box, so the discrete energy is one fixed
+    function of the positions; the bunch grows to 1.7 times its initial
+    half-width over the run and stays inside the mesh's usable nodes). The
+    variational force is minus the gradient of that energy: leapfrog keeps
+    the total energy KE + U_PP + U_PM (the
+    oracle's, at the fixed placement, from the GPU's positions) within a
+    bounded error, while the mesh self-force lets the total momentum drift.
+    The central-difference field conserves momentum to rounding (its pair
+    and mesh forces are both antisymmetric), while the energy, of which it is
+    not the gradient, drifts further."""
+    wl = W.get("gauss4k")
+    x0, p0 = wl.draw()
+    g = np.asarray(wl.grid)
+    s = 2.5
+    c0 = 0.5 * (x0.min(axis=0) + x0.max(axis=0))
+    place = np.concatenate([c0 - 0.5 * (g - 1) * s * np.asarray(wl.h), [s]])
+    pl = {"x0": place[:3], "s": s, "hp": s * np.asarray(wl.h), "rc": s * wl.r_cut, "a": wl.split / s}
+    nsteps, every = 200, 20
+    out = {}
+    for mode, name in ((p3m.GATHER_VARIATIONAL, "variational"), (p3m.GATHER_MOMENTUM, "momentum")):
+        c = p3m.Context.from_workload(wl, gather=mode)
+        prm = O.Params.from_workload(wl, gather=name)
+        x, p = dev(x0), dev(p0)
+        rep = dev(np.tile(place, every + 1))
+        e, mom, pscale = [], [], []
+        for k in range(nsteps // every + 1):
+            if k:
+                c.step(x, p, wl.dt, every, place_replay=rep)
+                assert c.status_sync() == p3m.OK
+            xh, ph = host(x), host(p)
+            Q = O.deposit(xh, prm, pl)
+            upm = 0.5 * wl.ke_q2 * float((Q * O.mesh_potential(Q, prm, pl)).sum())
+            upp = O.pp_energy(xh, prm, pl["rc"], pl["a"])
+            e.append(float((ph * ph).sum()) / (2 * wl.m) + upp + upm)
+            mom.append(float(np.linalg.norm(ph.sum(axis=0))))
+            pscale.append(float(np.linalg.norm(ph, axis=1).sum()))
+        e = np.array(e)
+        de = float(np.abs(e - e[0]).max() / abs(e[0]))
+        dp = max(mom[1:]) / max(pscale[1:])
+        out[mode] = (de, dp)
+        print(f"gather {name}: max |E - E0|/|E0| {de:.3e}, max |sum p| / sum |p| {dp:.3e}", flush=True)
+    assert out[p3m.GATHER_MOMENTUM][1] < 1e-12
+    assert out[p3m.GATHER_VARIATIONAL][1] > 1e3 * out[p3m.GATHER_MOMENTUM][1]
+    assert out[p3m.GATHER_VARIATIONAL][0] < out[p3m.GATHER_MOMENTUM][0]
+
+
 # ---- grounded planar cathode (image charges on the mesh) ------------------------
 
 def _cathode(wl, x, precision=p3m.FP64, below=0.5e-3):
