@@ -39,7 +39,39 @@ template <typename T, int L>
 struct Cfg {
   static constexpr int raw = kLdsBytes / (L * (int)sizeof(C2<T>));
   static constexpr int B = raw < 1 ? 1 : raw;   // lines per block (power of two)
+  // blocks of the strided y and z passes whose B-wide rows share one 128-byte line
+  static constexpr int share = 128 / (int)sizeof(C2<T>) / B;
+  static constexpr int G = share < 1 ? 1 : share;
 };
+
+// Block order of the strided y and z passes. Logical block l = row * nchp +
+// chunk takes the B values k_x = chunk * B .. of one row of lines; nchp is
+// the chunk count rounded up to a multiple of G, so the G chunks of one
+// 128-byte line are G consecutive logical blocks. Work-groups are dealt to
+// the XCDs round-robin, so those G blocks are placed kXcds slots apart in
+// runs of G * kXcds: they run on one XCD at about the same time and its L2
+// fetches each line once, not once per chunk (at 1024-point float lines
+// B = 4 and G = 4). Returns false for the padding blocks.
+template <int G>
+__device__ __forceinline__ bool line_block(int nch, long long nrows, int& row, int& kx0, int B) {
+  const long long hb = blockIdx.x;
+  const int j = (int)(hb % (G * kXcds));
+  const long long l = hb - j + (long long)(j % kXcds) * G + j / kXcds;
+  const int nchp = (nch + G - 1) / G * G;
+  const long long r = l / nchp;
+  const int c = (int)(l - r * nchp);
+  row = (int)r;
+  kx0 = c * B;
+  return r < nrows && c < nch;
+}
+
+template <typename T, int L>
+unsigned line_grid(long long nrows, int K) {
+  constexpr int B = Cfg<T, L>::B, G = Cfg<T, L>::G;
+  const long long nchp = ((K + B - 1) / B + G - 1) / G * G;
+  const long long run = (long long)G * kXcds;
+  return (unsigned)((nrows * nchp + run - 1) / run * run);
+}
 
 template <typename T>
 __device__ __forceinline__ void dft2(C2<T>* v) {
@@ -222,8 +254,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_y(Geo geo, C2<T>* __restric
   constexpr int PER = (L * B + kFftThreads - 1) / kFftThreads;
   __shared__ C2<T> s[L * B];
   const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
-  const int nch = (K + B - 1) / B;
-  const int z = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
+  int z, kx0;
+  if (!line_block<Cfg<T, L>::G>((K + B - 1) / B, geo.grid[2], z, kx0, B)) return;
   C2<T>* base = S + (long long)z * L * KS;
   const int nin = INV ? L : N;
   C2<T> hold[DIFF ? PER : 1];
@@ -288,8 +320,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z(Geo geo, C2<T>* __restric
   __shared__ C2<T> s[L * B];
   const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
   const int ly = 2 * geo.grid[1];
-  const int nch = (K + B - 1) / B;
-  const int ky = blockIdx.x / nch, kx0 = (blockIdx.x % nch) * B;
+  int ky, kx0;
+  if (!line_block<Cfg<T, L>::G>((K + B - 1) / B, ly, ky, kx0, B)) return;
   const long long zstride = (long long)ly * KS;
   C2<T>* base = S + (long long)ky * KS;
   for (int e = threadIdx.x; e < L * B; e += kFftThreads) {
@@ -905,15 +937,13 @@ void run_y(const Geo& g, C2<T>* S, const C2<T>* tw, hipStream_t st) {
     k_fft_y_reg<INV><<<(unsigned)(g.grid[2] * ((K + 15) / 16)), kFftThreads, 0, st>>>(g, S, tw);
     return;
   }
-  unsigned blocks = (unsigned)(g.grid[2] * ((K + B - 1) / B));
-  k_fft_y<T, L, INV><<<blocks, kFftThreads, 0, st>>>(g, S, tw);
+  k_fft_y<T, L, INV><<<line_grid<T, L>(g.grid[2], K), kFftThreads, 0, st>>>(g, S, tw);
 }
 template <typename T, int L>
 void run_z(const Geo& g, C2<T>* S, const T* gz, const C2<double>* gimg, const C2<T>* tw,
            hipStream_t st) {
-  constexpr int B = Cfg<T, L>::B;
   int K = g.grid[0] + 1;
-  unsigned blocks = (unsigned)(2 * g.grid[1] * ((K + B - 1) / B));
+  const unsigned blocks = line_grid<T, L>(2 * g.grid[1], K);
   if constexpr (std::is_same<T, float>::value && L == kRegL) {
     if (!gimg) {
       const unsigned slots = (unsigned)((z_reg_groups(g) + kXcds - 1) / kXcds * 4 * kXcds);
@@ -1010,12 +1040,12 @@ void launch_convolve_diff(const Geo& g, const R* Q, C2<R>* S, C2<R>* S2, C2<R>* 
   const long long rows = (long long)g.grid[1] * g.grid[2];
 #define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], st)
 #define YF(L) run_y<R, L, false>(g, S, tw[1], st)
-#define ZD(L)                                                                                       \
-  k_fft_z<R, L, false, true><<<(unsigned)(2 * g.grid[1] * ((K + Cfg<R, L>::B - 1) / Cfg<R, L>::B)), \
-                               kFftThreads, 0, st>>>(g, S, gz, nullptr, tw[2], S2, dtab[2])
+#define ZD(L)                                                                     \
+  k_fft_z<R, L, false, true><<<line_grid<R, L>(2 * g.grid[1], K), kFftThreads, 0, st>>>( \
+      g, S, gz, nullptr, tw[2], S2, dtab[2])
 #define YD(L)                                                                                \
   do {                                                                                       \
-    const unsigned nb = (unsigned)(g.grid[2] * ((K + Cfg<R, L>::B - 1) / Cfg<R, L>::B));     \
+    const unsigned nb = line_grid<R, L>(g.grid[2], K);                                       \
     k_fft_y<R, L, true, true><<<nb, kFftThreads, 0, st>>>(g, S, tw[1], S3, dtab[1]);         \
     k_fft_y<R, L, true, false><<<nb, kFftThreads, 0, st>>>(g, S2, tw[1]);                    \
   } while (0)
