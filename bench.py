@@ -52,6 +52,8 @@ def parse():
                     help="Fourier table of the mesh kernel (built at create)")
     ap.add_argument("--cathode", action="store_true",
                     help="grounded plane 1 mm below the bunch (image charges on the mesh)")
+    ap.add_argument("--pp-cell-div", type=int, default=None, choices=[1, 2],
+                    help="PP cells per cutoff along each axis (default: the workload's own)")
     ap.add_argument("--fp64-steps", type=int, default=3,
                     help="leapfrog steps of the float64 path timed for its own particle-steps/s (0: skip)")
     ap.add_argument("--cpu-targets", type=int, default=32768,
@@ -254,7 +256,10 @@ def main():
     zc = float(x0[:, 2].min()) - 1e-3 if args.cathode else None
     infl = {"sampled": p3m.INFLUENCE_SAMPLED, "optimal": p3m.INFLUENCE_OPTIMAL,
             "principal": p3m.INFLUENCE_PRINCIPAL, "lattice": p3m.INFLUENCE_LATTICE}[args.influence]
-    ctx = p3m.Context.from_workload(wl, precision=prec, gather=gmode, cathode_z=zc, influence=infl)
+    ckw = dict(gather=gmode, cathode_z=zc, influence=infl)
+    if args.pp_cell_div is not None:
+        ckw["pp_cell_div"] = args.pp_cell_div
+    ctx = p3m.Context.from_workload(wl, precision=prec, **ckw)
 
     d0 = ctx.diagnostics(x, p)
     info = ctx.info()
@@ -327,7 +332,7 @@ def main():
     x = torch.tensor(x0, dtype=torch.float64, device=dev)
     p = torch.tensor(p0, dtype=torch.float64, device=dev)
     f_this = ctx.forces(x)
-    ctx64 = p3m.Context.from_workload(wl, precision=p3m.FP64, gather=gmode, cathode_z=zc, influence=infl)
+    ctx64 = p3m.Context.from_workload(wl, precision=p3m.FP64, **ckw)
     f64 = ctx64.forces(x)
     err = float(torch.sqrt(((f_this - f64) ** 2).sum() / (f64 ** 2).sum()))
     err_max = float(torch.linalg.norm(f_this - f64, dim=1).max() / torch.sqrt((f64 ** 2).sum(dim=1).mean()))
@@ -404,6 +409,7 @@ def main():
             "gather": args.gather,
             "boundary": "grounded plane 1 mm below the bunch" if args.cathode else "open",
             "influence": args.influence,
+            "pp_cells_per_cutoff": args.pp_cell_div or wl.pp_cell_div,
             "force_rms_err_vs_fp64": err,
             "force_max_particle_err_vs_fp64": err_max,
             "fp64_particle_steps_per_s": fp64_rate,

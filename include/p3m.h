@@ -147,7 +147,10 @@ typedef struct {
     int32_t zoom;       /* 1: zoom the mesh to fit the bunch; 0: EDOMAIN    [1]    */
     int32_t gather;     /* P3M_GATHER_VARIATIONAL or _MOMENTUM     [VARIATIONAL]  */
     int32_t mesh_precision; /* P3M_MESH_AUTO, _F32 or _F64 (P3M_FP32C only) [AUTO] */
-    int32_t reserved;   /* must be 0                                               */
+    int32_t pp_cell_div; /* PP cells per cutoff along each axis: 1 (edge >= r_c,
+                            27 neighbour cells) or 2 (edge >= r_c/2, 125 half-size
+                            cells: 125/8 instead of 27 cutoff cubes of candidates
+                            per particle, for dense bunches); 0 means 1       [0]  */
     double ke;          /* Coulomb constant 1/(4 pi eps0)     [8.9875517923e9]    */
     double q;           /* macro-particle charge, C                        [1.0]  */
     double m;           /* macro-particle mass, kg                         [1.0]  */

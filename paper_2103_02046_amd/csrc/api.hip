@@ -540,7 +540,7 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   else p3m_default_opts(&o);
   if (o.order != P3M_CIC && o.order != P3M_TSC) return P3M_EINVAL;
   if (o.gather != P3M_GATHER_VARIATIONAL && o.gather != P3M_GATHER_MOMENTUM) return P3M_EINVAL;
-  if (o.reserved != 0) return P3M_EINVAL;
+  if (o.pp_cell_div < 0 || o.pp_cell_div > 2) return P3M_EINVAL;
   if (o.influence < P3M_INFLUENCE_SAMPLED || o.influence > P3M_INFLUENCE_LATTICE) return P3M_EINVAL;
   if (o.influence != P3M_INFLUENCE_SAMPLED && o.boundary == P3M_BOUNDARY_CATHODE) return P3M_EINVAL;
   if (o.boundary != P3M_BOUNDARY_OPEN && o.boundary != P3M_BOUNDARY_CATHODE) return P3M_EINVAL;
@@ -582,13 +582,15 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
   g.cathode = o.boundary == P3M_BOUNDARY_CATHODE ? 1 : 0;
   g.zc = g.cathode ? o.cathode_z : 0.0;
   g.influence = o.influence;
+  g.pp_div = o.pp_cell_div == 2 ? 2 : 1;
   g.ncells = 1;
   for (int d = 0; d < 3; ++d) {
     g.grid[d] = grid[d];
     g.h[d] = h[d];
     g.hu[d] = h[d] / r_cut;
+    // PP cells of edge >= r_c / pp_div covering the mesh span exactly
     const double span = (grid[d] - 1) * h[d];
-    long long nc = (long long)std::floor(span / r_cut);
+    long long nc = (long long)std::floor(span * g.pp_div / r_cut);
     if (nc < 1) nc = 1;
     if (nc > 4096) nc = 4096;
     g.ncell[d] = (int)nc;

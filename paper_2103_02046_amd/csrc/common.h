@@ -62,6 +62,7 @@ struct Geo {
   int influence;       // mesh kernel table: kInfluence*
   int wpacked;         // per call: float records carry position residuals, weights all 1
   int mdiff;           // float mesh in the difference form (three difference meshes, no phi)
+  int pp_div;          // PP cells per cutoff along each axis (1 or 2): cell edge >= r_c / pp_div
   double zc;           // plane position (m)
 };
 
@@ -100,9 +101,15 @@ template <> struct alignas(32) PPRec<double> { double x, y, z, w; };
 // unit for all axes, fix_unit = (largest cell edge) / 2^kFixBits Lu; the
 // cell edge of axis d is the integer fix_edge(d) units, so separations of
 // particles in neighbouring cells are exact integers (rounded once, to
-// float, after the subtraction). double form: offset from the cell corner
-// in units of Lu.
-constexpr int kFixBits = 29;
+// float, after the subtraction). The x slot holds the position plus
+// kFixBias in its low 29 bits and the cell's x index modulo 8 in its top
+// three (kXCodeShift), from which the pair kernel reads a candidate's cell
+// offset along its row of cells (|offset| <= 2). double form: offset from
+// the cell corner in units of Lu.
+constexpr int kFixBits = 28;
+constexpr int kFixBias = 1 << 27;                        // x slot: position + bias in [0, 2^29)
+constexpr int kXCodeShift = 29;                          // bits 29..31: cell x index mod 8
+constexpr int kFixMask = (1 << kXCodeShift) - 1;
 struct alignas(16) PPFix { int x, y, z; float w; };
 template <typename R> struct PPPosOf { using type = PPRec<R>; };
 template <> struct PPPosOf<float> { using type = PPFix; };

@@ -92,10 +92,13 @@ struct Acc3<double> {
 };
 
 // Work groups (kGroupRun particles at most, one cell) come from the cell
-// sort. The candidates of every particle of a group lie in 9 contiguous
-// ranges: cells cx-1 .. cx+1 of the 3 x 3 neighbouring rows (a row of cells
-// is contiguous in the sorted order); consecutive groups are spatial
-// neighbours.
+// sort. Cells have edges >= r_c / D (D = Geo::pp_div, 1 or 2), so the
+// candidates of every particle of a group lie in (2D+1)^2 contiguous
+// ranges: cells cx-D .. cx+D of the (2D+1) x (2D+1) neighbouring rows (a
+// row of cells is contiguous in the sorted order); consecutive groups are
+// spatial neighbours. Halving the cells (D = 2) cuts the candidate volume
+// from 27 to 125/8 cutoff cubes, for dense bunches whose half-size cells
+// still fill the groups.
 
 // (m << 1) | sign(v): one v_alignbit_b32 for float; the sign of a double is
 // the top bit of its high word.
@@ -121,7 +124,7 @@ constexpr int kXcdRun = 32;              // consecutive waves of groups given to
 
 // Pair forces of four groups in one wave (lanes 16q .. 16q+15 hold the
 // targets of group q).
-// The candidates of a group are the concatenation of its 9 row ranges, L of
+// The candidates of a group are the concatenation of its row ranges, L of
 // them, read in runs of 8 consecutive ones (8 lanes, 128 contiguous bytes).
 // With S = ceil(L / 64) tiles, tile t holds runs t, t+S, ..., t+7S: an evenly
 // spread sample of the whole neighbourhood, so the hits of a tile spread
@@ -132,8 +135,10 @@ constexpr int kXcdRun = 32;              // consecutive waves of groups given to
 //      edges at most): a 64-bit hit mask;
 //   3. each lane evaluates its own hits from the exact separation: in the
 //      float form the difference of fixed-point positions relative to the
-//      group's first cell corner (cell offsets are whole multiples of
-//      2^kFixBits), an integer rounded once to float; in the double form
+//      group's cell corner (cell offsets are whole multiples of the cell
+//      edge in units, fix_edge), an integer rounded once to float; a
+//      candidate's offset along the row comes from the x code in its
+//      record, the row's offsets from its range; in the double form
 //      cell-local positions plus cell-corner offsets (exact multiples of the
 //      cell edge). The tile sum is added to the per-particle total with
 //      Kahan compensation (float form).
@@ -153,7 +158,7 @@ __device__ __forceinline__ void wave_sync() {
 // are sorted [n][3] float64. float form: the separation from the fixed-point
 // records (residuals included), the Jacobian in float with the same erfc fit
 // as the force, Kahan-compensated per-particle sums.
-template <typename R, bool ENERGY, bool PACKED, bool HVP = false>
+template <typename R, bool ENERGY, bool PACKED, bool HVP, int DIV>
 __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter,
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
                                            const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
@@ -174,7 +179,13 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   __shared__ V4 tloc[kFix ? 1 : NT];        // double: cell-local x, y, z and the charge weight
   __shared__ V4 toff[kFix ? 1 : NT];        // double: cell-corner offset from the group's first cell
   __shared__ V4 tvel[HVP ? NT : 1];         // HVP: the candidates' v (in R)
-  __shared__ int rstart[kWaveGroups][9], rpre[kWaveGroups][10];
+  // neighbourhood of a group's cell: DIV cells on each side along each axis
+  // (cells of edge >= r_c / DIV), as NR row ranges of W cells
+  constexpr int W = 2 * DIV + 1;
+  constexpr int NR = W * W;
+  constexpr int RPL = (NR + 15) / 16;   // row ranges per lane of a group
+  __shared__ int rstart[kWaveGroups][NR], rpre[kWaveGroups][NR + 1];
+  __shared__ int2 royz[kFix ? kWaveGroups : 1][kFix ? NR : 1];   // float: the rows' y, z offsets in units
   __shared__ int gtot[kWaveGroups];
   // Work-group b runs on XCD b % 8 (round-robin dealing). Runs of kXcdRun
   // consecutive waves of groups (spatial neighbours, which share candidates)
@@ -206,44 +217,57 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     cy = (int)((k0 / (uint32_t)nx) % (uint32_t)ny);
     cz = (int)(k0 / ((uint32_t)nx * (uint32_t)ny));
   }
-  // 9 candidate ranges per group (lanes 0..8 of each quarter): cells
-  // cx0-1 .. cx0+1 of the rows (cy+dy, cz+dz), row r = (dy+1) + 3 (dz+1)
-  int len = 0;
-  if (ql < 9) {
-    const int dy = ql % 3 - 1, dz = ql / 3 - 1;
-    const int y = cy + dy, z = cz + dz;
+  // NR candidate ranges per group, range r = (dy + DIV) + W (dz + DIV) on
+  // lane r % 16 of the group's quarter: cells cx0-DIV .. cx0+DIV of the row
+  // (cy+dy, cz+dz); their lengths' prefix (in range order) in rpre
+  const int cx0c = cx0 & 7;   // float form: the group's cell x index mod 8 (the records' x code)
+  int lens[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int r = ql + 16 * u;
     int b = 0, e = 0;
-    if (gvalid && y >= 0 && y < ny && z >= 0 && z < nz) {
-      const int row = (z * ny + y) * nx;
-      const int xlo = cx0 > 0 ? cx0 - 1 : 0, xhi = cx0 + 1 < nx ? cx0 + 1 : nx - 1;
-      b = cs[row + xlo];
-      e = cs[row + xhi + 1];
+    if (r < NR) {
+      const int dy = r % W - DIV, dz = r / W - DIV;
+      const int y = cy + dy, z = cz + dz;
+      if (gvalid && y >= 0 && y < ny && z >= 0 && z < nz) {
+        const int row = (z * ny + y) * nx;
+        const int xlo = cx0 > DIV ? cx0 - DIV : 0, xhi = cx0 + DIV < nx ? cx0 + DIV : nx - 1;
+        b = cs[row + xlo];
+        e = cs[row + xhi + 1];
+      }
+      rstart[q][r] = b;
+      if constexpr (kFix) royz[q][r] = make_int2(dy * key_, dz * kez);
     }
-    rstart[q][ql] = b;
-    len = e - b;
+    lens[u] = e - b;
   }
-  int inc = len;
-  for (int off = 1; off < 16; off <<= 1) {
-    const int v = __shfl_up(inc, off, 16);
-    if (ql >= off) inc += v;
+  int tot = 0;
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    int inc = lens[u];
+    for (int off = 1; off < 16; off <<= 1) {
+      const int v = __shfl_up(inc, off, 16);
+      if (ql >= off) inc += v;
+    }
+    if (ql + 16 * u < NR) rpre[q][ql + 16 * u + 1] = tot + inc;
+    tot += __shfl(inc, 15, 16);
   }
-  if (ql < 9) rpre[q][ql + 1] = inc;
-  if (ql == 0) rpre[q][0] = 0;
-  if (ql == 8) gtot[q] = inc;
+  if (ql == 0) {
+    rpre[q][0] = 0;
+    gtot[q] = tot;
+  }
   wave_sync();
   // the target of this lane
   const bool active = gvalid && ql < gd.y;
   R lx = 0, ly = 0, lz = 0, tw = 0;
   int ix = 0, iy = 0, iz = 0;
   int tres = 0;   // float form, packed records: the target's position residuals
-  int tdc = 0;
   double vi[3] = {0.0, 0.0, 0.0};   // HVP: the target's v
   if (active) {
+    // every target of a group is in the group's cell (cell offset 0)
     const int j = gd.x + ql;
     const PPPos<R> me = rec[j];
-    tdc = (int)(keys[j] % (uint32_t)nx) - cx0;   // 0: every target of a group is in its first cell
     if constexpr (kFix) {
-      ix = me.x + tdc * kex;
+      ix = (me.x & kFixMask) - kFixBias;
       iy = me.y;
       iz = me.z;
       tres = __float_as_int(me.w);
@@ -256,19 +280,19 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     if constexpr (HVP)
       for (int d = 0; d < 3; ++d) vi[d] = hv_in[3 * j + d];
   }
-  const R tox = (R)tdc * cux;
   // cutoff test: r^2 - lim = (|t|^2 + (|c|^2 - lim)) - 2 t.c with lim =
   // 1 + margin; the margin covers the rounding of the expanded form for
-  // positions within two cell edges of the group's corner (|c|^2 <= 12 cu^2)
+  // positions within DIV + 1 cell edges of the group's corner
+  // (|c|^2 <= 3 (DIV + 1)^2 cu^2)
   const double cmax = fmax(geo.cu[0], fmax(geo.cu[1], geo.cu[2]));
-  const R lim = (R)(1.0 + 1e-5 * fmax(1.0, 4.0 * cmax * cmax));
+  const R lim = (R)(1.0 + 1e-5 * fmax(1.0, (DIV + 1) * (DIV + 1) * cmax * cmax));
   R tx, ty, tz;
   if constexpr (kFix) {
     tx = active ? (R)ix * fu : (R)1e18;
     ty = (R)iy * fu;
     tz = (R)iz * fu;
   } else {
-    tx = active ? lx + tox : (R)1e18;
+    tx = active ? lx : (R)1e18;
     ty = ly;
     tz = lz;
   }
@@ -287,26 +311,28 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     cq[h] = (slot / kRun) * S * kRun + slot % kRun;
     int r = 0;
 #pragma unroll
-    for (int k = 1; k < 9; ++k) r += (cq[h] >= rpre[q][k]) ? 1 : 0;
+    for (int k = 1; k < NR; ++k) r += (cq[h] >= rpre[q][k]) ? 1 : 0;
     cr[h] = r;
   }
-  PPPos<R> nx_o[kPerLane];
-  int nx_c[kPerLane];
+  PPPos<R> nx_o[kPerLane] = {};
+  int nx_c[kFix ? 1 : kPerLane];   // double form: the candidate's cell x offset
   bool nx_ok[kPerLane];
   double nx_v[HVP ? kPerLane : 1][3];
+  // The loads are unconditional (a slot past the group's candidates reads
+  // the group's first particle, a valid index), so they stay in flight
+  // across the tests and hit loop of the current tile.
   auto fetch = [&](int t) {
 #pragma unroll
     for (int h = 0; h < kPerLane; ++h) {
       const int qi = cq[h] + kRun * t;
       nx_ok[h] = t < S && qi < L;
-      if (nx_ok[h]) {
+      if (nx_ok[h])
         while (qi >= rpre[q][cr[h] + 1]) ++cr[h];
-        const int k = rstart[q][cr[h]] + (qi - rpre[q][cr[h]]);
-        nx_o[h] = rec[k];
-        nx_c[h] = (int)(keys[k] % (uint32_t)nx) - cx0;
-        if constexpr (HVP)
-          for (int d = 0; d < 3; ++d) nx_v[h][d] = hv_in[3 * k + d];
-      }
+      const int k = nx_ok[h] ? rstart[q][cr[h]] + (qi - rpre[q][cr[h]]) : gd.x;
+      nx_o[h] = rec[k];
+      if constexpr (!kFix) nx_c[h] = (int)(keys[k] % (uint32_t)nx) - cx0;
+      if constexpr (HVP)
+        for (int d = 0; d < 3; ++d) nx_v[h][d] = hv_in[3 * k + d];
     }
   };
   fetch(0);
@@ -330,20 +356,26 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
 #pragma unroll
     for (int h = 0; h < kPerLane; ++h) {
       V4 c{(R)1e18, (R)0, (R)0, (R)1e30};
-      const int dy = cr[h] % 3 - 1, dz = cr[h] / 3 - 1;
       if constexpr (kFix) {
-        int4 fx = make_int4(0, 0, 0, 0);
-        if (nx_ok[h]) {
-          fx = make_int4(nx_o[h].x + nx_c[h] * kex, nx_o[h].y + dy * key_, nx_o[h].z + dz * kez,
-                         __float_as_int(nx_o[h].w));
-          c.x = (R)fx.x * fu;
-          c.y = (R)fx.y * fu;
-          c.z = (R)fx.z * fu;
-          c.w = c.x * c.x + c.y * c.y + c.z * c.z - lim;
-        }
+        // computed for every slot (a slot past the group's candidates holds
+        // a stale record) and then, past them, replaced by a far point that
+        // no cutoff test passes (|t|^2 + 1e30 - 2 t.c > 0)
+        // the candidate's cell offset along the row from the x codes (mod 8,
+        // |offset| <= DIV), its row's y, z offsets from the range
+        const int raw = nx_o[h].x;
+        const int dxc = (int)__builtin_amdgcn_sbfe((unsigned)((int)((unsigned)raw >> kXCodeShift) - cx0c), 0, 3);
+        const int2 oyz = royz[q][cr[h]];
+        const int4 fx = make_int4((raw & kFixMask) - kFixBias + dxc * kex, nx_o[h].y + oyz.x, nx_o[h].z + oyz.y,
+                                  __float_as_int(nx_o[h].w));
+        const R cx = (R)fx.x * fu, cy_ = (R)fx.y * fu, cz_ = (R)fx.z * fu;
+        c.x = nx_ok[h] ? cx : (R)1e18;
+        c.y = cy_;
+        c.z = cz_;
+        c.w = nx_ok[h] ? cx * cx + cy_ * cy_ + cz_ * cz_ - lim : (R)1e30;
         tfix[TS * q + 16 * h + ql] = fx;
       } else {
         V4 cl{(R)0, (R)0, (R)0, (R)0}, co{(R)0, (R)0, (R)0, (R)0};
+        const int dy = cr[h] % W - DIV, dz = cr[h] / W - DIV;
         if (nx_ok[h]) {
           cl = V4{nx_o[h].x, nx_o[h].y, nx_o[h].z, nx_o[h].w};
           co = V4{(R)nx_c[h] * cux, (R)dy * cuy, (R)dz * cuz, (R)0};
@@ -417,7 +449,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       } else {
         const V4 cl = tloc[TS * q + k];
         const V4 co = toff[TS * q + k];
-        dx = (lx - cl.x) + (tox - co.x);
+        dx = (lx - cl.x) - co.x;
         dy = (ly - cl.y) - co.y;
         dz = (lz - cl.z) - co.z;
         wj = cl.w;
@@ -530,23 +562,47 @@ unsigned pp_blocks(int64_t n, const Geo& geo) {
 template <typename R>
 constexpr bool kPackable = std::is_same<R, float>::value;
 
+template <typename R, int DIV>
+void launch_pp_div(unsigned blocks, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
+                   const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
+                   hipStream_t st, unsigned long long* wclock) {
+  const bool packed = std::is_same<R, float>::value && geo.wpacked;
+  if (energy && packed)
+    k_pp<R, true, kPackable<R>, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out,
+                                                                   energy);
+  else if (energy)
+    k_pp<R, true, false, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
+  else if (packed)
+    k_pp<R, false, kPackable<R>, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out,
+                                                                    nullptr, nullptr, nullptr, wclock);
+  else
+    k_pp<R, false, false, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out,
+                                                             nullptr, nullptr, nullptr, wclock);
+}
+
 template <typename R>
 void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
                hipStream_t st, unsigned long long* wclock) {
   // one wave per quad of groups; waves beyond the groups built leave at once
   const unsigned blocks = pp_blocks(n, geo);
-  const bool packed = std::is_same<R, float>::value && geo.wpacked;
-  if (energy && packed)
-    k_pp<R, true, kPackable<R>><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
-  else if (energy)
-    k_pp<R, true, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
-  else if (packed)
-    k_pp<R, false, kPackable<R>><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr,
-                                                         nullptr, nullptr, wclock);
+  if (geo.pp_div == 2)
+    launch_pp_div<R, 2>(blocks, rec, keys, cell_start, geo, desc, counter, out, energy, st, wclock);
   else
-    k_pp<R, false, false><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, nullptr, nullptr,
-                                                  nullptr, wclock);
+    launch_pp_div<R, 1>(blocks, rec, keys, cell_start, geo, desc, counter, out, energy, st, wclock);
+}
+
+template <typename R, int DIV>
+void launch_pp_hvp_div(unsigned blocks, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
+                       const Geo& geo, const int2* desc, int* counter, const double* v_sorted,
+                       double* out_sorted, hipStream_t st) {
+  const bool packed = std::is_same<R, float>::value && geo.wpacked;
+  if (packed)
+    k_pp<R, false, kPackable<R>, true, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo,
+                                                                   nullptr, nullptr, v_sorted, out_sorted);
+  else
+    k_pp<R, false, false, true, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
+                                                            nullptr, v_sorted, out_sorted);
 }
 
 template <typename R>
@@ -555,13 +611,10 @@ void launch_pp_hvp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const i
                    hipStream_t st) {
   // the tiled pair kernel in its Hessian-vector mode, over the cell sort's groups
   const unsigned blocks = pp_blocks(n, geo);
-  const bool packed = std::is_same<R, float>::value && geo.wpacked;
-  if (packed)
-    k_pp<R, false, kPackable<R>, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
-                                                              nullptr, v_sorted, out_sorted);
+  if (geo.pp_div == 2)
+    launch_pp_hvp_div<R, 2>(blocks, rec, keys, cell_start, geo, desc, counter, v_sorted, out_sorted, st);
   else
-    k_pp<R, false, false, true><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
-                                                       nullptr, v_sorted, out_sorted);
+    launch_pp_hvp_div<R, 1>(blocks, rec, keys, cell_start, geo, desc, counter, v_sorted, out_sorted, st);
 }
 template void launch_pp_hvp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
                                    const int2*, int*, const double*, double*, hipStream_t);

@@ -204,19 +204,21 @@ __global__ void __launch_bounds__(kThreads) k_cell_scatter(int64_t n, const uint
 }
 
 template <typename R>
-__device__ __forceinline__ PPPos<R> make_pos(const double* loc, const double* cu, double w, bool packed);
+__device__ __forceinline__ PPPos<R> make_pos(const double* loc, const double* cu, int cx, double w, bool packed);
 template <>
-__device__ __forceinline__ PPPos<double> make_pos<double>(const double* loc, const double*, double w, bool) {
+__device__ __forceinline__ PPPos<double> make_pos<double>(const double* loc, const double*, int, double w, bool) {
   return PPPos<double>{loc[0], loc[1], loc[2], w};
 }
 // Nearest fixed-point value. Inside the mesh a particle lies in [0, 1] cell
 // edges of its cell's corner; one outside it (reported as a domain error)
-// is clamped to [-1/2, 3/2) edges, which keeps every PP separation, cell
-// offsets included, below 2^31 units (an edge is at most 2^29 units).
+// is clamped to [-1/2, 3/2) edges. An edge is at most 2^kFixBits = 2^28
+// units, so the position plus the bias 2^27 lies in [0, 2^29) and the x
+// slot holds (v + kFixBias) | (cx mod 8) << kXCodeShift; every PP
+// separation, cell offsets of up to two edges included, stays below 2^31.
 // packed (every weight 1): the weight slot holds the residuals u - rint(u),
 // rounded to 2^-kResBits units, as three 10-bit fields (x lowest).
 template <>
-__device__ __forceinline__ PPPos<float> make_pos<float>(const double* loc, const double* cu, double w,
+__device__ __forceinline__ PPPos<float> make_pos<float>(const double* loc, const double* cu, int cx, double w,
                                                         bool packed) {
   const double unit = fix_unit(cu);
   int v[3];
@@ -229,6 +231,7 @@ __device__ __forceinline__ PPPos<float> make_pos<float>(const double* loc, const
     const int r = min(max((int)rint((u - v[d]) * (1 << kResBits)), -511), 511);
     res |= ((unsigned)r & 1023u) << (10 * d);
   }
+  v[0] = (int)(((unsigned)(v[0] + kFixBias) & (unsigned)kFixMask) | (((unsigned)cx & 7u) << kXCodeShift));
   return PPFix{v[0], v[1], v[2], packed ? __uint_as_float(res) : (float)w};
 }
 
@@ -269,7 +272,7 @@ __global__ void __launch_bounds__(kThreads) k_reorder(
                                                         : c[d] * geo.cu[d];
     loc[d] = (xi[d] - P.x0[d]) * P.inv_lu - corner;
   }
-  pp[j] = make_pos<R>(loc, geo.cu, w, geo.wpacked != 0);
+  pp[j] = make_pos<R>(loc, geo.cu, c[0], w, geo.wpacked != 0);
   // Mesh record: stencil origin and fractional offset (Sec. 2.4.2 B-splines).
   // CIC: base floor(u), offset u - base in [0, 1).
   // TSC: centre floor(u + 1/2), offset u - centre in [-1/2, 1/2), base centre - 1.

@@ -45,7 +45,7 @@ INFLUENCE_SAMPLED, INFLUENCE_OPTIMAL, INFLUENCE_PRINCIPAL, INFLUENCE_LATTICE = 0
 class Opts(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("zoom", ctypes.c_int32),
                 ("gather", ctypes.c_int32), ("mesh_precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("ke", ctypes.c_double), ("q", ctypes.c_double),
+                ("pp_cell_div", ctypes.c_int32), ("ke", ctypes.c_double), ("q", ctypes.c_double),
                 ("m", ctypes.c_double), ("boundary", ctypes.c_int32), ("influence", ctypes.c_int32),
                 ("cathode_z", ctypes.c_double)]
 
@@ -114,7 +114,7 @@ class Context:
 
     def __init__(self, grid, h, r_cut, split, order=TSC, precision=FP64, zoom=True, ke=8.9875517923e9,
                  q=1.0, m=1.0, mesh_precision=MESH_AUTO, gather=GATHER_VARIATIONAL, cathode_z=None,
-                 influence=INFLUENCE_SAMPLED):
+                 influence=INFLUENCE_SAMPLED, pp_cell_div=0):
         L = lib()
         o = Opts()
         L.p3m_default_opts(ctypes.byref(o))
@@ -125,6 +125,7 @@ class Context:
         if cathode_z is not None:
             o.boundary, o.cathode_z = BOUNDARY_CATHODE, float(cathode_z)
         o.influence = int(influence)
+        o.pp_cell_div = int(pp_cell_div)
         g = (ctypes.c_int32 * 3)(*[int(v) for v in grid])
         hh = (ctypes.c_double * 3)(*[float(v) for v in h])
         self._ctx = ctypes.c_void_p()
@@ -136,6 +137,7 @@ class Context:
 
     @classmethod
     def from_workload(cls, wl, precision=FP64, **kw):
+        kw.setdefault("pp_cell_div", wl.pp_cell_div)
         return cls(wl.grid, wl.h, wl.r_cut, wl.split, order=wl.order, precision=precision,
                    q=wl.q, m=wl.m, **kw)
 

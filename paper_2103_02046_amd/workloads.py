@@ -47,6 +47,7 @@ class Workload:
     m: float             # macro-particle mass [kg]
     n0: float            # initial peak number density [1/m^3]
     seed: int = 0
+    pp_cell_div: int = 1  # PP cells per cutoff along each axis (2: half-size cells, for dense cores)
 
     @property
     def ke_q2(self) -> float:
@@ -164,8 +165,10 @@ def halo_tsc(n=1 << 25, grid=512, steps=50, seed=0):
     q, m = _macro(n)
     n_core, _ = halo_split(n)
     n0 = n_core / ((2 * math.pi) ** 1.5 * sigma_c ** 3)
+    # the core holds ~10^3 particles per cutoff cube: half-size PP cells
+    # (about 10^2 each) still fill the pair kernel's groups of 16
     return Workload("halo", n, (grid,) * 3, (h,) * 3, rc, 3.0 / rc, TSC,
-                    _dt(n0, q, m), steps, q, m, n0, seed)
+                    _dt(n0, q, m), steps, q, m, n0, seed, pp_cell_div=2)
 
 
 CONFIGS = {

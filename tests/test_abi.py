@@ -36,7 +36,7 @@ def test_default_opts_and_argument_errors_without_gpu():
     L = p3m.lib()
     o = p3m.Opts()
     assert L.p3m_default_opts(ctypes.byref(o)) == p3m.OK
-    assert (o.order, o.precision, o.zoom, o.gather, o.reserved) == (p3m.TSC, p3m.FP64, 1, p3m.GATHER_VARIATIONAL, 0)
+    assert (o.order, o.precision, o.zoom, o.gather, o.pp_cell_div) == (p3m.TSC, p3m.FP64, 1, p3m.GATHER_VARIATIONAL, 0)
     assert o.ke == pytest.approx(8.9875517923e9)
     assert L.p3m_default_opts(None) == p3m.EINVAL
     ctx = ctypes.c_void_p()
@@ -54,6 +54,10 @@ def test_default_opts_and_argument_errors_without_gpu():
     g = (ctypes.c_int32 * 3)(16, 16, 16)
     hh = (ctypes.c_double * 3)(1, 1, 1)
     assert L.p3m_create(ctypes.byref(ctx), g, hh, 1.0, 1.0, ctypes.byref(bad)) == p3m.EINVAL
+    for div in (-1, 3):   # PP cells per cutoff: 0 (default 1), 1 or 2
+        L.p3m_default_opts(ctypes.byref(bad))
+        bad.pp_cell_div = div
+        assert L.p3m_create(ctypes.byref(ctx), g, hh, 1.0, 1.0, ctypes.byref(bad)) == p3m.EINVAL
     assert L.p3m_last_error(None) == b"null context"
     L.p3m_destroy(None)
 

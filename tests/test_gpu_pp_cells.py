@@ -1,0 +1,154 @@
+"""PP cells of half the cutoff (p3m_opts.pp_cell_div = 2) against the oracle.
+
+With cell edges >= r_c/2 the pair kernel reads the 5 x 5 rows of 5 cells
+around each group's cell (125 half-size cells) instead of 3 x 3 rows of 3
+cells. The pair set is the same strict-cutoff set either way (the oracle's
+cell list and O(N^2) pins fix it), so the PP force must match the oracle to
+the same bounds as with whole-cutoff cells: float64 within 1e-11 relative
+rms, float-compensated within 1e-5, plus per-particle bounds; the ordered
+pair count of the float64 path must equal a k-d tree's count exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial import cKDTree
+
+from oracle import oracle as O
+from paper_2103_02046_amd import p3m
+from paper_2103_02046_amd import workloads as W
+from parity_util import per_particle, rms_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 1e-5
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def cases():
+    return {
+        "gauss4k": W.get("gauss4k"),                                # CIC, 32^3, sparse cells
+        "aniso32k": W.aniso_tsc(n=1 << 15, grid=32, steps=5),      # TSC, anisotropic cells
+        "dense": W.aniso_tsc(n=1 << 16, grid=16, steps=5),         # ~10^2 particles per half cell
+    }
+
+
+@pytest.mark.parametrize("name", ["gauss4k", "aniso32k", "dense"])
+@pytest.mark.parametrize("precision,tol", [(p3m.FP64, TOL64), (p3m.FP32C, TOL32)])
+def test_half_cells_pp_parity(name, precision, tol):
+    wl = cases()[name]
+    x, _ = wl.draw()
+    prm = O.Params.from_workload(wl)
+    _, parts = O.forces(x, prm, parts=True)
+    c = p3m.Context.from_workload(wl, precision=precision, pp_cell_div=2)
+    assert c.info()["ncells"] > 4 * p3m.Context.from_workload(wl, precision=precision).info()["ncells"]
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    fpp, fpm = host(fpp), host(fpm)
+    e_pp, e_pm = rms_err(fpp, parts["pp"]), rms_err(fpm, parts["pm"])
+    worst, own, k = per_particle(fpp, parts["pp"])
+    print(f"{name} precision {precision} half cells: pp {e_pp:.2e} (worst particle {worst:.2e} of rms, "
+          f"{own:.2e} of its own) pm {e_pm:.2e}", flush=True)
+    assert e_pp < tol and e_pm < tol
+    # a single particle on a wrong path would show here: float64 to 1e-9 of
+    # the rms pair force, float-compensated to 1e-4
+    assert worst < (1e-9 if precision == p3m.FP64 else 1e-4)
+    assert c.status_sync() == p3m.OK
+
+
+@pytest.mark.parametrize("name", ["gauss4k", "dense"])
+def test_half_cells_pair_count_exact(name):
+    """The float64 diagnostics count the ordered in-cutoff pairs in the pair
+    kernel: the same integer with either cell size and from a k-d tree."""
+    wl = cases()[name]
+    x, p = wl.draw()
+    n1 = p3m.Context.from_workload(wl).diagnostics(dev(x), dev(p))["pairs"]
+    n2 = p3m.Context.from_workload(wl, pp_cell_div=2).diagnostics(dev(x), dev(p))["pairs"]
+    rc = O.placement(x, O.Params.from_workload(wl))["rc"]
+    ref = 2 * len(cKDTree(x).query_pairs(rc))   # a k-d tree's unordered pairs within r_c (ties: measure zero)
+    print(f"{name}: ordered pairs {n1:.0f} (whole cells) {n2:.0f} (half cells) k-d tree {ref}", flush=True)
+    assert n1 == n2 == ref
+
+
+@pytest.mark.parametrize("grid", [(4, 4, 4), (8, 16, 32), (64, 8, 16)])
+def test_half_cells_ragged_grids(grid):
+    """Few cells per axis (the neighbourhood clipped at the grid's faces)
+    and anisotropic cell counts."""
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((700, 3)) * np.array([1.0, 0.7, 1.3])
+    h = (0.4, 0.3, 0.5)
+    prm = O.Params(grid, h, 0.7, 3.0 / 0.7, 2, 1.0)
+    _, parts = O.forces(x, prm, parts=True)
+    for precision, tol in ((p3m.FP64, TOL64), (p3m.FP32C, TOL32)):
+        c = p3m.Context(grid, h, 0.7, 3.0 / 0.7, order=2, ke=1.0, q=1.0, precision=precision, pp_cell_div=2)
+        fpp, _, _ = c.forces_parts(dev(x))
+        assert rms_err(host(fpp), parts["pp"]) < tol
+
+
+def test_half_cells_close_pairs_across_cell_boundaries():
+    """Close pairs straddling a half-size cell boundary on every axis, with
+    cell edges that are not whole multiples of each other: the candidate's
+    cell offset along its row comes from the x code of its record, the
+    other two from its row; the separation must stay the exact difference
+    of the fixed-point positions, so the residual fields keep close pairs
+    at float precision."""
+    rng = np.random.default_rng(26)
+    n, grid = 8192, 32
+    h = (1e-4, 1e-4, 1.37e-4)
+    rc = 2.3e-4
+    x = rng.standard_normal((n, 3)) * np.array([6e-4, 6e-4, 9e-4])
+    prm = O.Params((grid,) * 3, h, rc, 3.0 / rc, 2, 1.0, m=1.0)
+    pl = O.placement(x, prm)
+    s = pl["s"]
+    ncell = [max(1, math.floor((grid - 1) * h[d] * 2 / rc)) for d in range(3)]
+    cell = [s * (grid - 1) * h[d] / ncell[d] for d in range(3)]
+    m = 36
+    first = rng.choice(n // 2, m, replace=False)
+    second = n // 2 + first
+    for k in range(m):
+        d = k % 3
+        c = round((x[first[k], d] - pl["x0"][d]) / cell[d])
+        c = min(max(c, 1), ncell[d] - 1)
+        zb = pl["x0"][d] + c * cell[d]
+        sep = s * rc * 10.0 ** rng.uniform(-5, -3)
+        u = rng.standard_normal(3) * 0.3 * sep
+        u[d] = 0.0
+        x[first[k], d] = zb - 0.5 * sep
+        x[second[k]] = x[first[k]] + u
+        x[second[k], d] = zb + 0.5 * sep
+    pl = O.placement(x, prm)
+    assert pl["s"] == pytest.approx(s, rel=1e-12)
+    idx = np.concatenate([first, second])
+    ref = O.pp_sample(x, prm, pl["rc"], pl["a"], idx)
+    c = p3m.Context((grid,) * 3, h, rc, 3.0 / rc, order=2, precision=p3m.FP32C, ke=1.0, q=1.0, m=1.0,
+                    pp_cell_div=2)
+    fpp, _, _ = c.forces_parts(dev(x))
+    got = host(fpp)[idx]
+    rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    print(f"half cells, close pairs across cell boundaries: max rel pp error {rel.max():.2e}", flush=True)
+    assert rel.max() < 3e-6
+
+
+@pytest.mark.parametrize("precision,tol", [(p3m.FP64, 1e-10), (p3m.FP32C, 1e-5)])
+def test_half_cells_hvp_parity(precision, tol):
+    """The pair kernel's Hessian-vector mode over half-size cells."""
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((600, 3))
+    prm = O.Params((16, 16, 16), (0.3,) * 3, 0.6, 3.0 / 0.6, 2, 1.0, m=1.0, dt=0.01)
+    v = rng.standard_normal(x.shape)
+    c = p3m.Context(prm.grid, prm.h, prm.r_cut, prm.split, order=2, ke=1.0, q=1.0, m=1.0, precision=precision,
+                    pp_cell_div=2)
+    out = host(c.hvp(dev(x), dev(v)))
+    ref = O.hvp(x, v, prm, O.placement(x, prm))
+    e = rms_err(out, ref)
+    print(f"half cells HVP precision {precision}: {e:.2e}", flush=True)
+    assert e < tol
