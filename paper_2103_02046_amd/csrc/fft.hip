@@ -559,6 +559,227 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_z_reg(Geo geo, C2<float>* _
   }
 }
 
+// ---- float lines of 1024 points held in registers (y and z passes) -----------
+// 1024 = 16 x 16 x 4, w = e^{-2 pi i / 1024}. With n = r + 64 m (r < 64,
+// m < 16), r = p + 4 q (p < 4, q < 16) and k = k1 + 16 c + 256 d (k1, c < 16,
+// d < 4):
+//   X[k] = sum_p w4^(p d) w^(16 p c) sum_q w16^(q c) [w^(r k1) sum_m x[r + 64 m] w16^(m k1)].
+// A block of 256 threads holds B = 4 lines (b = t % 4, consecutive k_x):
+//   phase A, thread (b, r = t / 4): its 16 points x[r + 64 m], a DFT-16 over m,
+//     twiddles w^(r k1); LDS transpose;
+//   phase B, thread (b, p = (t / 4) % 4, k1 = t / 16): a DFT-16 over q,
+//     twiddles w^(16 p c); LDS transpose;
+//   phase C, thread (b, c4 = (t / 4) % 4, k1): DFT-4s over p, after which it
+//     holds X[k1 + 16 (4 c4 + j) + 256 d] for j, d < 4 at v[4 j + d].
+// The transposed network takes that layout back: with the same index
+// splitting read the other way, Z[r + 64 m] = sum_{k1} w16^(k1 m) w^(k1 r)
+// sum_c w16^(c q) w^(16 c p) sum_d w4^(d p) y[k1 + 16 c + 256 d] is a forward
+// transform from the C layout to the A layout (DFT-4s in registers, two LDS
+// transposes, DFT-16s), so a line multiplied in the C layout goes straight
+// into the inverse. The LDS rows of one k1 are kPad1k entries apart, so the
+// four k1 of a wave's reads fall in different banks.
+constexpr int kReg1k = 1024;
+constexpr int kPad1k = 4 * 64 + 16;
+
+__device__ __forceinline__ void fwd1k(C2<float>* v, C2<float>* s, const C2<float>* __restrict__ tw) {
+  const int t = threadIdx.x, b = t & 3;
+  {
+    const int r = t >> 2;
+    dft16(v);
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[r * k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) s[k1 * kPad1k + 4 * r + b] = v[k1];
+  }
+  __syncthreads();
+  const int p = (t >> 2) & 3, k1 = t >> 4;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = s[k1 * kPad1k + 4 * (p + 4 * q) + b];
+  dft16(v);
+#pragma unroll
+  for (int c = 1; c < 16; ++c) v[c] = cmul(v[c], tw[16 * p * c]);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 16; ++c) s[k1 * kPad1k + ((c & 3) * 4 + p) * 16 + (c >> 2) * 4 + b] = v[c];
+  __syncthreads();
+  const int c4 = p;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    C2<float> u[4];
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) u[pp] = s[k1 * kPad1k + (j * 4 + pp) * 16 + c4 * 4 + b];
+    dft4(u);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) v[4 * j + d] = u[d];
+  }
+}
+
+// The transposed network: v[4 j + d] = y[k1 + 16 (4 c4 + j) + 256 d] on entry
+// (C layout), v[m] = Z[r + 64 m] on return (A layout), Z the forward
+// transform of y. The caller syncs before it if s was being read.
+__device__ __forceinline__ void fwd1k_t(C2<float>* v, C2<float>* s, const C2<float>* __restrict__ tw) {
+  const int t = threadIdx.x, b = t & 3, c4 = (t >> 2) & 3, k1 = t >> 4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    C2<float> u[4] = {v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
+    dft4(u);   // over d, output index p
+    const int c = 4 * c4 + j;
+#pragma unroll
+    for (int pp = 0; pp < 4; ++pp) {
+      const C2<float> x = pp ? cmul(u[pp], tw[16 * c * pp]) : u[0];
+      s[k1 * kPad1k + (j * 4 + pp) * 16 + c4 * 4 + b] = x;
+    }
+  }
+  __syncthreads();
+  const int p = c4;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) v[c] = s[k1 * kPad1k + ((c & 3) * 4 + p) * 16 + (c >> 2) * 4 + b];
+  dft16(v);   // over c, output index q
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = k1 * (p + 4 * q);
+    if (q || p) v[q] = cmul(v[q], tw[e]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s[k1 * kPad1k + 4 * (p + 4 * q) + b] = v[q];
+  __syncthreads();
+  const int r = t >> 2;
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) v[kk] = s[kk * kPad1k + 4 * r + b];
+  dft16(v);   // over k1, output index m
+}
+
+// Frequency held at v[e] in the C layout: k1 + 16 (4 c4 + j) + 256 d, e = 4 j + d.
+__device__ __forceinline__ int c1k_freq(int e) {
+  const int t = threadIdx.x;
+  return (t >> 4) + 16 * (4 * ((t >> 2) & 3) + (e >> 2)) + 256 * (e & 3);
+}
+
+// z pass on 1024-point float lines, free space: forward (N = 512 inputs),
+// times the kernel table, inverse, keep z < N; DIFF: also the inverse of the
+// product times dz(k_z) = e^{2 pi i k_z / L} - 1 into S2 (the z difference).
+// Block order as k_fft_z (line_block, 4 k_x per block).
+template <bool DIFF>
+__global__ void __launch_bounds__(kFftThreads) k_fft_z_1k(Geo geo, C2<float>* __restrict__ S,
+                                                          const float* __restrict__ gz,
+                                                          const C2<float>* __restrict__ tw,
+                                                          C2<float>* __restrict__ S2,
+                                                          const C2<float>* __restrict__ dz) {
+  constexpr int L = kReg1k, N = L / 2, B = 4;
+  __shared__ C2<float> s[16 * kPad1k];
+  const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
+  const int ly = 2 * geo.grid[1];
+  int ky, kx0;
+  if (!line_block<Cfg<float, L>::G>((K + B - 1) / B, ly, ky, kx0, B)) return;
+  const int t = threadIdx.x, b = t & 3, r = t >> 2;
+  const int kx = kx0 + b;
+  const bool valid = kx < K;
+  const long long zstride = (long long)ly * KS;
+  C2<float>* base = S + (long long)ky * KS + kx;
+  C2<float> v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m)
+    v[m] = (m < 8 && valid) ? base[(long long)(r + 64 * m) * zstride] : C2<float>{0.f, 0.f};
+  // the kernel table at this thread's frequencies, loaded before the transform
+  const int kyp = ky <= geo.grid[1] ? ky : ly - ky;
+  const long long gplane_s = (long long)(geo.grid[1] + 1) * KS;
+  const float* grow = gz + (long long)kyp * KS + (valid ? kx : K - 1);
+  float g[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int kz = c1k_freq(e);
+    g[e] = grow[(kz <= N ? kz : L - kz) * gplane_s];
+  }
+  fwd1k(v, s, tw);
+  // conj(Ghat Z): the input of the inverse
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = C2<float>{g[e] * v[e].x, -(g[e] * v[e].y)};
+  C2<float> hold[DIFF ? 16 : 1];
+  if constexpr (DIFF) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) hold[e] = v[e];
+  }
+  __syncthreads();   // phase C's reads of s are done
+  fwd1k_t(v, s, tw);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) base[(long long)(r + 64 * m) * zstride] = C2<float>{v[m].x, -v[m].y};
+  }
+  if constexpr (DIFF) {
+    // conj(g Z dz) = conj(g Z) conj(dz)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = cmul(hold[e], cconj(dz[c1k_freq(e)]));
+    __syncthreads();
+    fwd1k_t(v, s, tw);
+    if (valid) {
+      C2<float>* base2 = S2 + (long long)ky * KS + kx;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) base2[(long long)(r + 64 * m) * zstride] = C2<float>{v[m].x, -v[m].y};
+    }
+  }
+}
+
+// y pass on 1024-point float lines: forward (N inputs, all outputs, C-layout
+// stores) or inverse (all inputs loaded in the C layout, N outputs kept),
+// conjugating around the transposed network; DIFF (inverse only): also the
+// inverse of the line times dy(k_y) into S3 (the y difference).
+template <bool INV, bool DIFF>
+__global__ void __launch_bounds__(kFftThreads) k_fft_y_1k(Geo geo, C2<float>* __restrict__ S,
+                                                          const C2<float>* __restrict__ tw,
+                                                          C2<float>* __restrict__ S3,
+                                                          const C2<float>* __restrict__ dy) {
+  static_assert(INV || !DIFF, "the difference form acts on the inverse pass");
+  constexpr int L = kReg1k, B = 4;
+  __shared__ C2<float> s[16 * kPad1k];
+  const int K = geo.grid[0] + 1, KS = spec_stride(geo.grid[0]);
+  int z, kx0;
+  if (!line_block<Cfg<float, L>::G>((K + B - 1) / B, geo.grid[2], z, kx0, B)) return;
+  const int t = threadIdx.x, b = t & 3, r = t >> 2;
+  const int kx = kx0 + b;
+  const bool valid = kx < K;
+  C2<float>* base = S + (long long)z * L * KS + kx;
+  C2<float> v[16];
+  if constexpr (!INV) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m)
+      v[m] = (m < 8 && valid) ? base[(long long)(r + 64 * m) * KS] : C2<float>{0.f, 0.f};
+    fwd1k(v, s, tw);
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) base[(long long)c1k_freq(e) * KS] = v[e];
+    }
+  } else {
+    // conj of the spectrum in the C layout
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      C2<float> x = valid ? base[(long long)c1k_freq(e) * KS] : C2<float>{0.f, 0.f};
+      v[e] = C2<float>{x.x, -x.y};
+    }
+    C2<float> hold[DIFF ? 16 : 1];
+    if constexpr (DIFF) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) hold[e] = v[e];
+    }
+    fwd1k_t(v, s, tw);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) base[(long long)(r + 64 * m) * KS] = C2<float>{v[m].x, -v[m].y};
+    }
+    if constexpr (DIFF) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = cmul(hold[e], cconj(dy[c1k_freq(e)]));
+      __syncthreads();
+      fwd1k_t(v, s, tw);
+      if (valid) {
+        C2<float>* base3 = S3 + (long long)z * L * KS + kx;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) base3[(long long)(r + 64 * m) * KS] = C2<float>{v[m].x, -v[m].y};
+      }
+    }
+  }
+}
+
 // x passes on 256-point float lines (two real rows of N = 128 per complex
 // line): the same 16 x 16 transform, with the lanes of a line along the
 // row (index fastest) so that loads and stores run along rows. The LDS rows
@@ -937,6 +1158,11 @@ void run_y(const Geo& g, C2<T>* S, const C2<T>* tw, hipStream_t st) {
     k_fft_y_reg<INV><<<(unsigned)(g.grid[2] * ((K + 15) / 16)), kFftThreads, 0, st>>>(g, S, tw);
     return;
   }
+  if constexpr (std::is_same<T, float>::value && L == kReg1k) {
+    static_assert(B == 4, "1024-point register lines take 4 k_x per block");
+    k_fft_y_1k<INV, false><<<line_grid<T, L>(g.grid[2], K), kFftThreads, 0, st>>>(g, S, tw, nullptr, nullptr);
+    return;
+  }
   k_fft_y<T, L, INV><<<line_grid<T, L>(g.grid[2], K), kFftThreads, 0, st>>>(g, S, tw);
 }
 template <typename T, int L>
@@ -948,6 +1174,12 @@ void run_z(const Geo& g, C2<T>* S, const T* gz, const C2<double>* gimg, const C2
     if (!gimg) {
       const unsigned slots = (unsigned)((z_reg_groups(g) + kXcds - 1) / kXcds * 4 * kXcds);
       k_fft_z_reg<<<slots, kFftThreads, 0, st>>>(g, S, gz, tw);
+      return;
+    }
+  }
+  if constexpr (std::is_same<T, float>::value && L == kReg1k) {
+    if (!gimg) {
+      k_fft_z_1k<false><<<blocks, kFftThreads, 0, st>>>(g, S, gz, tw, nullptr, nullptr);
       return;
     }
   }
@@ -1040,14 +1272,24 @@ void launch_convolve_diff(const Geo& g, const R* Q, C2<R>* S, C2<R>* S2, C2<R>* 
   const long long rows = (long long)g.grid[1] * g.grid[2];
 #define XF(L) run_x_fwd<R, L>(g, Q, S, tw[0], st)
 #define YF(L) run_y<R, L, false>(g, S, tw[1], st)
-#define ZD(L)                                                                     \
-  k_fft_z<R, L, false, true><<<line_grid<R, L>(2 * g.grid[1], K), kFftThreads, 0, st>>>( \
-      g, S, gz, nullptr, tw[2], S2, dtab[2])
+#define ZD(L)                                                                                \
+  do {                                                                                       \
+    const unsigned nb = line_grid<R, L>(2 * g.grid[1], K);                                   \
+    if constexpr (std::is_same<R, float>::value && L == kReg1k)                              \
+      k_fft_z_1k<true><<<nb, kFftThreads, 0, st>>>(g, S, gz, tw[2], S2, dtab[2]);           \
+    else                                                                                     \
+      k_fft_z<R, L, false, true><<<nb, kFftThreads, 0, st>>>(g, S, gz, nullptr, tw[2], S2, dtab[2]); \
+  } while (0)
 #define YD(L)                                                                                \
   do {                                                                                       \
     const unsigned nb = line_grid<R, L>(g.grid[2], K);                                       \
-    k_fft_y<R, L, true, true><<<nb, kFftThreads, 0, st>>>(g, S, tw[1], S3, dtab[1]);         \
-    k_fft_y<R, L, true, false><<<nb, kFftThreads, 0, st>>>(g, S2, tw[1]);                    \
+    if constexpr (std::is_same<R, float>::value && L == kReg1k) {                            \
+      k_fft_y_1k<true, true><<<nb, kFftThreads, 0, st>>>(g, S, tw[1], S3, dtab[1]);          \
+      k_fft_y_1k<true, false><<<nb, kFftThreads, 0, st>>>(g, S2, tw[1], nullptr, nullptr);   \
+    } else {                                                                                 \
+      k_fft_y<R, L, true, true><<<nb, kFftThreads, 0, st>>>(g, S, tw[1], S3, dtab[1]);       \
+      k_fft_y<R, L, true, false><<<nb, kFftThreads, 0, st>>>(g, S2, tw[1]);                  \
+    }                                                                                        \
   } while (0)
 #define XD(L)                                                                                \
   do {                                                                                       \

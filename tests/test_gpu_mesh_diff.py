@@ -110,3 +110,58 @@ def test_float_mesh_difference_form_step_and_energy():
     d = c.diagnostics(xd, pd)
     r = O.diagnostics(host(xd), host(pd), prm)
     assert d["u_pm"] == pytest.approx(r["u_pm"], rel=1e-5)
+
+
+@pytest.mark.parametrize("grid", [(16, 16, 512), (16, 512, 16), (512, 16, 16), (32, 512, 512)])
+def test_float_mesh_1024_point_lines(grid):
+    """Meshes with 512-node axes (1024-point zero-padded lines, the
+    register-resident transform of the y and z passes): a 2^18-particle ball
+    stretched along the mesh, float32 mesh in the difference form, against
+    the oracle element by element: total force, mesh part and, on request,
+    the potential."""
+    n = 1 << 18
+    wl = W.sphere_tsc(n=n, grid=256)
+    x, _ = wl.draw()
+    x = x * (np.asarray(grid, float) / 256.0)
+    h = tuple(wl.h[0] for _ in range(3))
+    rc = 2.5 * h[0]
+    prm = O.Params(grid, h, rc, 3.0 / rc, 2, wl.ke_q2, wl.m)
+    ref, parts = O.forces(x, prm, parts=True)
+    c = p3m.Context(grid, h, rc, 3.0 / rc, order=2, precision=p3m.FP32C, q=wl.q, m=wl.m,
+                    mesh_precision=p3m.MESH_F32)
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    fpp, fpm = host(fpp), host(fpm)
+    e = rms_err(fpp + fpm, ref)
+    e_pm = rms_err(fpm, parts["pm"], ref)
+    e_rms_max, e_max, k = per_particle(fpp + fpm, ref)
+    phi = host(c.mesh(1))
+    e_phi = rms_err(phi, parts["phi"])
+    print(f"grid {grid}: total {e:.3e}, pm share {e_pm:.3e} (own rms {rms_err(fpm, parts['pm']):.3e}); "
+          f"per particle max |dF|/rms {e_rms_max:.3e}, max |dF|/max(|F|, rms) {e_max:.3e}; phi {e_phi:.3e}",
+          flush=True)
+    assert e < TOL32 and e_pm < TOL32 and e_max < TOL32_MAX and e_phi < 1e-5
+    assert c.status_sync() == p3m.OK
+
+
+@pytest.mark.parametrize("grid", [(16, 16, 512), (16, 512, 16)])
+def test_float_potential_form_1024_point_lines(grid):
+    """The potential form on 1024-point float lines (the momentum-conserving
+    gather takes phi itself, so the z and y passes run their plain forward and
+    inverse transforms): the potential node by node against the oracle's."""
+    n = 1 << 16
+    wl = W.sphere_tsc(n=n, grid=256)
+    x, _ = wl.draw()
+    x = x * (np.asarray(grid, float) / 256.0)
+    h = tuple(wl.h[0] for _ in range(3))
+    rc = 2.5 * h[0]
+    prm = O.Params(grid, h, rc, 3.0 / rc, 2, wl.ke_q2, wl.m, gather="momentum")
+    _, parts = O.forces(x, prm, parts=True)
+    c = p3m.Context(grid, h, rc, 3.0 / rc, order=2, precision=p3m.FP32C, q=wl.q, m=wl.m,
+                    mesh_precision=p3m.MESH_F32, gather=p3m.GATHER_MOMENTUM)
+    assert c.info()["mesh_bits"] == 32
+    fpp, fpm, _ = c.forces_parts(dev(x))
+    phi = host(c.mesh(1))
+    e_phi = rms_err(phi, parts["phi"])
+    e_pm = rms_err(host(fpm), parts["pm"])
+    print(f"grid {grid} potential form: phi {e_phi:.3e}, pm {e_pm:.3e}", flush=True)
+    assert e_phi < 1e-5 and e_pm < 1e-4
