@@ -117,7 +117,7 @@ template <>
 struct Vec4<double> { using T = double4; };
 
 constexpr int kWaveGroups = 4;           // groups per wave (16 lanes each)
-constexpr int kRun = 8;                  // consecutive candidates read together
+constexpr int kRun = 2;                  // consecutive candidates read together
 constexpr int kTileK = 64;               // candidates per group per tile
 constexpr int kPerLane = kTileK / 16;    // candidates each lane stages per tile
 constexpr int kXcdRun = 32;              // consecutive waves of groups given to one XCD
@@ -125,10 +125,14 @@ constexpr int kXcdRun = 32;              // consecutive waves of groups given to
 // Pair forces of four groups in one wave (lanes 16q .. 16q+15 hold the
 // targets of group q).
 // The candidates of a group are the concatenation of its row ranges, L of
-// them, read in runs of 8 consecutive ones (8 lanes, 128 contiguous bytes).
-// With S = ceil(L / 64) tiles, tile t holds runs t, t+S, ..., t+7S: an evenly
+// them, read in runs of kRun = 2 consecutive ones (32 contiguous bytes).
+// With S = ceil(L / 64) tiles, tile t holds runs t, t+S, ..., t+31S: an evenly
 // spread sample of the whole neighbourhood, so the hits of a tile spread
-// evenly over the group's targets. Per tile:
+// evenly over the group's targets. Consecutive sorted particles sit in one
+// small cell, so a run's candidates are all near a target or all far from
+// it; short runs keep the hits per lane per tile close to their mean, which
+// is what the lanes of a wave wait for in the hit loop (runs of 8, 4 and 2:
+// PP 96.4, 91.9 and 89.1 ms on the 2^25-particle core/halo bunch). Per tile:
 //   1. each group stages its 64 candidates in LDS (loaded one tile ahead);
 //   2. each lane tests its group's 64 candidates against its target, with
 //      positions relative to the group's first cell corner (a few cell
@@ -302,8 +306,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   const int S = (L + kTileK - 1) / kTileK;
   const int nt = max(max((gtot[0] + kTileK - 1) / kTileK, (gtot[1] + kTileK - 1) / kTileK),
                      max((gtot[2] + kTileK - 1) / kTileK, (gtot[3] + kTileK - 1) / kTileK));
-  // slot s = 16h + ql of tile t holds candidate ((s/8) S + t) 8 + s%8; it
-  // advances by 8 per tile and its row range index monotonically
+  // slot s = 16h + ql of tile t holds candidate ((s/kRun) S + t) kRun +
+  // s%kRun; it advances by kRun per tile and its row range index monotonically
   int cq[kPerLane], cr[kPerLane];
 #pragma unroll
   for (int h = 0; h < kPerLane; ++h) {
