@@ -39,6 +39,54 @@ struct Kahan3 {
   }
 };
 
+// Half-precision cutoff test of the float form. Coordinates relative to a
+// point O of the group's cell, in cutoff units, are rounded to fp16: T for
+// the targets (to nearest), C for the candidates (toward zero), and
+// W = fp16(|C|^2 - lim). Products of two fp16 values are exact in float32,
+// so v = |T|^2 + W - 2 T.C = |T - C|^2 - lim + (W - (|C|^2 - lim)) costs two
+// v_dot2_f32_f16 and the candidate needs 8 bytes of LDS.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_rtz(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+}
+
+// a.lo b.lo + a.hi b.hi + c for fp16 pairs a, b, in the VOP3P form: its
+// accumulator is an operand of its own, where the builtin's two-operand
+// form ties it to the result and costs a copy of c per call
+__device__ __forceinline__ float dot2_acc(uint32_t a, uint32_t b, float c) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// A bound on the spacing of fp16 values of magnitude <= x: 2^(e - 11) for
+// x < 2^e, and at least the subnormal spacing 2^-24.
+__device__ __forceinline__ double ulp16_bound(double x) {
+  int e;
+  frexp(x, &e);
+  return ldexp(1.0, e - 11 > -24 ? e - 11 : -24);
+}
+
+// lim of the fp16 test, in cutoff units, for cells of largest edge emax.
+// Positions lie in [-1/2, 3/2) edges of their cell's corner and O is half
+// an edge from that corner, so targets lie within tmax = emax of O, and a
+// candidate within the cutoff of one of them within cmx = tmax + 1. Per
+// coordinate T errs by at most uT (half a spacing) and C by uC (a spacing),
+// each plus 2^-14 should fp16 subnormals be flushed, so |T - C| <=
+// |t - c| + sqrt(3) (uT + uC); W errs by at most uW. A pair inside the
+// cutoff therefore gives v < 0 once lim exceeds (1 + sqrt(3) (uT + uC))^2 +
+// uW, plus 1e-5 of the largest terms for the float32 sums and conversions
+// and the rounding of the hit loop's own test on the exact separation.
+__device__ __forceinline__ float fp16_test_lim(double emax) {
+  const double flush = ldexp(1.0, -14);
+  const double tmax = emax * (1.0 + 1e-6), cmx = tmax + 1.0;
+  const double uT = 0.5 * ulp16_bound(tmax) + flush, uC = ulp16_bound(cmx) + flush;
+  const double uW = ulp16_bound(fmax(1.1, (cmx + uC) * (cmx + uC))) + flush;
+  const double d = sqrt(3.0) * (uT + uC);
+  return (float)(1.0 + 2.0 * d + d * d + uW + 1e-5 * fmax(1.0, 3.0 * cmx * cmx));
+}
+
 __device__ __forceinline__ float erfcx_poly(float t) {
   float acc = (float)p3m_erfcx_coef[P3M_ERFCX_DEG];
 #pragma unroll
@@ -175,10 +223,14 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   // reads fall in different LDS banks
   constexpr int TS = kTileK + 1;
   constexpr int NT = kWaveGroups * TS;
+  // the float form's fp16 test tile: pairs of candidates read as 16 bytes,
+  // groups 66 slots (132 dwords) apart, so their reads start 4 banks apart
+  constexpr int TSH = kTileK + 2;
   constexpr bool kFix = std::is_same<R, float>::value;
   // PACKED: float records whose weight slot holds position residuals (all weights 1)
   static_assert(kFix || !PACKED, "residual packing is a float-form layout");
-  __shared__ V4 tile[NT];                   // group-relative x, y, z (cutoff test)
+  __shared__ V4 tile[kFix ? 1 : NT];        // double: group-relative x, y, z and |c|^2 - lim (cutoff test)
+  __shared__ uint4 tileh[kFix ? kWaveGroups * TSH / 2 : 1];   // float: fp16 (Cx, Cy), (Cz, W) per candidate
   __shared__ int4 tfix[kFix ? NT : 1];      // float: fixed-point x, y, z from the group's corner; weight bits
   __shared__ V4 tloc[kFix ? 1 : NT];        // double: cell-local x, y, z and the charge weight
   __shared__ V4 toff[kFix ? 1 : NT];        // double: cell-corner offset from the group's first cell
@@ -213,6 +265,10 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
   const R cux = (R)geo.cu[0], cuy = (R)geo.cu[1], cuz = (R)geo.cu[2];
   const int kex = fix_edge(geo.cu, 0), key_ = fix_edge(geo.cu, 1), kez = fix_edge(geo.cu, 2);
+  // float form: fixed-point positions relative to O, (kex/2, key/2, kez/2)
+  // units from the group cell's corner; the offset is common to targets and
+  // candidates, so the hit loop's integer separations do not change
+  const int hx = kex >> 1, hy = key_ >> 1, hz = kez >> 1;
   const R fu = (R)fix_unit(geo.cu);
   int cx0 = 0, cy = 0, cz = 0;
   if (gvalid) {
@@ -240,7 +296,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         e = cs[row + xhi + 1];
       }
       rstart[q][r] = b;
-      if constexpr (kFix) royz[q][r] = make_int2(dy * key_, dz * kez);
+      if constexpr (kFix) royz[q][r] = make_int2(dy * key_ - hy, dz * kez - hz);
     }
     lens[u] = e - b;
   }
@@ -271,9 +327,9 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     const int j = gd.x + ql;
     const PPPos<R> me = rec[j];
     if constexpr (kFix) {
-      ix = (me.x & kFixMask) - kFixBias;
-      iy = me.y;
-      iz = me.z;
+      ix = (me.x & kFixMask) - (kFixBias + hx);
+      iy = me.y - hy;
+      iz = me.z - hz;
       tres = __float_as_int(me.w);
     } else {
       lx = me.x;
@@ -285,23 +341,25 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       for (int d = 0; d < 3; ++d) vi[d] = hv_in[3 * j + d];
   }
   // cutoff test: r^2 - lim = (|t|^2 + (|c|^2 - lim)) - 2 t.c with lim =
-  // 1 + margin; the margin covers the rounding of the expanded form for
-  // positions within DIV + 1 cell edges of the group's corner
-  // (|c|^2 <= 3 (DIV + 1)^2 cu^2)
+  // 1 + margin. double: the margin covers the rounding of the expanded form
+  // for positions within DIV + 1 cell edges of the group's corner
+  // (|c|^2 <= 3 (DIV + 1)^2 cu^2); float: the fp16 form above
   const double cmax = fmax(geo.cu[0], fmax(geo.cu[1], geo.cu[2]));
-  const R lim = (R)(1.0 + 1e-5 * fmax(1.0, (DIV + 1) * (DIV + 1) * cmax * cmax));
-  R tx, ty, tz;
+  const R lim = kFix ? (R)fp16_test_lim(cmax) : (R)(1.0 + 1e-5 * fmax(1.0, (DIV + 1) * (DIV + 1) * cmax * cmax));
+  R t2x = 0, t2y = 0, t2z = 0, tt = 0;
+  uint32_t tP = 0u, tQ = 0u;   // float: fp16 (-2 Tx, -2 Ty) and (-2 Tz, 1)
   if constexpr (kFix) {
-    tx = active ? (R)ix * fu : (R)1e18;
-    ty = (R)iy * fu;
-    tz = (R)iz * fu;
+    const _Float16 hx_ = (_Float16)((R)ix * fu), hy_ = (_Float16)((R)iy * fu), hz_ = (_Float16)((R)iz * fu);
+    tP = __builtin_bit_cast(uint32_t, half2v{(_Float16)-2 * hx_, (_Float16)-2 * hy_});
+    tQ = __builtin_bit_cast(uint32_t, half2v{(_Float16)-2 * hz_, (_Float16)1});
+    tt = (float)hx_ * (float)hx_ + (float)hy_ * (float)hy_ + (float)hz_ * (float)hz_;
   } else {
-    tx = active ? lx : (R)1e18;
-    ty = ly;
-    tz = lz;
+    const R tx = active ? lx : (R)1e18;
+    t2x = (R)-2 * tx;
+    t2y = (R)-2 * ly;
+    t2z = (R)-2 * lz;
+    tt = tx * tx + ly * ly + lz * lz;
   }
-  const R t2x = (R)-2 * tx, t2y = (R)-2 * ty, t2z = (R)-2 * tz;
-  const R tt = tx * tx + ty * ty + tz * tz;
   const int L = gtot[q];
   const int S = (L + kTileK - 1) / kTileK;
   const int nt = max(max((gtot[0] + kTileK - 1) / kTileK, (gtot[1] + kTileK - 1) / kTileK),
@@ -362,20 +420,23 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       V4 c{(R)1e18, (R)0, (R)0, (R)1e30};
       if constexpr (kFix) {
         // computed for every slot (a slot past the group's candidates holds
-        // a stale record) and then, past them, replaced by a far point that
-        // no cutoff test passes (|t|^2 + 1e30 - 2 t.c > 0)
+        // a stale record) and then, past them, replaced by C = 0, W = +inf,
+        // which no cutoff test passes
         // the candidate's cell offset along the row from the x codes (mod 8,
         // |offset| <= DIV), its row's y, z offsets from the range
         const int raw = nx_o[h].x;
         const int dxc = (int)__builtin_amdgcn_sbfe((unsigned)((int)((unsigned)raw >> kXCodeShift) - cx0c), 0, 3);
         const int2 oyz = royz[q][cr[h]];
-        const int4 fx = make_int4((raw & kFixMask) - kFixBias + dxc * kex, nx_o[h].y + oyz.x, nx_o[h].z + oyz.y,
-                                  __float_as_int(nx_o[h].w));
-        const R cx = (R)fx.x * fu, cy_ = (R)fx.y * fu, cz_ = (R)fx.z * fu;
-        c.x = nx_ok[h] ? cx : (R)1e18;
-        c.y = cy_;
-        c.z = cz_;
-        c.w = nx_ok[h] ? cx * cx + cy_ * cy_ + cz_ * cz_ - lim : (R)1e30;
+        const int4 fx = make_int4((raw & kFixMask) - (kFixBias + hx) + dxc * kex, nx_o[h].y + oyz.x,
+                                  nx_o[h].z + oyz.y, __float_as_int(nx_o[h].w));
+        // C: the float coordinates cut to fp16's 11 significant bits (toward
+        // zero, exact in the packing below), so that W is |C|^2 - lim
+        const float rx = __uint_as_float(__float_as_uint((R)fx.x * fu) & 0xffffe000u);
+        const float ry = __uint_as_float(__float_as_uint((R)fx.y * fu) & 0xffffe000u);
+        const float rz = __uint_as_float(__float_as_uint((R)fx.z * fu) & 0xffffe000u);
+        const float w = fmaf(rx, rx, fmaf(ry, ry, fmaf(rz, rz, -lim)));
+        reinterpret_cast<uint2*>(tileh)[TSH * q + 16 * h + ql] =
+            nx_ok[h] ? make_uint2(pack_rtz(rx, ry), pack_rtz(rz, w)) : make_uint2(0u, 0x7c000000u);
         tfix[TS * q + 16 * h + ql] = fx;
       } else {
         V4 cl{(R)0, (R)0, (R)0, (R)0}, co{(R)0, (R)0, (R)0, (R)0};
@@ -394,7 +455,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
       if constexpr (HVP)
         tvel[TS * q + 16 * h + ql] = nx_ok[h] ? V4{(R)nx_v[h][0], (R)nx_v[h][1], (R)nx_v[h][2], (R)0}
                                               : V4{(R)0, (R)0, (R)0, (R)0};
-      tile[TS * q + 16 * h + ql] = c;
+      if constexpr (!kFix) tile[TS * q + 16 * h + ql] = c;
     }
     wave_sync();
     fetch(t + 1);
@@ -403,19 +464,35 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     //    candidate k of a half-tile ends at bit 31 - k. The test is a little
     //    generous; the evaluation below repeats it exactly on the precise
     //    separation.
-    const V4* tq = tile + TS * q;
     uint32_t m0 = 0u, m1 = 0u;
+    if constexpr (kFix) {
+      // (Cx, Cy), (Cz, W) of candidate k at 8-byte slot k of the group's tile
+      const uint2* hq = reinterpret_cast<const uint2*>(tileh) + TSH * q;
+      const half2v P = __builtin_bit_cast(half2v, tP);
+#pragma unroll 8
+      for (int k = 0; k < 32; ++k) {
+        const uint2 c = hq[k];
+        m0 = mask_shift_in(m0, __builtin_amdgcn_fdot2(P, __builtin_bit_cast(half2v, c.x), dot2_acc(tQ, c.y, tt), false));
+      }
+#pragma unroll 8
+      for (int k = 32; k < 64; ++k) {
+        const uint2 c = hq[k];
+        m1 = mask_shift_in(m1, __builtin_amdgcn_fdot2(P, __builtin_bit_cast(half2v, c.x), dot2_acc(tQ, c.y, tt), false));
+      }
+    } else {
+      const V4* tq = tile + TS * q;
 #pragma unroll 4
-    for (int k = 0; k < 32; ++k) {
-      const V4 c = tq[k];
-      const R v = fma(t2z, c.z, fma(t2y, c.y, fma(t2x, c.x, tt + c.w)));
-      m0 = mask_shift_in(m0, v);
-    }
+      for (int k = 0; k < 32; ++k) {
+        const V4 c = tq[k];
+        const R v = fma(t2z, c.z, fma(t2y, c.y, fma(t2x, c.x, tt + c.w)));
+        m0 = mask_shift_in(m0, v);
+      }
 #pragma unroll 4
-    for (int k = 0; k < 32; ++k) {
-      const V4 c = tq[32 + k];
-      const R v = fma(t2z, c.z, fma(t2y, c.y, fma(t2x, c.x, tt + c.w)));
-      m1 = mask_shift_in(m1, v);
+      for (int k = 0; k < 32; ++k) {
+        const V4 c = tq[32 + k];
+        const R v = fma(t2z, c.z, fma(t2y, c.y, fma(t2x, c.x, tt + c.w)));
+        m1 = mask_shift_in(m1, v);
+      }
     }
     if (!active) m0 = m1 = 0u;
     // 3. own hits (the particle itself and coincident ones give r2 = 0).
