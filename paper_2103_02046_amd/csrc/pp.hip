@@ -46,6 +46,17 @@ struct Kahan3 {
 // so v = |T|^2 + W - 2 T.C = |T - C|^2 - lim + (W - (|C|^2 - lim)) costs two
 // v_dot2_f32_f16 and the candidate needs 8 bytes of LDS.
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+// clang vectors, not HIP's uint2/uint4 structs: a copy of the struct is read
+// member by member (4-byte loads), a vector in a single LDS access. The test
+// tile is written as 8-byte and read as 16-byte vectors, so both types may
+// alias anything.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4), may_alias));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2), may_alias));
+
+// the fp16 pair in a 32-bit value; taken by value, since clang's
+// __builtin_bit_cast of a vector element (c.z) reads the vector's first
+// element instead
+__device__ __forceinline__ half2v as_half2(uint32_t v) { return __builtin_bit_cast(half2v, v); }
 
 __device__ __forceinline__ uint32_t pack_rtz(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
@@ -230,7 +241,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   // PACKED: float records whose weight slot holds position residuals (all weights 1)
   static_assert(kFix || !PACKED, "residual packing is a float-form layout");
   __shared__ V4 tile[kFix ? 1 : NT];        // double: group-relative x, y, z and |c|^2 - lim (cutoff test)
-  __shared__ uint4 tileh[kFix ? kWaveGroups * TSH / 2 : 1];   // float: fp16 (Cx, Cy), (Cz, W) per candidate
+  __shared__ u32x4 tileh[kFix ? kWaveGroups * TSH / 2 : 1];   // float: fp16 (Cx, Cy), (Cz, W) per candidate
   __shared__ int4 tfix[kFix ? NT : 1];      // float: fixed-point x, y, z from the group's corner; weight bits
   __shared__ V4 tloc[kFix ? 1 : NT];        // double: cell-local x, y, z and the charge weight
   __shared__ V4 toff[kFix ? 1 : NT];        // double: cell-corner offset from the group's first cell
@@ -435,8 +446,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
         const float ry = __uint_as_float(__float_as_uint((R)fx.y * fu) & 0xffffe000u);
         const float rz = __uint_as_float(__float_as_uint((R)fx.z * fu) & 0xffffe000u);
         const float w = fmaf(rx, rx, fmaf(ry, ry, fmaf(rz, rz, -lim)));
-        reinterpret_cast<uint2*>(tileh)[TSH * q + 16 * h + ql] =
-            nx_ok[h] ? make_uint2(pack_rtz(rx, ry), pack_rtz(rz, w)) : make_uint2(0u, 0x7c000000u);
+        reinterpret_cast<u32x2*>(tileh)[TSH * q + 16 * h + ql] =
+            nx_ok[h] ? u32x2{pack_rtz(rx, ry), pack_rtz(rz, w)} : u32x2{0u, 0x7c000000u};
         tfix[TS * q + 16 * h + ql] = fx;
       } else {
         V4 cl{(R)0, (R)0, (R)0, (R)0}, co{(R)0, (R)0, (R)0, (R)0};
@@ -466,18 +477,21 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
     //    separation.
     uint32_t m0 = 0u, m1 = 0u;
     if constexpr (kFix) {
-      // (Cx, Cy), (Cz, W) of candidate k at 8-byte slot k of the group's tile
-      const uint2* hq = reinterpret_cast<const uint2*>(tileh) + TSH * q;
-      const half2v P = __builtin_bit_cast(half2v, tP);
-#pragma unroll 8
-      for (int k = 0; k < 32; ++k) {
-        const uint2 c = hq[k];
-        m0 = mask_shift_in(m0, __builtin_amdgcn_fdot2(P, __builtin_bit_cast(half2v, c.x), dot2_acc(tQ, c.y, tt), false));
+      // one 16-byte read per two candidates: (Cx, Cy), (Cz, W) of candidates
+      // 2k and 2k + 1
+      const u32x4* hq = tileh + (TSH / 2) * q;
+      const half2v P = as_half2(tP);
+#pragma unroll 4
+      for (int k = 0; k < 16; ++k) {
+        const u32x4 c = hq[k];
+        m0 = mask_shift_in(m0, __builtin_amdgcn_fdot2(P, as_half2(c.x), dot2_acc(tQ, c.y, tt), false));
+        m0 = mask_shift_in(m0, __builtin_amdgcn_fdot2(P, as_half2(c.z), dot2_acc(tQ, c.w, tt), false));
       }
-#pragma unroll 8
-      for (int k = 32; k < 64; ++k) {
-        const uint2 c = hq[k];
-        m1 = mask_shift_in(m1, __builtin_amdgcn_fdot2(P, __builtin_bit_cast(half2v, c.x), dot2_acc(tQ, c.y, tt), false));
+#pragma unroll 4
+      for (int k = 16; k < 32; ++k) {
+        const u32x4 c = hq[k];
+        m1 = mask_shift_in(m1, __builtin_amdgcn_fdot2(P, as_half2(c.x), dot2_acc(tQ, c.y, tt), false));
+        m1 = mask_shift_in(m1, __builtin_amdgcn_fdot2(P, as_half2(c.z), dot2_acc(tQ, c.w, tt), false));
       }
     } else {
       const V4* tq = tile + TS * q;
