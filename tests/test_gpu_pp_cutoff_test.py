@@ -96,3 +96,21 @@ def test_pairs_just_inside_the_cutoff(h, div):
     print(f"h {h} D={div}: {m} pairs just inside; ordered pairs k-d tree {bounds(x, rcp, 1e-6)}, "
           f"float-compensated {got['fp32c']:.0f}, float64 {got['fp64']:.0f}", flush=True)
     check(got, x, rcp)
+
+
+@pytest.mark.parametrize("div", [1, 2])
+@pytest.mark.parametrize("grid", [(4, 4, 4), (8, 16, 32), (64, 8, 16)])
+def test_pair_count_on_ragged_grids(grid, div):
+    """Few cells per axis, cells up to about 1.7 cutoffs wide (the margin's
+    largest coordinates) and anisotropic cell counts."""
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((3000, 3)) * np.array([1.0, 0.7, 1.3])
+    h, rc = (0.4, 0.3, 0.5), 0.7
+    prm = O.Params(grid, h, rc, 3.0 / rc, 2, 1.0)
+    rcp = O.placement(x, prm)["rc"]
+    p = np.zeros_like(x)
+    got = counts(lambda prec: p3m.Context(grid, h, rc, 3.0 / rc, order=2, ke=1.0, q=1.0, precision=prec,
+                                          pp_cell_div=div), x, p)
+    print(f"grid {grid} D={div}: ordered pairs k-d tree {bounds(x, rcp, 1e-6)}, float-compensated "
+          f"{got['fp32c']:.0f}, float64 {got['fp64']:.0f}", flush=True)
+    check(got, x, rcp)
