@@ -612,8 +612,8 @@ p3m_status p3m_create(p3m_ctx** out, const int32_t grid[3], const double h[3], d
       dalloc(&ctx->bbox_part, 6 * 1024) != hipSuccess || dalloc(&ctx->acc, 64) != hipSuccess ||
       dalloc(&ctx->sb.counter, 2) != hipSuccess || dalloc(&ctx->sb.cell_start, (size_t)g.ncells + 1) != hipSuccess ||
       dalloc(&ctx->sb.ccount, (size_t)g.ncells) != hipSuccess || dalloc(&ctx->sb.cfill, (size_t)g.ncells) != hipSuccess ||
-      dalloc(&ctx->sb.btot, (size_t)2 * cell_blocks(g.ncells)) != hipSuccess ||
-      dalloc(&ctx->sb.stot, (size_t)2 * cell_supers(g.ncells)) != hipSuccess)
+      dalloc(&ctx->sb.btot, (size_t)kCellTotals * cell_blocks(g.ncells)) != hipSuccess ||
+      dalloc(&ctx->sb.stot, (size_t)kCellTotals * cell_supers(g.ncells)) != hipSuccess)
     return bail(P3M_ENOMEM);
   // the per-cell counts start at zero; each sort leaves them at zero
   if (hipMemset(ctx->sb.ccount, 0, (size_t)g.ncells * sizeof(int)) != hipSuccess) return bail(P3M_EHIP);
@@ -995,9 +995,10 @@ p3m_status p3m_profile_pp_waves(p3m_ctx* ctx, int64_t cap, double* out, int64_t*
   if (!ctx || cap < 0 || (cap > 0 && !out) || !count) return P3M_EINVAL;
   if (!ctx->wclock_valid) return fail(ctx, P3M_ESTATE, "no pair-kernel waves recorded");
   hipStream_t st = (hipStream_t)stream;
-  int groups = 0;
-  HIPCHK(hipMemcpyAsync(&groups, ctx->sb.counter, sizeof(int), hipMemcpyDeviceToHost, st));
+  int cnt[2] = {0, 0};   // dense-cell and other PP groups
+  HIPCHK(hipMemcpyAsync(cnt, ctx->sb.counter, sizeof(cnt), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  const int64_t groups = (int64_t)cnt[0] + cnt[1];
   const int64_t waves = (groups + 3) / 4;
   *count = waves;
   const int64_t m = waves < cap ? waves : cap;

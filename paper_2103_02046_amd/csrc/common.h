@@ -12,8 +12,13 @@ constexpr int kBitNonFinite = 2;  // a non-finite position
 
 constexpr int kThreads = 256;     // block size of the particle kernels
 // PP work groups: runs of at most kGroupRun consecutive sorted particles of
-// one cell, listed in cell order (built by the cell sort, read by the PP kernel).
+// one cell (built by the cell sort, read by the PP kernel). Groups of cells
+// of at least kDenseCell particles come first, in cell order, from the front
+// of the group array; the others follow, in cell order, stored from its back
+// (index cap - 1 - i): the long waves of dense regions start first and the
+// short ones fill the end of the launch, while neighbours stay adjacent.
 constexpr int kGroupRun = 16;
+constexpr int kDenseCell = 2 * kGroupRun;
 constexpr int kXcds = 8;          // MI355X: work-groups are dealt round-robin to 8 XCDs
 
 // Placement of one evaluation, written on the device by the finalize kernel.

@@ -19,16 +19,17 @@ struct SortBufs {
   uint32_t *keys_in, *keys, *perm;   // [n]: keys in input order; sorted keys and input index
   int* ccount;      // [ncells] particles per cell, zero between sorts
   int* cfill;       // [ncells] the scatter's fill pointers
-  int* btot;        // [2 cell_blocks] particles and groups per block of cells
-  int* stot;        // [2 cell_supers] their sums per super-block
+  int* btot;        // [kCellTotals cell_blocks] particles, dense-cell and other groups per block of cells
+  int* stot;        // [kCellTotals cell_supers] their sums per super-block
   int* cell_start;  // [ncells + 1]
-  int* counter;     // [0] PP groups built
+  int* counter;     // [0] PP groups of dense cells, [1] other PP groups
 };
+constexpr int kCellTotals = 3;
 int cell_blocks(long long ncells);
 int cell_supers(long long ncells);
 // Counting sort of the particles by PP cell: keys, cell starts and the PP
-// work groups (desc, counter[0]); on return *keys/*perm point at the sorted
-// key and input index arrays.
+// work groups (desc of pp_group_bound(n, geo) entries, counter[0..1]); on
+// return *keys/*perm point at the sorted key and input index arrays.
 void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& geo, SortBufs& b, int2* desc,
                       uint32_t** keys, uint32_t** perm, hipStream_t st);
 // Stepping in cell order: the reorder can also move the particle state into

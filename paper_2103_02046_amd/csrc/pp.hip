@@ -154,8 +154,9 @@ struct Acc3<double> {
 // sort. Cells have edges >= r_c / D (D = Geo::pp_div, 1 or 2), so the
 // candidates of every particle of a group lie in (2D+1)^2 contiguous
 // ranges: cells cx-D .. cx+D of the (2D+1) x (2D+1) neighbouring rows (a
-// row of cells is contiguous in the sorted order); consecutive groups are
-// spatial neighbours. Halving the cells (D = 2) cuts the candidate volume
+// row of cells is contiguous in the sorted order); consecutive groups of
+// one class (cells of at least kDenseCell particles first, then the others)
+// are spatial neighbours. Halving the cells (D = 2) cuts the candidate volume
 // from 27 to 125/8 cutoff cubes, for dense bunches whose half-size cells
 // still fill the groups.
 
@@ -222,7 +223,7 @@ __device__ __forceinline__ void wave_sync() {
 // records (residuals included), the Jacobian in float with the same erfc fit
 // as the force, Kahan-compensated per-particle sums.
 template <typename R, bool ENERGY, bool PACKED, bool HVP, int DIV>
-__global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter,
+__global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const int* __restrict__ counter, int gcap,
                                            const PPPos<R>* __restrict__ rec, const uint32_t* __restrict__ keys,
                                            const int* __restrict__ cs, Geo geo, PPRec<R>* __restrict__ out,
                                            double* __restrict__ energy, const double* __restrict__ hv_in = nullptr,
@@ -259,7 +260,8 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   // go to one XCD, so its L2 serves their shared candidates once; the runs
   // are dealt to the XCDs in turn, which keeps dense and sparse regions
   // spread over all of them.
-  const int ngroups = counter[0];
+  // dense-cell groups at desc[0 ..), the others at desc[gcap - 1 - i]
+  const int ndense = counter[0], ngroups = ndense + counter[1];
   const int nwaves = (ngroups + kWaveGroups - 1) / kWaveGroups;
   const int xcd = (int)(blockIdx.x % kXcds), k = (int)(blockIdx.x / kXcds);
   const int wave = ((k / kXcdRun) * kXcds + xcd) * kXcdRun + k % kXcdRun;
@@ -272,7 +274,7 @@ __global__ void __launch_bounds__(64) k_pp(const int2* __restrict__ desc, const 
   const int gid = gbase + q;
   const bool gvalid = gid < ngroups;
   int2 gd = make_int2(0, 0);
-  if (gvalid) gd = desc[gid];
+  if (gvalid) gd = desc[gid < ndense ? gid : gcap - 1 - (gid - ndense)];
   const int nx = geo.ncell[0], ny = geo.ncell[1], nz = geo.ncell[2];
   const R cux = (R)geo.cu[0], cuy = (R)geo.cu[1], cuz = (R)geo.cu[2];
   const int kex = fix_edge(geo.cu, 0), key_ = fix_edge(geo.cu, 1), kez = fix_edge(geo.cu, 2);
@@ -658,20 +660,20 @@ template <typename R>
 constexpr bool kPackable = std::is_same<R, float>::value;
 
 template <typename R, int DIV>
-void launch_pp_div(unsigned blocks, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
+void launch_pp_div(unsigned blocks, int gcap, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                    const Geo& geo, const int2* desc, int* counter, PPRec<R>* out, double* energy,
                    hipStream_t st, unsigned long long* wclock) {
   const bool packed = std::is_same<R, float>::value && geo.wpacked;
   if (energy && packed)
-    k_pp<R, true, kPackable<R>, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out,
+    k_pp<R, true, kPackable<R>, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, gcap, rec, keys, cell_start, geo, out,
                                                                    energy);
   else if (energy)
-    k_pp<R, true, false, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out, energy);
+    k_pp<R, true, false, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, gcap, rec, keys, cell_start, geo, out, energy);
   else if (packed)
-    k_pp<R, false, kPackable<R>, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out,
+    k_pp<R, false, kPackable<R>, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, gcap, rec, keys, cell_start, geo, out,
                                                                     nullptr, nullptr, nullptr, wclock);
   else
-    k_pp<R, false, false, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, out,
+    k_pp<R, false, false, false, DIV><<<blocks, 64, 0, st>>>(desc, counter, gcap, rec, keys, cell_start, geo, out,
                                                              nullptr, nullptr, nullptr, wclock);
 }
 
@@ -681,22 +683,23 @@ void launch_pp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const int* 
                hipStream_t st, unsigned long long* wclock) {
   // one wave per quad of groups; waves beyond the groups built leave at once
   const unsigned blocks = pp_blocks(n, geo);
+  const int gcap = pp_group_bound(n, geo);
   if (geo.pp_div == 2)
-    launch_pp_div<R, 2>(blocks, rec, keys, cell_start, geo, desc, counter, out, energy, st, wclock);
+    launch_pp_div<R, 2>(blocks, gcap, rec, keys, cell_start, geo, desc, counter, out, energy, st, wclock);
   else
-    launch_pp_div<R, 1>(blocks, rec, keys, cell_start, geo, desc, counter, out, energy, st, wclock);
+    launch_pp_div<R, 1>(blocks, gcap, rec, keys, cell_start, geo, desc, counter, out, energy, st, wclock);
 }
 
 template <typename R, int DIV>
-void launch_pp_hvp_div(unsigned blocks, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
+void launch_pp_hvp_div(unsigned blocks, int gcap, const PPPos<R>* rec, const uint32_t* keys, const int* cell_start,
                        const Geo& geo, const int2* desc, int* counter, const double* v_sorted,
                        double* out_sorted, hipStream_t st) {
   const bool packed = std::is_same<R, float>::value && geo.wpacked;
   if (packed)
-    k_pp<R, false, kPackable<R>, true, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo,
+    k_pp<R, false, kPackable<R>, true, DIV><<<blocks, 64, 0, st>>>(desc, counter, gcap, rec, keys, cell_start, geo,
                                                                    nullptr, nullptr, v_sorted, out_sorted);
   else
-    k_pp<R, false, false, true, DIV><<<blocks, 64, 0, st>>>(desc, counter, rec, keys, cell_start, geo, nullptr,
+    k_pp<R, false, false, true, DIV><<<blocks, 64, 0, st>>>(desc, counter, gcap, rec, keys, cell_start, geo, nullptr,
                                                             nullptr, v_sorted, out_sorted);
 }
 
@@ -706,10 +709,11 @@ void launch_pp_hvp(int64_t n, const PPPos<R>* rec, const uint32_t* keys, const i
                    hipStream_t st) {
   // the tiled pair kernel in its Hessian-vector mode, over the cell sort's groups
   const unsigned blocks = pp_blocks(n, geo);
+  const int gcap = pp_group_bound(n, geo);
   if (geo.pp_div == 2)
-    launch_pp_hvp_div<R, 2>(blocks, rec, keys, cell_start, geo, desc, counter, v_sorted, out_sorted, st);
+    launch_pp_hvp_div<R, 2>(blocks, gcap, rec, keys, cell_start, geo, desc, counter, v_sorted, out_sorted, st);
   else
-    launch_pp_hvp_div<R, 1>(blocks, rec, keys, cell_start, geo, desc, counter, v_sorted, out_sorted, st);
+    launch_pp_hvp_div<R, 1>(blocks, gcap, rec, keys, cell_start, geo, desc, counter, v_sorted, out_sorted, st);
 }
 template void launch_pp_hvp<float>(int64_t, const PPPos<float>*, const uint32_t*, const int*, const Geo&,
                                    const int2*, int*, const double*, double*, hipStream_t);

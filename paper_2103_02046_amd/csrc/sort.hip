@@ -83,99 +83,106 @@ constexpr int kCellTile = kThreads * kCellItems;     // 512 cells per block
 constexpr int kSuper = 64;                           // blocks per super-block of the start prefix
 constexpr int kDirectPrefix = 2048;                  // above this many blocks, super-block totals
 
-// Particles and PP groups (runs of <= 16 of one cell) per block of cells,
-// and on large grids their sums per super-block of kSuper blocks (stot,
-// cleared by the key kernel).
+// Particles, dense-cell groups and other groups (runs of <= 16 of one
+// cell) per block of cells, and on large grids their sums per super-block of
+// kSuper blocks (stot, cleared by the key kernel); kTotals values each.
+constexpr int kTotals = kCellTotals;
+
+__device__ __forceinline__ void cell_groups(int v, int& dense, int& sparse) {
+  const int g = (v + kGroupRun - 1) / kGroupRun;
+  if (v >= kDenseCell) dense += g;
+  else sparse += g;
+}
+
 __global__ void __launch_bounds__(kThreads) k_cell_totals(const int* __restrict__ ccount, long long ncells,
                                                           int* __restrict__ btot, int* __restrict__ stot,
                                                           bool super_prefix) {
   const long long c0 = blockIdx.x * (long long)kCellTile + (long long)threadIdx.x * kCellItems;
-  int s = 0, gs = 0;
+  int s = 0, gd = 0, gsp = 0;
 #pragma unroll
   for (int k = 0; k < kCellItems; ++k) {
     if (c0 + k < ncells) {
       const int v = ccount[c0 + k];
       s += v;
-      gs += (v + kGroupRun - 1) / kGroupRun;
+      cell_groups(v, gd, gsp);
     }
   }
-  int tot_s, tot_g;
-  (void)block_exclusive_scan(s, &tot_s);
-  (void)block_exclusive_scan(gs, &tot_g);
+  int tot[kTotals];
+  (void)block_exclusive_scan(s, &tot[0]);
+  (void)block_exclusive_scan(gd, &tot[1]);
+  (void)block_exclusive_scan(gsp, &tot[2]);
   if (threadIdx.x == 0) {
-    btot[2 * blockIdx.x] = tot_s;
-    btot[2 * blockIdx.x + 1] = tot_g;
-    if (super_prefix) {
-      atomicAdd(&stot[2 * (blockIdx.x / kSuper)], tot_s);
-      atomicAdd(&stot[2 * (blockIdx.x / kSuper) + 1], tot_g);
+    for (int c = 0; c < kTotals; ++c) {
+      btot[kTotals * blockIdx.x + c] = tot[c];
+      if (super_prefix) atomicAdd(&stot[kTotals * (blockIdx.x / kSuper) + c], tot[c]);
     }
   }
 }
 
 // Cell starts (exclusive prefix of the counts), the scatter's fill pointers,
-// and the PP work groups in cell order. A block's offset is the sum of the
-// block totals before it. Up to kDirectPrefix blocks each block adds them
-// all; above, it adds the super-block totals before its super-block and the
-// block totals before it inside its super-block (at most kSuper - 1), so the
-// work stays linear in the number of blocks. ccount is cleared for the next
-// sort; the last block stores cell_start[ncells] and the number of groups
-// (counter[0]).
+// and the PP work groups: dense-cell groups in cell order from the front of
+// desc, the others in cell order from its back (desc[cap - 1 - i]). A
+// block's offsets are the sums of the block totals before it. Up to
+// kDirectPrefix blocks each block adds them all; above, it adds the
+// super-block totals before its super-block and the block totals before it
+// inside its super-block (at most kSuper - 1), so the work stays linear in
+// the number of blocks. ccount is cleared for the next sort; the last block
+// stores cell_start[ncells] and the numbers of dense and other groups
+// (counter[0], counter[1]).
 __global__ void __launch_bounds__(kThreads) k_cell_starts(int* __restrict__ ccount, long long ncells,
                                                           const int* __restrict__ btot,
                                                           const int* __restrict__ stot, bool super_prefix,
                                                           int* __restrict__ cell_start, int* __restrict__ cfill,
-                                                          int2* __restrict__ desc, int* __restrict__ counter) {
-  __shared__ int red[2][kWaves];
+                                                          int2* __restrict__ desc, int cap,
+                                                          int* __restrict__ counter) {
+  __shared__ int red[kTotals][kWaves];
   const int t = threadIdx.x;
   const int sb = super_prefix ? (int)blockIdx.x / kSuper : 0, first = sb * kSuper;
-  int ps = 0, pg = 0;
-  for (int q = t; q < sb; q += kThreads) {
-    ps += stot[2 * q];
-    pg += stot[2 * q + 1];
-  }
-  for (int q = first + t; q < (int)blockIdx.x; q += kThreads) {
-    ps += btot[2 * q];
-    pg += btot[2 * q + 1];
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    ps += __shfl_xor(ps, off);
-    pg += __shfl_xor(pg, off);
-  }
-  if ((t & 63) == 0) {
-    red[0][t >> 6] = ps;
-    red[1][t >> 6] = pg;
+  int pre[kTotals] = {0, 0, 0};
+  for (int q = t; q < sb; q += kThreads)
+    for (int c = 0; c < kTotals; ++c) pre[c] += stot[kTotals * q + c];
+  for (int q = first + t; q < (int)blockIdx.x; q += kThreads)
+    for (int c = 0; c < kTotals; ++c) pre[c] += btot[kTotals * q + c];
+  for (int c = 0; c < kTotals; ++c) {
+    for (int off = 32; off > 0; off >>= 1) pre[c] += __shfl_xor(pre[c], off);
+    if ((t & 63) == 0) red[c][t >> 6] = pre[c];
   }
   __syncthreads();
-  int P = 0, G = 0;
+  int P = 0, GD = 0, GS = 0;
   for (int w = 0; w < kWaves; ++w) {
     P += red[0][w];
-    G += red[1][w];
+    GD += red[1][w];
+    GS += red[2][w];
   }
   const long long c0 = blockIdx.x * (long long)kCellTile + (long long)t * kCellItems;
   int v[kCellItems];
-  int s = 0, gs = 0;
+  int s = 0, gd = 0, gsp = 0;
 #pragma unroll
   for (int k = 0; k < kCellItems; ++k) {
     v[k] = c0 + k < ncells ? ccount[c0 + k] : 0;
     s += v[k];
-    gs += (v[k] + kGroupRun - 1) / kGroupRun;
+    cell_groups(v[k], gd, gsp);
   }
   int tot;
   int start = P + block_exclusive_scan(s, &tot);
-  int g = G + block_exclusive_scan(gs, &tot);
+  int g = GD + block_exclusive_scan(gd, &tot);
+  int h = GS + block_exclusive_scan(gsp, &tot);
 #pragma unroll
   for (int k = 0; k < kCellItems; ++k) {
     if (c0 + k < ncells) {
       cell_start[c0 + k] = start;
       cfill[c0 + k] = start;
       ccount[c0 + k] = 0;
-      for (int j = 0; j < v[k]; j += kGroupRun) desc[g++] = make_int2(start + j, min(kGroupRun, v[k] - j));
+      const bool dense = v[k] >= kDenseCell;
+      for (int j = 0; j < v[k]; j += kGroupRun)
+        desc[dense ? g++ : cap - 1 - h++] = make_int2(start + j, min(kGroupRun, v[k] - j));
       start += v[k];
     }
   }
   if (blockIdx.x == gridDim.x - 1 && t == kThreads - 1) {
     cell_start[ncells] = start;
     counter[0] = g;
+    counter[1] = h;
   }
 }
 
@@ -343,10 +350,10 @@ void launch_cell_sort(int64_t n, const double* x, const Place* pl, const Geo& ge
   const int nbc = cell_blocks(geo.ncells);
   const bool sup = nbc > kDirectPrefix;
   k_cell_keys<<<blocks_for(n), kThreads, 0, st>>>(n, x, pl, geo, b.keys_in, b.ccount, b.stot,
-                                                  sup ? 2 * cell_supers(geo.ncells) : 0);
+                                                  sup ? kTotals * cell_supers(geo.ncells) : 0);
   k_cell_totals<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot, b.stot, sup);
   k_cell_starts<<<nbc, kThreads, 0, st>>>(b.ccount, geo.ncells, b.btot, b.stot, sup, b.cell_start, b.cfill,
-                                          desc, b.counter);
+                                          desc, pp_group_bound(n, geo), b.counter);
   k_cell_scatter<<<blocks_for(n), kThreads, 0, st>>>(n, b.keys_in, b.cfill, b.keys, b.perm);
   *keys = b.keys;
   *perm = b.perm;
