@@ -17,23 +17,40 @@ namespace {
 
 constexpr int kWaves = kThreads / 64;
 
-// Exclusive scan of 256 values held one per thread; returns the thread's
-// exclusive prefix and writes the block total to *total.
-__device__ inline int block_exclusive_scan(int v, int* total) {
-  __shared__ int s[kThreads];
-  const int t = threadIdx.x;
-  s[t] = v;
+// Exclusive scans of C values per thread over the block's 256 threads: a
+// shuffle scan inside each wave, then the wave totals through LDS (two
+// barriers for all C). excl[c] is the thread's exclusive prefix, total[c]
+// the block total.
+template <int C>
+__device__ inline void block_exclusive_scan(const int (&v)[C], int (&excl)[C], int (&total)[C]) {
+  __shared__ int wsum[C][kWaves];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int incl[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) incl[c] = v[c];
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1)
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int u = __shfl_up(incl[c], off);
+      if (lane >= off) incl[c] += u;
+    }
+  if (lane == 63)
+#pragma unroll
+    for (int c = 0; c < C; ++c) wsum[c][w] = incl[c];
   __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
-    int add = t >= off ? s[t - off] : 0;
-    __syncthreads();
-    s[t] += add;
-    __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    int before = 0, all = 0;
+    for (int k = 0; k < kWaves; ++k) {
+      const int x = wsum[c][k];
+      before += k < w ? x : 0;
+      all += x;
+    }
+    excl[c] = before + incl[c] - v[c];
+    total[c] = all;
   }
-  int incl = s[t];
-  *total = s[kThreads - 1];
-  __syncthreads();
-  return incl - v;
+  __syncthreads();   // wsum is free for the next call
 }
 
 // ---- counting sort by cell ------------------------------------------------
@@ -107,10 +124,9 @@ __global__ void __launch_bounds__(kThreads) k_cell_totals(const int* __restrict_
       cell_groups(v, gd, gsp);
     }
   }
-  int tot[kTotals];
-  (void)block_exclusive_scan(s, &tot[0]);
-  (void)block_exclusive_scan(gd, &tot[1]);
-  (void)block_exclusive_scan(gsp, &tot[2]);
+  const int val[kTotals] = {s, gd, gsp};
+  int excl[kTotals], tot[kTotals];
+  block_exclusive_scan<kTotals>(val, excl, tot);
   if (threadIdx.x == 0) {
     for (int c = 0; c < kTotals; ++c) {
       btot[kTotals * blockIdx.x + c] = tot[c];
@@ -163,10 +179,12 @@ __global__ void __launch_bounds__(kThreads) k_cell_starts(int* __restrict__ ccou
     s += v[k];
     cell_groups(v[k], gd, gsp);
   }
-  int tot;
-  int start = P + block_exclusive_scan(s, &tot);
-  int g = GD + block_exclusive_scan(gd, &tot);
-  int h = GS + block_exclusive_scan(gsp, &tot);
+  const int val[kTotals] = {s, gd, gsp};
+  int excl[kTotals], tot[kTotals];
+  block_exclusive_scan<kTotals>(val, excl, tot);
+  int start = P + excl[0];
+  int g = GD + excl[1];
+  int h = GS + excl[2];
 #pragma unroll
   for (int k = 0; k < kCellItems; ++k) {
     if (c0 + k < ncells) {
