@@ -152,3 +152,33 @@ def test_half_cells_hvp_parity(precision, tol):
     e = rms_err(out, ref)
     print(f"half cells HVP precision {precision}: {e:.2e}", flush=True)
     assert e < tol
+
+
+@pytest.mark.parametrize("div", [1, 2])
+def test_dense_and_sparse_cells_mixed(div):
+    """A 2^16-particle core/halo bunch on a 64^3 mesh: cells from one to a
+    hundred and more particles, so the cell sort lists groups of both
+    classes (cells of at least 32 particles first, from the front of the
+    group array; the others from its back) and some waves take groups of
+    both. PP against the oracle, particle by particle, in both precisions;
+    the ordered pair count against a k-d tree's."""
+    wl = W.halo_tsc(n=1 << 16, grid=64, steps=5)
+    x, p = wl.draw()
+    prm = O.Params.from_workload(wl)
+    _, parts = O.forces(x, prm, parts=True)
+    for precision, tol, worst_tol in ((p3m.FP64, TOL64, 1e-9), (p3m.FP32C, TOL32, 1e-4)):
+        c = p3m.Context.from_workload(wl, precision=precision, pp_cell_div=div)
+        fpp, _, _ = c.forces_parts(dev(x))
+        fpp = host(fpp)
+        e = rms_err(fpp, parts["pp"])
+        worst, own, k = per_particle(fpp, parts["pp"])
+        print(f"core/halo 2^16 D={div} precision {precision}: pp {e:.2e} (worst particle {worst:.2e} of rms, "
+              f"{own:.2e} of its own)", flush=True)
+        assert e < tol and worst < worst_tol
+        assert c.status_sync() == p3m.OK
+    n64 = p3m.Context.from_workload(wl, pp_cell_div=div).diagnostics(dev(x), dev(p))["pairs"]
+    rc = O.placement(x, prm)["rc"]
+    t = cKDTree(x)
+    ref = int(t.count_neighbors(t, rc)) - len(x)
+    print(f"core/halo 2^16 D={div}: ordered pairs {n64:.0f}, k-d tree {ref}", flush=True)
+    assert n64 == ref
