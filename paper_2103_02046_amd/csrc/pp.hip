@@ -195,12 +195,14 @@ constexpr int kXcdRun = 32;              // consecutive waves of groups given to
 // PP 96.4, 91.9 and 89.1 ms on the 2^25-particle core/halo bunch). Per tile:
 //   1. each group stages its 64 candidates in LDS (loaded one tile ahead);
 //   2. each lane tests its group's 64 candidates against its target, with
-//      positions relative to the group's first cell corner (a few cell
-//      edges at most): a 64-bit hit mask;
+//      positions relative to the group's cell (a few cell edges at most;
+//      float form: fp16 coordinates and two v_dot2_f32_f16 per candidate
+//      under a bounded margin, double form: the expanded square in double):
+//      a 64-bit hit mask;
 //   3. each lane evaluates its own hits from the exact separation: in the
-//      float form the difference of fixed-point positions relative to the
-//      group's cell corner (cell offsets are whole multiples of the cell
-//      edge in units, fix_edge), an integer rounded once to float; a
+//      float form the difference of fixed-point positions relative to a
+//      point of the group's cell (cell offsets are whole multiples of the
+//      cell edge in units, fix_edge), an integer rounded once to float; a
 //      candidate's offset along the row comes from the x code in its
 //      record, the row's offsets from its range; in the double form
 //      cell-local positions plus cell-corner offsets (exact multiples of the
