@@ -55,7 +55,8 @@ struct Stencil {
 // each, consecutive lanes on consecutive nodes. A box larger than the tile
 // is covered in pieces (z-slabs, or y-bands of one plane), each a pass over
 // the block's particles; past kMaxPieces (very sparse bunches) each particle
-// adds its weights to the mesh directly. The fixed-point unit is 2^-s of the
+// adds its weights to the mesh directly, one particle's nodes on as many
+// lanes. The fixed-point unit is 2^-s of the
 // block's largest |charge weight| with s chosen so that 2048 contributions
 // cannot overflow: a node value keeps 50 bits below that weight.
 constexpr int kDepItems = 4;
@@ -220,6 +221,34 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
           }
         }
         __syncthreads();
+      }
+    }
+  } else if constexpr (!GRAD) {
+    // Direct atomics with one particle's NS^3 nodes on NS^3 lanes of the
+    // wave (two TSC or eight CIC particles per instruction): an instruction
+    // then touches about ten cache lines (rows of NS consecutive nodes)
+    // instead of one line per lane, and the direct blocks of a sparse halo
+    // run about three times faster than with one particle per lane.
+    constexpr int NN = NS * NS * NS, PPI = 64 / NN;
+    const int lane = t & 63, sub = lane / NN, node = lane - sub * NN;
+    const int a = node % NS, bb = (node / NS) % NS, c = node / (NS * NS);
+#pragma unroll 1
+    for (int it = 0; it < kDepItems; ++it) {
+      const int64_t jw = j0 + it * kDepThreads + (t & ~63);   // the wave's 64 particles
+#pragma unroll 1
+      for (int p0 = 0; p0 < 64; p0 += PPI) {
+        const int64_t j = jw + p0 + sub;
+        if (sub >= PPI || j >= n) continue;
+        const MeshRec<R> m = mesh[j];
+        const R q = rec_weight(pp, j, geo);
+        int b[3];
+        unpack_base(m, nx, nxy, b);
+        const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
+        // this lane's weights, selected by value (no dynamic register index)
+        const R wa = a == 0 ? S.w[0][0] : (a == 1 ? S.w[0][1] : S.w[0][NS - 1]);
+        const R wb = bb == 0 ? S.w[1][0] : (bb == 1 ? S.w[1][1] : S.w[1][NS - 1]);
+        const R wc = c == 0 ? S.w[2][0] : (c == 1 ? S.w[2][1] : S.w[2][NS - 1]);
+        atomicAdd(Q + ((long long)(b[2] + c) * ny + (b[1] + bb)) * nx + b[0] + a, (M)(q * wb * wc * wa));
       }
     }
   } else {

@@ -67,6 +67,8 @@ def block_paths(x, prm, pl, order):
 CASES = {
     # sparse: 30000 particles filling a 128^3 mesh, a block spans over 16 tiles
     "direct": dict(grid=128, n=30000, order=2, want="direct"),
+    # the same with CIC: eight particles' 2 x 2 x 2 nodes per atomic instruction
+    "direct-cic": dict(grid=128, n=30000, order=1, want="direct"),
     # dense on 64^3: a block spans a few planes of the whole x-y extent
     "z-slabs": dict(grid=64, n=200000, order=2, want="z-slabs"),
     # medium on 128^3: a block spans many y rows of a few planes
