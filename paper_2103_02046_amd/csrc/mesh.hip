@@ -228,19 +228,32 @@ __global__ void __launch_bounds__(kDepThreads) k_deposit(int64_t n, const PPPos<
     // wave (two TSC or eight CIC particles per instruction): an instruction
     // then touches about ten cache lines (rows of NS consecutive nodes)
     // instead of one line per lane, and the direct blocks of a sparse halo
-    // run about three times faster than with one particle per lane.
+    // run about three times faster than with one particle per lane. Each
+    // lane loads one record of the wave's 64 particles (coalesced); the
+    // loop takes them from their lanes by shuffles, so it waits on no load.
     constexpr int NN = NS * NS * NS, PPI = 64 / NN;
     const int lane = t & 63, sub = lane / NN, node = lane - sub * NN;
     const int a = node % NS, bb = (node / NS) % NS, c = node / (NS * NS);
 #pragma unroll 1
     for (int it = 0; it < kDepItems; ++it) {
       const int64_t jw = j0 + it * kDepThreads + (t & ~63);   // the wave's 64 particles
+      const int64_t jl = jw + lane;
+      MeshRec<R> mine{};
+      R qmine = (R)0;
+      if (jl < n) {
+        mine = mesh[jl];
+        qmine = rec_weight(pp, jl, geo);
+      }
 #pragma unroll 1
       for (int p0 = 0; p0 < 64; p0 += PPI) {
-        const int64_t j = jw + p0 + sub;
-        if (sub >= PPI || j >= n) continue;
-        const MeshRec<R> m = mesh[j];
-        const R q = rec_weight(pp, j, geo);
+        const int src = min(p0 + sub, 63);   // every lane takes part in the shuffles
+        MeshRec<R> m;
+        m.fx = __shfl(mine.fx, src);
+        m.fy = __shfl(mine.fy, src);
+        m.fz = __shfl(mine.fz, src);
+        m.base = __shfl(mine.base, src);
+        const R q = __shfl(qmine, src);
+        if (sub >= PPI || jw + p0 + sub >= n) continue;
         int b[3];
         unpack_base(m, nx, nxy, b);
         const Stencil<R, ORDER> S(m.fx, m.fy, m.fz);
